@@ -1,0 +1,194 @@
+"""Benchmark: full NGF + curvature registration of a 256^3 CT-like pair on one
+MI355X, through the HIP library's C ABI.
+
+One step = one full registration from device-resident R and T: the pyramid
+(4 levels, 32^3 ... 256^3), then multi-level L-BFGS (memory 5, up to 50
+iterations per level, early stop at a relative decrease of 1e-6), with every
+J + grad J evaluation (P, warp, NGF, adjoint, P^T gather, curvature, fused
+reductions) in the library's kernels.
+
+Printed (one JSON line):
+* value       J + grad J evaluations per second over the timed steps (all
+              levels, line-search trials included), i.e. whole-job throughput;
+* ms_per_step the full-registration time;
+* finest      a dedicated loop of evaluations at the 256^3 level alone;
+* roofline    the dominant kernel (the fused image-grid pass), timed with HIP
+              events on the library's stream over the timed region;
+* cpu_baseline the FP64 oracle on the host, one 256^3 evaluation.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "J+∇J evals/s and full-registration seconds at 256^3; HBM GB/s vs peak"
+
+
+def _src_hash():
+    h = hashlib.sha256()
+    for f in ("k_eval.hip",):
+        with open(os.path.join(ROOT, "paper_1812_06765_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_hash, launches_bytes):
+    """HBM traffic of the image-pass kernel from a committed counter summary,
+    only if it was taken from the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "image_pass_256_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_src_sha256_16") != kernel_hash:
+        return None
+    return t.get("hbm_bytes_per_launch_256")
+
+
+def cpu_baseline(R, T, steps_s=None):
+    """One J + grad J evaluation of the FP64 oracle at the 256^3 level."""
+    import numpy as np
+
+    import oracle as O
+    m = R.shape
+    my = tuple(v // 2 + 1 for v in m)
+    prob = O.Problem(R, T, (1.0, 1.0, 1.0), my, 0.1, 10.0, 10.0)
+    y = prob.identity().astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    O.eval_J_grad(prob, y)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "seconds": dt,
+            "sample": "one J+grad J evaluation of the float64 numpy oracle at the 256^3 "
+                      "finest level (129^3 nodes, identity deformation), single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--max-iter", type=int, default=50)
+    ap.add_argument("--finest-evals", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the registration of one pair runs on one "
+              "device and this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1812_06765_amd import ngf, synth
+
+    n = args.size
+    t_gen = time.perf_counter()
+    pr = synth.ct_phantom_pair((n, n, n), seed_R=5, seed_u=6)
+    t_gen = time.perf_counter() - t_gen
+    print(f"[bench] inputs {n}^3 generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
+    R = torch.from_numpy(pr.R).cuda()
+    T = torch.from_numpy(pr.T).cuda()
+    ctx = ngf.Context(alpha=0.1, tau=10.0, rho=10.0, levels=args.levels, ratio=2,
+                      max_iter=args.max_iter, lbfgs_mem=5, tol_J=1e-6, early_stop=True)
+
+    for _ in range(args.warmup):
+        ctx.register(R, T)
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    ctx.set_profiling(True)
+    evals = 0
+    reports = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y, rep = ctx.register(R, T)
+        evals += sum(r["evals"] for r in rep)
+        reports.append(rep)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, kms, vox, nodes = ctx.kernel_time()
+    ctx.set_profiling(False)
+    print(f"[bench] timed {args.steps} registrations in {dt:.3f}s", file=sys.stderr, flush=True)
+
+    # finest level alone: a dedicated loop of evaluations at the final y
+    li = ctx.level_info(0)
+    g = torch.empty_like(y)
+    ctx.eval_J_grad(0, y)
+    torch.cuda.synchronize()
+    tf = time.perf_counter()
+    for _ in range(args.finest_evals):
+        ctx.eval_J_grad_async(0, y, g)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - tf
+    N = li.m[0] * li.m[1] * li.m[2]
+    Ny = li.my[0] * li.my[1] * li.my[2]
+    finest_bytes = 8 * N + 24 * Ny
+
+    # roofline of the dominant kernel over the timed region: algorithmic bytes
+    # per launch = 8 N (read R, T) + 12 N^y (read y) + 12 N^y (write grad)
+    alg_bytes = 8 * vox + 24 * nodes
+    achieved = alg_bytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    khash = _src_hash()
+    out = {
+        "metric": METRIC,
+        "value": evals / dt,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 coordinates and reductions)",
+        "data": "synthetic: seeded CT-like phantom pair, B-spline warp (max 6 voxels)",
+        "config": {"workload": f"single pair {n}^3 CT phantom, {args.levels}-level pyramid, "
+                               f"deformation grid {li.my[0]}^3 at the finest level, "
+                               f"alpha=0.1, eps=10, L-BFGS m=5, <= {args.max_iter} it/level, "
+                               "early stop 1e-6",
+                   "global_batch": 1, "seq_len": None, "parallelism": "single GPU"},
+        "registration_s": dt / args.steps,
+        "evals_per_registration": evals / args.steps,
+        "levels": reports[-1],
+        "finest": {"evals_per_s": args.finest_evals / tf,
+                   "eval_us": 1e6 * tf / args.finest_evals,
+                   "compulsory_bytes": finest_bytes,
+                   "effective_GBs": finest_bytes * args.finest_evals / tf / 1e9},
+        "roofline": {
+            "kernel": "k_image_pass (fused P, warp, NGF, adjoint, tile P^T)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": _traffic(khash, None),
+            "launches": launches,
+            "avg_launch_us": 1e3 * kms / max(launches, 1),
+            "alg_bytes_per_launch": alg_bytes / max(launches, 1),
+            "kernel_src": khash,
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, 256^3 eval)...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(pr.R, pr.T)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,245 @@
+/*
+ * ngfreg.h - C ABI of the MI355X (gfx950) library for matrix-free NGF +
+ * curvature deformable 3D image registration.
+ *
+ * Method: Budelmann, Koenig, Papenberg, Lellmann, "Fully-deformable 3D image
+ * registration in two seconds" (BVM 2019).  The objective is
+ *     J(y) = D(R, T(P y)) + alpha S(y)                         (Sec. 2.1, Eq. 1)
+ * with D the normalised gradient field distance (Sec. 2.2, Eq. 2), S the
+ * curvature regulariser (Sec. 2.1), P the trilinear conversion from the
+ * deformation grid to the image grid and P^T its conflict-free gather adjoint
+ * (Sec. 2.2, "Grid conversion", Eq. 3).  It is minimised by L-BFGS in a
+ * coarse-to-fine scheme (Sec. 2.1) over a multi-level image pyramid
+ * (Sec. 2.2, "Generating the multi-level pyramid").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Layout.  Images are float32 arrays [m_x][m_y][m_z], z fastest (C order).
+ *   A deformation y (and a gradient with respect to y) is float32
+ *   [3][m^y_x][m^y_y][m^y_z]: component-major, then x, y, z, z fastest.
+ * Grids.  The image grid is cell-centred: voxel i has its centre at
+ *   (i + 1/2) h.  The deformation grid is nodal over the same domain
+ *   [0, m h]: node j sits at j h^y with h^y = m h / (m^y - 1), and
+ *   m^y = m / ratio + 1 per axis at every level.  y holds positions (a
+ *   transformation); the identity is y = node positions (ngf_identity).
+ * Levels.  Level 0 is the input resolution; level l has m / 2^l cells of
+ *   spacing h 2^l per axis; level (levels - 1) is the coarsest.
+ * Pointers.  Unless a call says otherwise, every pointer argument is device
+ *   memory owned by the caller (for instance a torch tensor), valid for the
+ *   duration of the call; the library never frees or retains it.  Work is
+ *   enqueued on the context's HIP stream in order; a call returns after its
+ *   work is enqueued unless it documents a synchronisation.
+ * Ownership.  The context owns every internal buffer (pyramid, index maps,
+ *   partial sums, L-BFGS history).  All of them are allocated by
+ *   ngf_create / ngf_build_pyramid; the evaluation and L-BFGS calls do not
+ *   allocate (ngf_eval_pair may, on its first call for a larger grid).
+ * Errors.  No call throws or aborts across the ABI.  Every call returns an
+ *   ngf_status; on failure ngf_last_error() describes the cause and the
+ *   outputs are left unspecified.  One context per host thread.
+ */
+#ifndef NGFREG_H
+#define NGFREG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ngf_ctx ngf_ctx;
+
+/* Image grid: cells per axis and spacing per axis (index 0 = x ... 2 = z). */
+typedef struct {
+    int32_t m[3];
+    double h[3];
+} ngf_grid;
+
+/* Model and solver parameters.
+ *   alpha      regulariser weight (Eq. 1), >= 0
+ *   tau, rho   edge parameters of the template and reference gradients (Eq. 2), > 0
+ *   levels     pyramid levels, 1..12
+ *   ratio      image cells per deformation cell per axis (2: m^y = m/2 + 1)
+ *   max_iter   L-BFGS iterations per level, >= 0
+ *   lbfgs_mem  stored correction pairs, 1..8
+ *   tol_J      relative decrease for the early stop
+ *   early_stop 1: stop a level when J falls by at most tol_J (1 + |J|)
+ */
+typedef struct {
+    double alpha;
+    double tau;
+    double rho;
+    int32_t levels;
+    int32_t ratio;
+    int32_t max_iter;
+    int32_t lbfgs_mem;
+    double tol_J;
+    int32_t early_stop;
+    int32_t reserved;
+} ngf_params;
+
+typedef enum {
+    NGF_OK = 0,
+    NGF_E_ARG = -1,       /* null pointer or parameter out of range */
+    NGF_E_SHAPE = -2,     /* grid not divisible / too small for the levels */
+    NGF_E_STATE = -3,     /* call out of order (e.g. no pyramid built) */
+    NGF_E_LEVEL = -4,     /* level index out of range */
+    NGF_E_OOM = -5,       /* device allocation failed */
+    NGF_E_HIP = -6,       /* a HIP runtime call failed */
+    NGF_E_NONFINITE = -7  /* NaN or infinity in an input or in J */
+} ngf_status;
+
+/* Outcome of one L-BFGS iteration. */
+enum {
+    NGF_INFO_OK = 0,              /* step accepted */
+    NGF_INFO_CONVERGED = 1,       /* zero gradient or early-stop criterion met */
+    NGF_INFO_MAX_ITER = 2,        /* level ended after max_iter iterations */
+    NGF_INFO_LINESEARCH_FAIL = 3, /* no Armijo step within 10 halvings; y kept */
+    NGF_INFO_NONFINITE = 4        /* J or the gradient is not finite */
+};
+
+#define NGF_MAX_LEVELS 12
+
+/* Per-level outcome of ngf_register (index = level). */
+typedef struct {
+    int32_t levels;
+    int32_t iters[NGF_MAX_LEVELS];
+    int32_t evals[NGF_MAX_LEVELS];
+    int32_t info[NGF_MAX_LEVELS];
+    double J[NGF_MAX_LEVELS];
+} ngf_report;
+
+/* Library version string (static storage). */
+const char* ngf_version(void);
+
+/* Create a context.  `stream` is a hipStream_t (NULL = the null stream) on
+ * which all work of this context is enqueued.  Errors: NGF_E_ARG for a null
+ * `out` / `p` or parameters out of the documented ranges; NGF_E_HIP. */
+ngf_status ngf_create(const ngf_params* p, void* stream, ngf_ctx** out);
+
+/* Destroy a context and free everything it owns; NULL is ignored.
+ * Synchronises the context's stream first. */
+void ngf_destroy(ngf_ctx* ctx);
+
+/* Message of the last failure on this context (static until the next call). */
+const char* ngf_last_error(const ngf_ctx* ctx);
+
+/* Replace alpha, tau, rho (and the solver fields) of a context. */
+ngf_status ngf_set_params(ngf_ctx* ctx, const ngf_params* p);
+
+/* Build the multi-level pyramid of R and T (Sec. 2.2, "Generating the
+ * multi-level pyramid"): level l+1 is the 2x2x2 box mean of level l, summed in
+ * float64 in a fixed order and rounded once to float32, bit-identical for
+ * identical inputs.  Also builds the per-axis index maps of every level
+ * (Sec. 2.2, "Grid conversion": the index sets and weights are determined
+ * beforehand per dimension) and sizes all scratch buffers.  The two images
+ * are processed on two internal streams that join the context's stream.
+ *   R, T       input images on `g` ([m_x][m_y][m_z] float32)
+ *   host_ptrs  0: R and T are device pointers; 1: host pointers (copied
+ *              host-to-device on the two streams)
+ * Shape rule: every m_d divisible by ratio * 2^(levels-1), and the coarsest
+ * level at least 4 cells and 2 deformation cells per axis; otherwise
+ * NGF_E_SHAPE.  Synchronises before returning. */
+ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
+                             const ngf_grid* g, int32_t host_ptrs);
+
+/* Number of pyramid levels and the grids of one level: `img` gets the image
+ * grid, `def` the deformation grid (m = node counts, h = node spacing).
+ * Either output may be NULL. */
+ngf_status ngf_level_info(const ngf_ctx* ctx, int32_t level, ngf_grid* img, ngf_grid* def);
+
+/* Copy the pyramid images of a level into caller buffers (device, float32,
+ * the level's image shape).  Either output may be NULL. */
+ngf_status ngf_level_images(ngf_ctx* ctx, int32_t level, float* R_out, float* T_out);
+
+/* Copy one axis of a level's index map into caller device buffers of the
+ * level's m_axis entries: j0 (int32 node index), w0, w1 (float32 weights,
+ * rounded to nearest from the exact rationals).  Image point i is
+ * interpolated from nodes j0[i] (weight w0[i]) and j0[i]+1 (weight w1[i]). */
+ngf_status ngf_index_map(ngf_ctx* ctx, int32_t level, int32_t axis,
+                         int32_t* j0, float* w0, float* w1);
+
+/* Write the identity deformation (node positions) of a level into y. */
+ngf_status ngf_identity(ngf_ctx* ctx, int32_t level, float* y);
+
+/* Objective and gradient at y on a level (Sec. 2.2, "Evaluating the objective
+ * function": P, then D with its gradient, then P^T; plus alpha S):
+ *   y      deformation of the level (input)
+ *   J      host double, receives J(y) (the call synchronises to return it);
+ *          may be NULL, then nothing synchronises
+ *   grad   device float32, receives grad J(y) (same layout as y); may be NULL
+ *   DS     host double[2], receives (D, S); may be NULL
+ * J is also kept on the device (see ngf_eval_J_device).  Reductions are
+ * float64 with a fixed order, so equal inputs give equal outputs. */
+ngf_status ngf_eval_J_grad(ngf_ctx* ctx, int32_t level, const float* y, double* J,
+                           float* grad, double* DS);
+
+/* Device address of the double[3] {J, D, S} written by the last evaluation. */
+ngf_status ngf_eval_J_device(ngf_ctx* ctx, const double** JDS);
+
+/* Start L-BFGS (Sec. 2.1; Nocedal 1980) on a level from y0 (device): drops the
+ * stored pairs and evaluates J and grad J at y0.  Synchronises. */
+ngf_status ngf_lbfgs_reset(ngf_ctx* ctx, int32_t level, const float* y0);
+
+/* One L-BFGS iteration on the level given to ngf_lbfgs_reset: direction by
+ * the two-loop recursion (float64 inner products), Armijo backtracking
+ * (c1 = 1e-4, halving, at most 10 halvings), pair update.  `J` (host, may be
+ * NULL) receives the objective after the iteration, `info` (host, may be
+ * NULL) one of NGF_INFO_*.  Synchronises once per trial evaluation. */
+ngf_status ngf_lbfgs_step(ngf_ctx* ctx, double* J, int32_t* info);
+
+/* Copy the current L-BFGS iterate and its gradient into caller device
+ * buffers (either may be NULL); `J` (host, may be NULL) gets J there. */
+ngf_status ngf_lbfgs_get(ngf_ctx* ctx, float* y, float* grad, double* J);
+
+/* Prolongate a deformation from level `coarse_level` to the next finer level
+ * (coarse-to-fine scheme of Sec. 2.1): along each axis fine node 2j takes
+ * coarse node j, fine node 2j+1 the mean of coarse nodes j and j+1.  Only for
+ * ratio-aligned grids (fine m^y - 1 = 2 (coarse m^y - 1)). */
+ngf_status ngf_prolongate(ngf_ctx* ctx, int32_t coarse_level, const float* y_c, float* y_f);
+
+/* Full registration (Sec. 2.1, Sec. 2.2): build the pyramid of R and T, then
+ * for each level from the coarsest, start at the identity (coarsest) or the
+ * prolongated result, and run L-BFGS until max_iter, a failed line search, a
+ * zero gradient or (early_stop) the relative-decrease criterion.
+ *   y_out      receives the finest-level deformation ([3][m^y] float32),
+ *              device or host memory according to host_ptrs
+ *   rep        host, may be NULL: per-level iterations, evaluations, J, info
+ * Synchronises before returning. */
+ngf_status ngf_register(ngf_ctx* ctx, const float* R, const float* T, const ngf_grid* g,
+                        float* y_out, int32_t host_ptrs, ngf_report* rep);
+
+/* As ngf_register, from the pyramid already built by ngf_build_pyramid
+ * (device-resident inputs; the pyramid step is not repeated). */
+ngf_status ngf_register_levels(ngf_ctx* ctx, float* y_out, ngf_report* rep);
+
+/* Differentiation form: J(y; R, T) and its gradients with respect to y and to
+ * the template T on an explicit image pair (not the pyramid), for an autograd
+ * wrapper.  dJ/dT[k] = sum_i e[i] W(i -> k), the transpose of the warp applied
+ * to the NGF sensitivity e of each image point; both P^T and dJ/dT are
+ * evaluated by scatter with float32 atomic additions (image-point major), so
+ * results are reproducible only up to rounding.
+ *   g, my      image grid and deformation-grid node counts
+ *   R, T, y    device inputs; J host double (NULL: no synchronisation)
+ *   grad_y     device float32 like y, or NULL; grad_T device float32 like T,
+ *              or NULL (with both NULL only J is computed)
+ * May allocate scratch on the first call for a larger grid. */
+ngf_status ngf_eval_pair(ngf_ctx* ctx, const ngf_grid* g, const int32_t my[3],
+                         const float* R, const float* T, const float* y, double* J,
+                         float* grad_y, float* grad_T);
+
+/* Profiling aid: when enabled, the library records HIP events around every
+ * launch of the fused image-grid kernel (the dominant kernel of an
+ * evaluation) on the context's stream.  ngf_kernel_time returns the number of
+ * recorded launches, their summed duration in milliseconds, and the image
+ * voxels and deformation nodes those launches covered, then clears the
+ * record; it synchronises.  At most 4096 launches are recorded.  Any output
+ * pointer may be NULL. */
+ngf_status ngf_set_profiling(ngf_ctx* ctx, int32_t enable);
+ngf_status ngf_kernel_time(ngf_ctx* ctx, int32_t* launches, double* total_ms,
+                           int64_t* voxels, int64_t* nodes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NGFREG_H */

@@ -1,0 +1,514 @@
+// Objective and gradient evaluation: J = D(R, T(P y)) + alpha S(y)
+// (Sec. 2.1, Eq. 1), evaluated in the three steps of Sec. 2.2 ("Evaluating
+// the objective function"): P, then the NGF distance of Eq. 2 with its
+// matrix-free gradient, then P^T as a conflict-free gather (Eq. 3).
+//
+// Two kernels per evaluation, plus a one-block reduction:
+//
+// * image pass (one workgroup per image tile of kTX x kTY x kTZ voxels):
+//     - stage the deformation nodes the tile needs in LDS;
+//     - for the tile and a two-voxel halo: y_hat = P y (float64), the
+//       trilinear warp T_y = T(y_hat) and, inside the tile, dT_y/dy_hat;
+//     - for the tile and a one-voxel face halo: central differences of T_y
+//       and R, the NGF term 1 - r^2 and v = dD/d(grad T_y);
+//     - inside the tile: e = G^T v (adjoint stencil), dD/dy_hat = e dT_y/dy_hat;
+//     - P^T restricted to the tile: separable weighted sums (z, y, x) onto the
+//       (B+1)^3 nodes the tile touches, written as one partial block per tile.
+//   Every write has one owner, so nothing races and nothing is atomic.
+// * node pass (one workgroup per node tile): gathers the (at most 8) tile
+//   partials of each node (this completes the sum of Eq. 3), adds
+//   alpha grad S with grad S = hbar^y A(A(y - X)) from LDS halo tiles, and
+//   writes grad J once.
+// * reduce: fixed-order float64 sums of the block partials of D and S.
+#include "ngf_internal.h"
+
+#include <math.h>
+
+namespace ngf {
+
+namespace {
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
+}
+
+// Sum over the workgroup (four wave64s) in a fixed order; result in thread 0.
+__device__ inline double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    return r;
+}
+__device__ inline double block_max(double v, double* sh) {
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    return r;
+}
+
+// Continuous template index along one axis (float64), clamped, with the
+// slope mask of the clamp, the cell and the float32 fraction.  The index is
+// y_hat / h - 1/2 with a correctly rounded division: at the identity every
+// index is an exact integer, and a product with a rounded 1/h can land one
+// ulp below it and flip the cell (and so the one-sided derivative).
+struct AxisCell {
+    int i0;
+    float f;
+    float s;
+};
+
+__device__ inline AxisCell axis_cell(double yhat, double h, int m) {
+    double xi = yhat / h - 0.5;
+    const double hi = static_cast<double>(m - 1);
+    const float s = (xi >= 0.0 && xi <= hi) ? 1.0f : 0.0f;
+    xi = fmin(fmax(xi, 0.0), hi);
+    const double fl = fmin(floor(xi), static_cast<double>(m - 2));
+    AxisCell c;
+    c.i0 = static_cast<int>(fl);
+    c.f = static_cast<float>(xi - fl);
+    c.s = s;
+    return c;
+}
+
+template <int TX, int TY, int TZ, int RATIO>
+struct ImageTile {
+    static constexpr int H2X = TX + 4, H2Y = TY + 4, H2Z = TZ + 4;
+    static constexpr int NH2 = H2X * H2Y * H2Z;
+    static constexpr int H1X = TX + 2, H1Y = TY + 2, H1Z = TZ + 2;
+    static constexpr int NH1 = H1X * H1Y * H1Z;
+    static constexpr int NT = TX * TY * TZ;
+    static constexpr int KT = NT / kThreads;
+    static constexpr int BX = TX / RATIO, BY = TY / RATIO, BZ = TZ / RATIO;
+    static constexpr int PX = BX + 1, PY = BY + 1, PZ = BZ + 1;
+    static constexpr int NP = PX * PY * PZ;
+    static constexpr int NBX = (TX + 4) / RATIO + 4, NBY = (TY + 4) / RATIO + 4,
+                         NBZ = (TZ + 4) / RATIO + 4;
+    static constexpr int NNODE = NBX * NBY * NBZ;
+    static constexpr int VX = H1X * TY * TZ, VY = TX * H1Y * TZ, VZ = TX * TY * H1Z;
+    static constexpr int NV = VX + VY + VZ;
+    static constexpr int A = (NV > 3 * NNODE ? NV : 3 * NNODE);
+    static constexpr int GZ = 3 * TX * TY * PZ, GY = 3 * TX * PY * PZ;
+    static_assert(NT % kThreads == 0, "tile must be a multiple of the workgroup");
+    static_assert(TX % RATIO == 0 && TY % RATIO == 0 && TZ % RATIO == 0, "ratio-aligned tile");
+    static constexpr int B = (NH2 > 3 * NT ? NH2 : 3 * NT);
+    static_assert(GZ + GY <= A, "P^T staging fits region A");
+    static constexpr int LDS_FLOATS = A + B;
+    static_assert(LDS_FLOATS * 4 <= 65536, "image tile fits 64 KiB of LDS");
+};
+
+template <int TX, int TY, int TZ, int RATIO, bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
+    using L = ImageTile<TX, TY, TZ, RATIO>;
+    extern __shared__ float smem[];
+    float* sA = smem;                  // nodes, then v, then P^T staging
+    float* sTy = smem + L::A;          // T_y on the two-voxel halo box
+    float* sG = sTy;                   // dD/dy_hat on the tile (after v is formed)
+    __shared__ double red[4];
+
+    const int tile = blockIdx.x;
+    const int tz = tile % a.ntz;
+    const int ty = (tile / a.ntz) % a.nty;
+    const int tx = tile / (a.ntz * a.nty);
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+    const int mx = a.mx, my = a.my, mz = a.mz;
+    const int sxT = my * mz;
+
+    // ---- stage 0: nodes of the two-voxel halo box into LDS --------------
+    const int nlox = a.j0x[max(x0 - 2, 0)];
+    const int nloy = a.j0y[max(y0 - 2, 0)];
+    const int nloz = a.j0z[max(z0 - 2, 0)];
+    const int nnod = a.nx * a.ny * a.nz;
+    for (int i = threadIdx.x; i < 3 * L::NNODE; i += kThreads) {
+        const int c = i / L::NNODE;
+        const int r = i - c * L::NNODE;
+        const int bz = r % L::NBZ;
+        const int byy = (r / L::NBZ) % L::NBY;
+        const int bx = r / (L::NBZ * L::NBY);
+        const int gx = min(nlox + bx, a.nx - 1), gy = min(nloy + byy, a.ny - 1),
+                  gz = min(nloz + bz, a.nz - 1);
+        sA[i] = a.y[c * nnod + (gx * a.ny + gy) * a.nz + gz];
+    }
+    __syncthreads();
+
+    // ---- stage 1: P and the warp ----------------------------------------
+    // y_hat at image voxel (gx,gy,gz) (already clamped into the domain)
+    auto warp_at = [&](int gx, int gy, int gz, float* dT) -> float {
+        const int jx = a.j0x[gx], jy = a.j0y[gy], jz = a.j0z[gz];
+        const double ax1 = a.w1x[gx], ay1 = a.w1y[gy], az1 = a.w1z[gz];
+        const double ax0 = a.w0x[gx], ay0 = a.w0y[gy], az0 = a.w0z[gz];
+        const int base = ((jx - nlox) * L::NBY + (jy - nloy)) * L::NBZ + (jz - nloz);
+        double yh[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float* Y = sA + c * L::NNODE + base;
+            const double v000 = Y[0], v001 = Y[1];
+            const double v010 = Y[L::NBZ], v011 = Y[L::NBZ + 1];
+            const double v100 = Y[L::NBY * L::NBZ], v101 = Y[L::NBY * L::NBZ + 1];
+            const double v110 = Y[L::NBY * L::NBZ + L::NBZ],
+                         v111 = Y[L::NBY * L::NBZ + L::NBZ + 1];
+            const double c00 = az0 * v000 + az1 * v001, c01 = az0 * v010 + az1 * v011;
+            const double c10 = az0 * v100 + az1 * v101, c11 = az0 * v110 + az1 * v111;
+            const double c0 = ay0 * c00 + ay1 * c01, c1 = ay0 * c10 + ay1 * c11;
+            yh[c] = ax0 * c0 + ax1 * c1;
+        }
+        const AxisCell cx = axis_cell(yh[0], a.hx, mx);
+        const AxisCell cy = axis_cell(yh[1], a.hy, my);
+        const AxisCell cz = axis_cell(yh[2], a.hz, mz);
+        const float* Tb = a.T + cx.i0 * sxT + cy.i0 * mz + cz.i0;
+        const float v000 = Tb[0], v001 = Tb[1], v010 = Tb[mz], v011 = Tb[mz + 1];
+        const float v100 = Tb[sxT], v101 = Tb[sxT + 1], v110 = Tb[sxT + mz],
+                    v111 = Tb[sxT + mz + 1];
+        // interpolation as (1-f) a + f b: exact at f = 0 and f = 1, so the
+        // identity warp reproduces T bit for bit
+        const float qx = 1.0f - cx.f, qy = 1.0f - cy.f, qz = 1.0f - cz.f;
+        const float c00 = fmaf(cz.f, v001, qz * v000), c01 = fmaf(cz.f, v011, qz * v010);
+        const float c10 = fmaf(cz.f, v101, qz * v100), c11 = fmaf(cz.f, v111, qz * v110);
+        const float c0 = fmaf(cy.f, c01, qy * c00), c1 = fmaf(cy.f, c11, qy * c10);
+        if (GRAD && dT != nullptr) {
+            const float d0 = c01 - c00, d1 = c11 - c10;
+            const float e00 = v001 - v000, e01 = v011 - v010, e10 = v101 - v100,
+                        e11 = v111 - v110;
+            dT[0] = (c1 - c0) * (cx.s * a.fihx);
+            dT[1] = fmaf(cx.f, d1, qx * d0) * (cy.s * a.fihy);
+            const float ez0 = fmaf(cy.f, e01, qy * e00), ez1 = fmaf(cy.f, e11, qy * e10);
+            dT[2] = fmaf(cx.f, ez1, qx * ez0) * (cz.s * a.fihz);
+        }
+        return fmaf(cx.f, c1, qx * c0);
+    };
+
+    float dTk[L::KT][3];
+#pragma unroll
+    for (int k = 0; k < L::KT; ++k) {
+        const int t = threadIdx.x + k * kThreads;
+        const int lz = t % TZ, ly = (t / TZ) % TY, lx = t / (TZ * TY);
+        const int gx = min(x0 + lx, mx - 1), gy = min(y0 + ly, my - 1), gz = min(z0 + lz, mz - 1);
+        const float v = warp_at(gx, gy, gz, dTk[k]);
+        sTy[((lx + 2) * L::H2Y + (ly + 2)) * L::H2Z + (lz + 2)] = v;
+    }
+    // halo shell of the two-voxel box: x slabs, then y slabs, then z slabs
+    {
+        constexpr int S1 = 4 * L::H2Y * L::H2Z;
+        constexpr int S2 = S1 + TX * 4 * L::H2Z;
+        constexpr int S3 = S2 + TX * TY * 4;
+        for (int s = threadIdx.x; s < S3; s += kThreads) {
+            int bx, byy, bz;
+            if (s < S1) {
+                const int slab = s / (L::H2Y * L::H2Z);
+                const int r = s - slab * (L::H2Y * L::H2Z);
+                bx = slab < 2 ? slab : TX + slab;
+                byy = r / L::H2Z;
+                bz = r - byy * L::H2Z;
+            } else if (s < S2) {
+                const int q = s - S1;
+                const int slab = (q / L::H2Z) & 3;
+                bx = 2 + q / (4 * L::H2Z);
+                byy = slab < 2 ? slab : TY + slab;
+                bz = q % L::H2Z;
+            } else {
+                const int q = s - S2;
+                const int slab = q & 3;
+                const int r = q >> 2;
+                bx = 2 + r / TY;
+                byy = 2 + r % TY;
+                bz = slab < 2 ? slab : TZ + slab;
+            }
+            const int gx = clampi(x0 - 2 + bx, 0, mx - 1), gy = clampi(y0 - 2 + byy, 0, my - 1),
+                      gz = clampi(z0 - 2 + bz, 0, mz - 1);
+            sTy[(bx * L::H2Y + byy) * L::H2Z + bz] = warp_at(gx, gy, gz, nullptr);
+        }
+    }
+    __syncthreads();
+
+    // ---- stage 2: NGF on the tile and its one-voxel face halo -------------
+    float* sVx = sA;
+    float* sVy = sA + L::VX;
+    float* sVz = sA + L::VX + L::VY;
+    double dsum = 0.0;
+    const float tau = a.tau, rho = a.rho;
+    for (int i = threadIdx.x; i < L::NH1; i += kThreads) {
+        const int b1z = i % L::H1Z;
+        const int b1y = (i / L::H1Z) % L::H1Y;
+        const int b1x = i / (L::H1Z * L::H1Y);
+        const int hx = (b1x == 0 || b1x == TX + 1), hy = (b1y == 0 || b1y == TY + 1),
+                  hz = (b1z == 0 || b1z == TZ + 1);
+        if (hx + hy + hz >= 2) continue;
+        const int gx = x0 - 1 + b1x, gy = y0 - 1 + b1y, gz = z0 - 1 + b1z;
+        const int cxp = clampi(gx, 0, mx - 1), cyp = clampi(gy, 0, my - 1),
+                  czp = clampi(gz, 0, mz - 1);
+        // position of the clamped voxel in the two-voxel box
+        const int p = ((cxp - x0 + 2) * L::H2Y + (cyp - y0 + 2)) * L::H2Z + (czp - z0 + 2);
+        constexpr int SX = L::H2Y * L::H2Z, SY = L::H2Z;
+        const float gTx = (sTy[p + SX] - sTy[p - SX]) * a.i2hx;
+        const float gTy = (sTy[p + SY] - sTy[p - SY]) * a.i2hy;
+        const float gTz = (sTy[p + 1] - sTy[p - 1]) * a.i2hz;
+        // reference differences straight from HBM/L2 (replicated ends)
+        const float* Rp = a.R + cxp * sxT + cyp * mz + czp;
+        const int dxp = (cxp < mx - 1) ? sxT : 0, dxm = (cxp > 0) ? sxT : 0;
+        const int dyp = (cyp < my - 1) ? mz : 0, dym = (cyp > 0) ? mz : 0;
+        const int dzp = (czp < mz - 1) ? 1 : 0, dzm = (czp > 0) ? 1 : 0;
+        const float gRx = (Rp[dxp] - Rp[-dxm]) * a.i2hx;
+        const float gRy = (Rp[dyp] - Rp[-dym]) * a.i2hy;
+        const float gRz = (Rp[dzp] - Rp[-dzm]) * a.i2hz;
+        const float aa = fmaf(gTx, gTx, fmaf(gTy, gTy, fmaf(gTz, gTz, tau * tau)));
+        const float bb = fmaf(gRx, gRx, fmaf(gRy, gRy, fmaf(gRz, gRz, rho * rho)));
+        const float ab = fmaf(gTx, gRx, fmaf(gTy, gRy, fmaf(gTz, gRz, tau * rho)));
+        const float iaa = 1.0f / aa, ibb = 1.0f / bb;
+        if (hx + hy + hz == 0 && gx < mx && gy < my && gz < mz) {
+            // 1 - r^2 by Lagrange's identity on a = (grad T, tau), b = (grad R, rho):
+            // |a|^2 |b|^2 - <a,b>^2 = sum_{p<q} (a_p b_q - a_q b_p)^2.  Each term is the
+            // difference of two separately rounded products (never fused), so it is
+            // exactly 0 when a = b.
+            float q1, q2, q3, q4, q5, q6;
+            {
+#pragma clang fp contract(off)
+                q1 = gTx * gRy - gTy * gRx;
+                q2 = gTx * gRz - gTz * gRx;
+                q3 = gTy * gRz - gTz * gRy;
+                q4 = gTx * rho - tau * gRx;
+                q5 = gTy * rho - tau * gRy;
+                q6 = gTz * rho - tau * gRz;
+            }
+            const float lag = fmaf(q1, q1, fmaf(q2, q2, fmaf(q3, q3,
+                                  fmaf(q4, q4, fmaf(q5, q5, q6 * q6)))));
+            dsum += static_cast<double>(lag * iaa * ibb);
+        }
+        if (GRAD) {
+            // v = -hbar r/(nT nR) (grad R - (c/nT^2) grad T) = -hbar (ab/(aa bb)) (b - (ab/aa) a);
+            // ab/aa by a correctly rounded division is exactly 1 when a = b, so v = 0 there
+            const float k1 = ab / aa;
+            const float coef = -a.hbar * ab * iaa * ibb;
+            float vx = coef * fmaf(-k1, gTx, gRx);
+            float vy = coef * fmaf(-k1, gTy, gRy);
+            float vz = coef * fmaf(-k1, gTz, gRz);
+            // outside the domain, the adjoint stencil's end rows are realised by a
+            // mirrored ghost: v_d(m) = -v_d(m-1), v_d(-1) = -v_d(0)
+            if (gx != cxp) vx = -vx;
+            if (gy != cyp) vy = -vy;
+            if (gz != czp) vz = -vz;
+            if (!hy && !hz) sVx[(b1x * TY + (b1y - 1)) * TZ + (b1z - 1)] = vx;
+            if (!hx && !hz) sVy[((b1x - 1) * L::H1Y + b1y) * TZ + (b1z - 1)] = vy;
+            if (!hx && !hy) sVz[((b1x - 1) * TY + (b1y - 1)) * L::H1Z + b1z] = vz;
+        }
+    }
+    const double dtot = block_sum(dsum, red);
+    if (threadIdx.x == 0) a.dpart[tile] = dtot;
+    if (!GRAD) return;
+    __syncthreads();
+
+    // ---- stage 3: e = G^T v and dD/dy_hat on the tile ---------------------
+#pragma unroll
+    for (int k = 0; k < L::KT; ++k) {
+        const int t = threadIdx.x + k * kThreads;
+        const int lz = t % TZ, ly = (t / TZ) % TY, lx = t / (TZ * TY);
+        const bool in = (x0 + lx < mx) && (y0 + ly < my) && (z0 + lz < mz);
+        const float ex = sVx[(lx * TY + ly) * TZ + lz] - sVx[((lx + 2) * TY + ly) * TZ + lz];
+        const float ey = sVy[(lx * L::H1Y + ly) * TZ + lz] - sVy[(lx * L::H1Y + ly + 2) * TZ + lz];
+        const float ez = sVz[(lx * TY + ly) * L::H1Z + lz] - sVz[(lx * TY + ly) * L::H1Z + lz + 2];
+        const float e = in ? fmaf(ex, a.i2hx, fmaf(ey, a.i2hy, ez * a.i2hz)) : 0.0f;
+        sG[t] = e * dTk[k][0];
+        sG[L::NT + t] = e * dTk[k][1];
+        sG[2 * L::NT + t] = e * dTk[k][2];
+    }
+    __syncthreads();
+
+    // ---- stage 4: P^T restricted to the tile (separable: z, y, x) ---------
+    float* sGz = sA;             // [3][TX][TY][PZ]
+    float* sGy = sA + L::GZ;     // [3][TX][PY][PZ]
+    const int jz0 = z0 / RATIO, jy0 = y0 / RATIO, jx0 = x0 / RATIO;
+    for (int i = threadIdx.x; i < L::GZ; i += kThreads) {
+        const int nz = i % L::PZ;
+        const int r = i / L::PZ;      // (c, lx, ly)
+        const int jz = jz0 + nz;
+        const int lo = max(0, RATIO * (nz - 1)), hi = min(TZ, RATIO * (nz + 1));
+        const float* g = sG + r * TZ;  // sG[c][lx][ly][:]
+        float acc = 0.0f;
+        for (int lz = lo; lz < hi; ++lz) {
+            const int iz = min(z0 + lz, mz - 1);
+            const float w = (a.j0z[iz] == jz) ? a.w0z[iz] : a.w1z[iz];
+            acc = fmaf(w, g[lz], acc);
+        }
+        sGz[i] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < L::GY; i += kThreads) {
+        const int nz = i % L::PZ;
+        const int ny = (i / L::PZ) % L::PY;
+        const int r = i / (L::PZ * L::PY);  // (c, lx)
+        const int jy = jy0 + ny;
+        const int lo = max(0, RATIO * (ny - 1)), hi = min(TY, RATIO * (ny + 1));
+        float acc = 0.0f;
+        for (int ly = lo; ly < hi; ++ly) {
+            const int iy = min(y0 + ly, my - 1);
+            const float w = (a.j0y[iy] == jy) ? a.w0y[iy] : a.w1y[iy];
+            acc = fmaf(w, sGz[(r * TY + ly) * L::PZ + nz], acc);
+        }
+        sGy[i] = acc;
+    }
+    __syncthreads();
+    float* out = a.part + static_cast<int64_t>(tile) * 3 * L::NP;
+    for (int i = threadIdx.x; i < 3 * L::NP; i += kThreads) {
+        const int nz = i % L::PZ;
+        const int ny = (i / L::PZ) % L::PY;
+        const int nxl = (i / (L::PZ * L::PY)) % L::PX;
+        const int c = i / L::NP;
+        const int jx = jx0 + nxl;
+        const int lo = max(0, RATIO * (nxl - 1)), hi = min(TX, RATIO * (nxl + 1));
+        float acc = 0.0f;
+        for (int lx = lo; lx < hi; ++lx) {
+            const int ix = min(x0 + lx, mx - 1);
+            const float w = (a.j0x[ix] == jx) ? a.w0x[ix] : a.w1x[ix];
+            acc = fmaf(w, sGy[((c * TX + lx) * L::PY + ny) * L::PZ + nz], acc);
+        }
+        out[i] = acc;
+    }
+}
+
+// ------------------------------------------------------------------------
+// node pass
+// ------------------------------------------------------------------------
+template <int NX, int NY, int NZ>
+__global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
+    constexpr int B2X = NX + 4, B2Y = NY + 4, B2Z = NZ + 4, NB2 = B2X * B2Y * B2Z;
+    constexpr int B1X = NX + 2, B1Y = NY + 2, B1Z = NZ + 2, NB1 = B1X * B1Y * B1Z;
+    constexpr int NT = NX * NY * NZ, KT = NT / kThreads;
+    static_assert(NT % kThreads == 0, "node tile must be a multiple of the workgroup");
+    __shared__ float su[NB2];
+    __shared__ float sAu[NB1];
+    __shared__ double red[4];
+
+    const int blk = blockIdx.x;
+    const int bz = blk % a.nbz;
+    const int byy = (blk / a.nbz) % a.nby;
+    const int bx = blk / (a.nbz * a.nby);
+    const int n0x = bx * NX, n0y = byy * NY, n0z = bz * NZ;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nn = nx * ny * nz;
+    const int PX = a.bx + 1, PY = a.by + 1, PZ = a.bz + 1;
+    const int NP = PX * PY * PZ;
+
+    double ssum = 0.0, gmax = 0.0, g2 = 0.0;
+    const double hyd[3] = {a.hyx, a.hyy, a.hyz};
+    for (int c = 0; c < 3; ++c) {
+        const float* yc = a.y + c * nn;
+        for (int i = threadIdx.x; i < NB2; i += kThreads) {
+            const int z = i % B2Z, yy = (i / B2Z) % B2Y, x = i / (B2Z * B2Y);
+            const int gx = clampi(n0x - 2 + x, 0, nx - 1), gy = clampi(n0y - 2 + yy, 0, ny - 1),
+                      gz = clampi(n0z - 2 + z, 0, nz - 1);
+            const int gc = c == 0 ? gx : (c == 1 ? gy : gz);
+            const double X = static_cast<double>(gc) * hyd[c];
+            su[i] = static_cast<float>(static_cast<double>(yc[(gx * ny + gy) * nz + gz]) - X);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < NB1; i += kThreads) {
+            const int z = i % B1Z, yy = (i / B1Z) % B1Y, x = i / (B1Z * B1Y);
+            const int gx = clampi(n0x - 1 + x, 0, nx - 1), gy = clampi(n0y - 1 + yy, 0, ny - 1),
+                      gz = clampi(n0z - 1 + z, 0, nz - 1);
+            const int p = ((gx - n0x + 2) * B2Y + (gy - n0y + 2)) * B2Z + (gz - n0z + 2);
+            const float u0 = su[p];
+            const float lx = su[p + B2Y * B2Z] - 2.0f * u0 + su[p - B2Y * B2Z];
+            const float ly = su[p + B2Z] - 2.0f * u0 + su[p - B2Z];
+            const float lz = su[p + 1] - 2.0f * u0 + su[p - 1];
+            sAu[i] = fmaf(lx, a.ihy2x, fmaf(ly, a.ihy2y, lz * a.ihy2z));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KT; ++k) {
+            const int t = threadIdx.x + k * kThreads;
+            const int lz = t % NZ, ly = (t / NZ) % NY, lx = t / (NZ * NY);
+            const int gx = n0x + lx, gy = n0y + ly, gz = n0z + lz;
+            if (gx >= nx || gy >= ny || gz >= nz) continue;
+            const int gxc = min(gx + 1, nx - 1), gxm = max(gx - 1, 0);
+            const int gyc = min(gy + 1, ny - 1), gym = max(gy - 1, 0);
+            const int gzc = min(gz + 1, nz - 1), gzm = max(gz - 1, 0);
+            auto at = [&](int x, int y, int z) {
+                return sAu[((x - n0x + 1) * B1Y + (y - n0y + 1)) * B1Z + (z - n0z + 1)];
+            };
+            const float au = at(gx, gy, gz);
+            ssum += static_cast<double>(au) * static_cast<double>(au);
+            if (!a.want_grad) continue;
+            const float lxx = at(gxc, gy, gz) - 2.0f * au + at(gxm, gy, gz);
+            const float lyy = at(gx, gyc, gz) - 2.0f * au + at(gx, gym, gz);
+            const float lzz = at(gx, gy, gzc) - 2.0f * au + at(gx, gy, gzm);
+            const float aau = fmaf(lxx, a.ihy2x, fmaf(lyy, a.ihy2y, lzz * a.ihy2z));
+            // gather the image-tile partials of this node (completes Eq. 3)
+            float gd = 0.0f;
+            const int txh = gx / a.bx, tyh = gy / a.by, tzh = gz / a.bz;
+            const int rx = gx - txh * a.bx, ry = gy - tyh * a.by, rz = gz - tzh * a.bz;
+            for (int ox = 0; ox < 2; ++ox) {
+                const int ttx = txh - ox, llx = rx + ox * a.bx;
+                if (ttx < 0 || ttx >= a.ntx || (ox == 1 && rx != 0)) continue;
+                for (int oy = 0; oy < 2; ++oy) {
+                    const int tty = tyh - oy, lly = ry + oy * a.by;
+                    if (tty < 0 || tty >= a.nty || (oy == 1 && ry != 0)) continue;
+                    for (int oz = 0; oz < 2; ++oz) {
+                        const int ttz = tzh - oz, llz = rz + oz * a.bz;
+                        if (ttz < 0 || ttz >= a.ntz || (oz == 1 && rz != 0)) continue;
+                        const int tile = (ttx * a.nty + tty) * a.ntz + ttz;
+                        gd += a.part[(static_cast<int64_t>(tile) * 3 + c) * NP +
+                                     (llx * PY + lly) * PZ + llz];
+                    }
+                }
+            }
+            const float g = fmaf(a.alpha_hbary, aau, gd);
+            a.grad[c * nn + (gx * ny + gy) * nz + gz] = g;
+            gmax = fmax(gmax, static_cast<double>(fabsf(g)));
+            g2 += static_cast<double>(g) * static_cast<double>(g);
+        }
+        __syncthreads();
+    }
+    const double st = block_sum(ssum, red);
+    if (threadIdx.x == 0) a.spart[blk] = st;
+    if (a.want_grad) {
+        const double gm = block_max(gmax, red);
+        const double gq = block_sum(g2, red);
+        if (threadIdx.x == 0) {
+            a.gpart[2 * blk] = gm;
+            a.gpart[2 * blk + 1] = gq;
+        }
+    }
+}
+
+template <int RATIO>
+void launch_image_ratio(const ImagePassArgs& a, hipStream_t s) {
+    using L = ImageTile<kTX, kTY, kTZ, RATIO>;
+    const int blocks = a.ntx * a.nty * a.ntz;
+    const size_t lds = sizeof(float) * L::LDS_FLOATS;
+    if (a.want_grad)
+        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, true>), dim3(blocks),
+                           dim3(kThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, false>), dim3(blocks),
+                           dim3(kThreads), lds, s, a);
+}
+
+}  // namespace
+
+void launch_image_pass(const ImagePassArgs& a, int ratio, hipStream_t s) {
+    switch (ratio) {
+        case 2: launch_image_ratio<2>(a, s); break;
+        case 4: launch_image_ratio<4>(a, s); break;
+        default: break;
+    }
+}
+
+void launch_node_pass(const NodePassArgs& a, hipStream_t s) {
+    const int blocks = a.nbx * a.nby * a.nbz;
+    hipLaunchKernelGGL((k_node_pass<kNX, kNY, kNZ>), dim3(blocks), dim3(kThreads), 0, s, a);
+}
+
+}  // namespace ngf

@@ -1,0 +1,334 @@
+// L-BFGS on the device (Sec. 2.1: L-BFGS after Nocedal, 1980).
+//
+// The two-loop recursion d = -H g is run in coefficient space: every vector
+// it forms is a linear combination of the basis {s_k, t_k (stored pairs), g},
+// so with the float64 Gram matrix of that basis the recursion reduces to
+// O(m^2) scalar work, and d is formed in one pass over the stored vectors.
+// The Gram matrix is updated after each accepted step by one pass that forms
+// the new pair and all its inner products.  In exact arithmetic this is the
+// two-loop recursion; every inner product is accumulated in float64 and
+// reduced in a fixed order.
+//
+// Storage: hist holds kSlots pairs, slot k at hist + 2 k n (s) and
+// hist + (2 k + 1) n (t).  Basis index of s in slot k is k, of t in slot k is
+// kSlots + k, of the gradient kBasisG.
+#include "ngf_internal.h"
+
+#include <math.h>
+
+namespace ngf {
+
+namespace {
+
+constexpr int kDots = 6 * kSlots + 6;  // inner products formed per update
+constexpr int kLbBlocks = 1024;
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+__global__ void k_lb_init(LbState* st, int mem, double hmin, const double* jds) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    st->count = 0;
+    st->free_slot = 0;
+    st->mem = mem;
+    st->hmin = hmin;
+    for (int i = 0; i < kSlots; ++i) st->order[i] = -1;
+    st->J = jds[0];
+    st->D = jds[1];
+    st->S = jds[2];
+    st->gmax = jds[3];
+    st->gnorm2 = jds[4];
+    st->gtd = 0.0;
+    st->flags = 0.0;
+    st->count_d = 0.0;
+    for (int i = 0; i < kBasis * kBasis; ++i) st->G[i] = 0.0;
+    for (int i = 0; i < kBasis; ++i) st->coef[i] = 0.0;
+    st->G[kBasisG * kBasis + kBasisG] = jds[4];
+}
+
+// Direction coefficients by the two-loop recursion over the Gram matrix.
+// Falls back to the scaled steepest-descent step (and drops the memory) when
+// there is no pair or the recursion does not give a descent direction.
+// The current point's J, max |g| and |g|^2 are taken from the state, where
+// k_lb_init and k_lb_gram_update put them.
+__global__ void k_lb_solve(LbState* st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double* G = st->G;
+    G[kBasisG * kBasis + kBasisG] = st->gnorm2;
+    double flags = 0.0;
+    double coef[kBasis];
+    for (int i = 0; i < kBasis; ++i) coef[i] = 0.0;
+    double gtd = 0.0;
+    if (!(st->gmax > 0.0)) {
+        st->flags = 2.0;
+        st->gtd = 0.0;
+        for (int i = 0; i < kBasis; ++i) st->coef[i] = 0.0;
+        return;
+    }
+    int count = st->count;
+    if (count > 0) {
+        double q[kBasis], al[kSlots];
+        for (int i = 0; i < kBasis; ++i) q[i] = 0.0;
+        q[kBasisG] = 1.0;
+        for (int k = count - 1; k >= 0; --k) {
+            const int si = st->order[k], ti = kSlots + st->order[k];
+            double sq = 0.0;
+            for (int l = 0; l < kBasis; ++l) sq += q[l] * G[si * kBasis + l];
+            al[k] = sq / G[si * kBasis + ti];
+            q[ti] -= al[k];
+        }
+        const int sn = st->order[count - 1], tn = kSlots + st->order[count - 1];
+        const double gamma = G[sn * kBasis + tn] / G[tn * kBasis + tn];
+        for (int i = 0; i < kBasis; ++i) q[i] *= gamma;
+        for (int k = 0; k < count; ++k) {
+            const int si = st->order[k], ti = kSlots + st->order[k];
+            double tr = 0.0;
+            for (int l = 0; l < kBasis; ++l) tr += q[l] * G[ti * kBasis + l];
+            const double b = tr / G[si * kBasis + ti];
+            q[si] += al[k] - b;
+        }
+        for (int i = 0; i < kBasis; ++i) coef[i] = -q[i];
+        for (int l = 0; l < kBasis; ++l) gtd += coef[l] * G[kBasisG * kBasis + l];
+        if (!(gtd < 0.0)) {
+            count = 0;
+            flags = 1.0;
+        }
+    }
+    if (count == 0) {
+        st->count = 0;
+        for (int i = 0; i < kSlots; ++i) st->order[i] = -1;
+        st->free_slot = 0;
+        const double scale = st->hmin / st->gmax;
+        for (int i = 0; i < kBasis; ++i) coef[i] = 0.0;
+        coef[kBasisG] = -scale;
+        gtd = -scale * st->gnorm2;
+    }
+    for (int i = 0; i < kBasis; ++i) st->coef[i] = coef[i];
+    st->gtd = gtd;
+    st->flags = flags;
+    st->count_d = static_cast<double>(st->count);
+}
+
+// d = sum_l coef_l b_l over the active basis; yt = y + d.
+__global__ __launch_bounds__(kThreads) void k_lb_combine(const LbState* st,
+                                                         const float* __restrict__ hist,
+                                                         int64_t n, const float* __restrict__ y,
+                                                         const float* __restrict__ g,
+                                                         float* __restrict__ d,
+                                                         float* __restrict__ yt) {
+    __shared__ double cs[kSlots], ct[kSlots];
+    __shared__ int sl[kSlots];
+    __shared__ double cg;
+    __shared__ int cnt;
+    if (threadIdx.x == 0) {
+        cnt = st->count;
+        cg = st->coef[kBasisG];
+        for (int k = 0; k < kSlots; ++k) {
+            const int s = k < st->count ? st->order[k] : 0;
+            sl[k] = s;
+            cs[k] = k < st->count ? st->coef[s] : 0.0;
+            ct[k] = k < st->count ? st->coef[kSlots + s] : 0.0;
+        }
+    }
+    __syncthreads();
+    const int count = cnt;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads) {
+        double v = cg * static_cast<double>(g[i]);
+        for (int k = 0; k < count; ++k) {
+            const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * n;
+            v += cs[k] * static_cast<double>(sk[i]) + ct[k] * static_cast<double>(sk[n + i]);
+        }
+        const float df = static_cast<float>(v);
+        d[i] = df;
+        yt[i] = y[i] + df;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_lb_axpy(const float* __restrict__ y,
+                                                      const float* __restrict__ d, float t,
+                                                      float* __restrict__ yt, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads)
+        yt[i] = fmaf(t, d[i], y[i]);
+}
+
+// Forms the new pair s = yt - y, t = gt - g in the free slot and all inner
+// products of {s, t, gt} with the stored pairs and with each other.
+// Per-block float64 partials: dotpart[block][kDots].
+__global__ __launch_bounds__(kThreads) void k_lb_update_dots(const LbState* st,
+                                                             float* __restrict__ hist,
+                                                             int64_t n,
+                                                             const float* __restrict__ y,
+                                                             const float* __restrict__ yt,
+                                                             const float* __restrict__ g,
+                                                             const float* __restrict__ gt,
+                                                             double* __restrict__ dotpart) {
+    __shared__ int sl[kSlots];
+    __shared__ int cnt, fs;
+    __shared__ double sh[4][kDots];
+    if (threadIdx.x == 0) {
+        cnt = st->count;
+        fs = st->free_slot;
+        for (int k = 0; k < kSlots; ++k) sl[k] = k < st->count ? st->order[k] : 0;
+    }
+    __syncthreads();
+    const int count = cnt;
+    double acc[kDots];
+#pragma unroll
+    for (int j = 0; j < kDots; ++j) acc[j] = 0.0;
+    float* sn = hist + (2 * static_cast<int64_t>(fs)) * n;
+    float* tn = sn + n;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kThreads) {
+        const float s = yt[i] - y[i];
+        const float t = gt[i] - g[i];
+        const float gn = gt[i];
+        sn[i] = s;
+        tn[i] = t;
+        const double sd = s, td = t, gd = gn;
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            if (k < count) {
+                const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * n;
+                const double a = sk[i], b = sk[n + i];
+                acc[6 * k + 0] += sd * a;
+                acc[6 * k + 1] += sd * b;
+                acc[6 * k + 2] += td * a;
+                acc[6 * k + 3] += td * b;
+                acc[6 * k + 4] += gd * a;
+                acc[6 * k + 5] += gd * b;
+            }
+        }
+        acc[6 * kSlots + 0] += sd * sd;
+        acc[6 * kSlots + 1] += sd * td;
+        acc[6 * kSlots + 2] += sd * gd;
+        acc[6 * kSlots + 3] += td * td;
+        acc[6 * kSlots + 4] += td * gd;
+        acc[6 * kSlots + 5] += gd * gd;
+    }
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kDots; ++j) {
+        const double v = wave_sum(acc[j]);
+        if ((threadIdx.x & 63) == 0) sh[w][j] = v;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kDots; j += kThreads)
+        dotpart[static_cast<int64_t>(blockIdx.x) * kDots + j] =
+            (sh[0][j] + sh[1][j]) + (sh[2][j] + sh[3][j]);
+}
+
+// Fixed-order sum of the per-block dot partials, curvature test of the new
+// pair, ring update and Gram-matrix update.
+__global__ __launch_bounds__(64) void k_lb_gram_update(LbState* st, const double* dotpart,
+                                                       int nblocks, const double* jds) {
+    __shared__ double dots[kDots];
+    for (int j = threadIdx.x; j < kDots; j += 64) {
+        double s = 0.0;
+        for (int b = 0; b < nblocks; ++b) s += dotpart[static_cast<int64_t>(b) * kDots + j];
+        dots[j] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double* G = st->G;
+    const int count = st->count;
+    const int fs = st->free_slot;
+    const double ss = dots[6 * kSlots + 0], sz = dots[6 * kSlots + 1],
+                 sg = dots[6 * kSlots + 2], zz = dots[6 * kSlots + 3],
+                 zg = dots[6 * kSlots + 4], gg = dots[6 * kSlots + 5];
+    const bool accept = sz > 1e-10 * sqrt(ss) * sqrt(zz);
+    auto setg = [&](int i, int j, double v) {
+        G[i * kBasis + j] = v;
+        G[j * kBasis + i] = v;
+    };
+    // the gradient row refers to the new gradient from now on
+    for (int k = 0; k < count; ++k) {
+        const int s = st->order[k];
+        setg(kBasisG, s, dots[6 * k + 4]);
+        setg(kBasisG, kSlots + s, dots[6 * k + 5]);
+    }
+    setg(kBasisG, kBasisG, gg);
+    if (accept) {
+        const int S = fs, T = kSlots + fs;
+        for (int k = 0; k < count; ++k) {
+            const int s = st->order[k];
+            setg(S, s, dots[6 * k + 0]);
+            setg(S, kSlots + s, dots[6 * k + 1]);
+            setg(T, s, dots[6 * k + 2]);
+            setg(T, kSlots + s, dots[6 * k + 3]);
+        }
+        setg(S, S, ss);
+        setg(S, T, sz);
+        setg(T, T, zz);
+        setg(kBasisG, S, sg);
+        setg(kBasisG, T, zg);
+        int c = count;
+        if (c == st->mem) {  // drop the oldest pair
+            for (int k = 1; k < c; ++k) st->order[k - 1] = st->order[k];
+            c -= 1;
+        }
+        st->order[c] = fs;
+        st->count = c + 1;
+        // next free slot: the lowest slot not in use
+        for (int s = 0; s < kSlots; ++s) {
+            bool used = false;
+            for (int k = 0; k < st->count; ++k) used |= (st->order[k] == s);
+            if (!used) {
+                st->free_slot = s;
+                break;
+            }
+        }
+    }
+    st->count_d = static_cast<double>(st->count);
+    st->J = jds[0];
+    st->D = jds[1];
+    st->S = jds[2];
+    st->gmax = jds[3];
+    st->gnorm2 = jds[4];
+}
+
+}  // namespace
+
+int lb_dot_blocks(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    if (b > kLbBlocks) b = kLbBlocks;
+    if (b < 1) b = 1;
+    return static_cast<int>(b);
+}
+
+void launch_lb_init(LbState* st, int mem, double hmin, const double* jds, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_init, dim3(1), dim3(64), 0, s, st, mem, hmin, jds);
+}
+
+void launch_lb_solve(LbState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_solve, dim3(1), dim3(64), 0, s, st);
+}
+
+void launch_lb_combine(LbState* st, const float* hist, int64_t n, const float* y, const float* g,
+                       float* d, float* yt, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_combine, dim3(lb_dot_blocks(n) * 2), dim3(kThreads), 0, s, st, hist,
+                       n, y, g, d, yt);
+}
+
+void launch_lb_axpy(const float* y, const float* d, float t, float* yt, int64_t n,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_axpy, dim3(lb_dot_blocks(n) * 2), dim3(kThreads), 0, s, y, d, t, yt,
+                       n);
+}
+
+void launch_lb_update_dots(LbState* st, float* hist, int64_t n, const float* y, const float* yt,
+                           const float* g, const float* gt, double* dotpart, int nblocks,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_update_dots, dim3(nblocks), dim3(kThreads), 0, s, st, hist, n, y, yt,
+                       g, gt, dotpart);
+}
+
+void launch_lb_gram_update(LbState* st, const double* dotpart, int nblocks, const double* jds,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_gram_update, dim3(1), dim3(64), 0, s, st, dotpart, nblocks, jds);
+}
+
+}  // namespace ngf

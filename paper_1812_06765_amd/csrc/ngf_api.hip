@@ -1,0 +1,791 @@
+// Host side of the C ABI declared in include/ngfreg.h: context, pyramid,
+// evaluation orchestration, L-BFGS driver and the multi-level registration.
+// Every compute step runs in the HIP kernels of this library; this file only
+// validates arguments, owns device buffers and enqueues work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ngfreg.h"
+#include "ngf_internal.h"
+
+using namespace ngf;
+
+namespace {
+
+struct Level {
+    int m[3] = {0, 0, 0};
+    int my[3] = {0, 0, 0};
+    double h[3] = {0, 0, 0};
+    double hy[3] = {0, 0, 0};
+    float* R = nullptr;
+    float* T = nullptr;
+    int32_t* j0[3] = {nullptr, nullptr, nullptr};
+    float* w0[3] = {nullptr, nullptr, nullptr};
+    float* w1[3] = {nullptr, nullptr, nullptr};
+    int64_t N() const { return static_cast<int64_t>(m[0]) * m[1] * m[2]; }
+    int64_t Ny() const { return static_cast<int64_t>(my[0]) * my[1] * my[2]; }
+};
+
+struct Status {
+    ngf_status code;
+};
+
+constexpr int kProfMax = 4096;
+
+}  // namespace
+
+struct ngf_ctx {
+    ngf_params p{};
+    hipStream_t stream = nullptr;
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t join[3] = {nullptr, nullptr, nullptr};
+    std::string err;
+    std::vector<Level> lv;
+    std::vector<void*> owned;  // every device allocation of the pyramid
+
+    // evaluation scratch (sized for level 0 by ngf_build_pyramid / ngf_reserve)
+    float* part = nullptr;
+    size_t part_cap = 0;  // floats
+    double* dpart = nullptr;
+    size_t dpart_cap = 0;
+    double* spart = nullptr;
+    double* gpart = nullptr;
+    size_t nblk_cap = 0;
+    double* jds = nullptr;       // device {J, D, S, max|g|, |g|^2, ...}
+    double* host_jds = nullptr;  // pinned
+    int* dflag = nullptr;
+
+    // L-BFGS
+    size_t lb_cap = 0;  // floats per vector
+    float* ly = nullptr;
+    float* lg = nullptr;
+    float* lyt = nullptr;
+    float* lgt = nullptr;
+    float* ld = nullptr;
+    float* ltmp = nullptr;
+    float* hist = nullptr;
+    LbState* st = nullptr;
+    LbState* host_st = nullptr;  // pinned
+    double* dotpart = nullptr;
+    int lb_level = -1;
+    double lb_J = 0.0;
+    double lb_gmax = 0.0;
+    int lb_evals = 0;
+
+    // pair form scratch
+    float* pair_img = nullptr;
+    size_t pair_img_cap = 0;
+
+    // profiling of the image-pass kernel
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    int nprof = 0;
+    int64_t prof_vox = 0;
+    int64_t prof_nodes = 0;
+};
+
+namespace {
+
+ngf_status fail(ngf_ctx* c, ngf_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(ctx, NGF_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+ngf_status dalloc(ngf_ctx* c, T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, NGF_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    return NGF_OK;
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+bool params_ok(const ngf_params* p, std::string* why) {
+    if (!(std::isfinite(p->alpha) && p->alpha >= 0.0)) return *why = "alpha must be >= 0", false;
+    if (!(std::isfinite(p->tau) && p->tau > 0.0)) return *why = "tau must be > 0", false;
+    if (!(std::isfinite(p->rho) && p->rho > 0.0)) return *why = "rho must be > 0", false;
+    if (p->levels < 1 || p->levels > NGF_MAX_LEVELS) return *why = "levels out of range", false;
+    if (p->ratio != 2 && p->ratio != 4) return *why = "ratio must be 2 or 4", false;
+    if (p->max_iter < 0) return *why = "max_iter must be >= 0", false;
+    if (p->lbfgs_mem < 1 || p->lbfgs_mem > kMaxMem) return *why = "lbfgs_mem out of range", false;
+    if (!(std::isfinite(p->tol_J) && p->tol_J >= 0.0)) return *why = "tol_J must be >= 0", false;
+    return true;
+}
+
+int tiles(int m, int t) { return (m + t - 1) / t; }
+
+int64_t part_floats(const Level& L, int ratio) {
+    const int64_t nt = static_cast<int64_t>(tiles(L.m[0], kTX)) * tiles(L.m[1], kTY) *
+                       tiles(L.m[2], kTZ);
+    const int64_t np = static_cast<int64_t>(kTX / ratio + 1) * (kTY / ratio + 1) *
+                       (kTZ / ratio + 1);
+    return nt * 3 * np;
+}
+int64_t img_tiles(const Level& L) {
+    return static_cast<int64_t>(tiles(L.m[0], kTX)) * tiles(L.m[1], kTY) * tiles(L.m[2], kTZ);
+}
+int64_t node_blocks(const Level& L) {
+    return static_cast<int64_t>(tiles(L.my[0], kNX)) * tiles(L.my[1], kNY) * tiles(L.my[2], kNZ);
+}
+
+ngf_status ensure_scratch(ngf_ctx* c, const Level& L) {
+    const size_t pf = static_cast<size_t>(part_floats(L, c->p.ratio));
+    if (pf > c->part_cap) {
+        dfree(c->part);
+        c->part = nullptr;
+        c->part_cap = 0;
+        if (dalloc(c, &c->part, pf) != NGF_OK) return NGF_E_OOM;
+        c->part_cap = pf;
+    }
+    const size_t nt = static_cast<size_t>(img_tiles(L));
+    if (nt > c->dpart_cap) {
+        dfree(c->dpart);
+        c->dpart = nullptr;
+        c->dpart_cap = 0;
+        if (dalloc(c, &c->dpart, nt) != NGF_OK) return NGF_E_OOM;
+        c->dpart_cap = nt;
+    }
+    const size_t nb = static_cast<size_t>(node_blocks(L));
+    if (nb > c->nblk_cap) {
+        dfree(c->spart);
+        dfree(c->gpart);
+        c->spart = c->gpart = nullptr;
+        c->nblk_cap = 0;
+        if (dalloc(c, &c->spart, nb) != NGF_OK) return NGF_E_OOM;
+        if (dalloc(c, &c->gpart, 2 * nb) != NGF_OK) return NGF_E_OOM;
+        c->nblk_cap = nb;
+    }
+    return NGF_OK;
+}
+
+ngf_status ensure_lbfgs(ngf_ctx* c, size_t n) {
+    if (n <= c->lb_cap) return NGF_OK;
+    for (float** p : {&c->ly, &c->lg, &c->lyt, &c->lgt, &c->ld, &c->ltmp, &c->hist}) {
+        dfree(*p);
+        *p = nullptr;
+    }
+    dfree(c->dotpart);
+    c->dotpart = nullptr;
+    c->lb_cap = 0;
+    for (float** p : {&c->ly, &c->lg, &c->lyt, &c->lgt, &c->ld, &c->ltmp})
+        if (dalloc(c, p, n) != NGF_OK) return NGF_E_OOM;
+    if (dalloc(c, &c->hist, static_cast<size_t>(2) * kSlots * n) != NGF_OK) return NGF_E_OOM;
+    if (dalloc(c, &c->dotpart, static_cast<size_t>(lb_dot_blocks(static_cast<int64_t>(n))) *
+                                   (6 * kSlots + 6)) != NGF_OK)
+        return NGF_E_OOM;
+    c->lb_cap = n;
+    return NGF_OK;
+}
+
+void free_pyramid(ngf_ctx* c) {
+    for (void* p : c->owned) dfree(p);
+    c->owned.clear();
+    c->lv.clear();
+}
+
+ImagePassArgs image_args(ngf_ctx* c, const Level& L, const float* R, const float* T,
+                         const float* y, bool grad) {
+    ImagePassArgs a{};
+    a.R = R;
+    a.T = T;
+    a.y = y;
+    a.j0x = L.j0[0];
+    a.j0y = L.j0[1];
+    a.j0z = L.j0[2];
+    a.w0x = L.w0[0];
+    a.w0y = L.w0[1];
+    a.w0z = L.w0[2];
+    a.w1x = L.w1[0];
+    a.w1y = L.w1[1];
+    a.w1z = L.w1[2];
+    a.part = c->part;
+    a.dpart = c->dpart;
+    a.mx = L.m[0];
+    a.my = L.m[1];
+    a.mz = L.m[2];
+    a.nx = L.my[0];
+    a.ny = L.my[1];
+    a.nz = L.my[2];
+    a.ntx = tiles(L.m[0], kTX);
+    a.nty = tiles(L.m[1], kTY);
+    a.ntz = tiles(L.m[2], kTZ);
+    a.hx = L.h[0];
+    a.hy = L.h[1];
+    a.hz = L.h[2];
+    a.fihx = static_cast<float>(1.0 / L.h[0]);
+    a.fihy = static_cast<float>(1.0 / L.h[1]);
+    a.fihz = static_cast<float>(1.0 / L.h[2]);
+    a.i2hx = static_cast<float>(0.5 / L.h[0]);
+    a.i2hy = static_cast<float>(0.5 / L.h[1]);
+    a.i2hz = static_cast<float>(0.5 / L.h[2]);
+    a.tau = static_cast<float>(c->p.tau);
+    a.rho = static_cast<float>(c->p.rho);
+    a.hbar = static_cast<float>(L.h[0] * L.h[1] * L.h[2]);
+    a.want_grad = grad ? 1 : 0;
+    return a;
+}
+
+// Enqueue one evaluation on the context stream; results land in c->jds and
+// (if grad != nullptr) in grad.
+ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float* T,
+                        const float* y, float* grad) {
+    const bool want = grad != nullptr;
+    ImagePassArgs a = image_args(c, L, R, T, y, want);
+    if (c->prof && c->nprof < kProfMax) {
+        HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof], c->stream));
+        launch_image_pass(a, c->p.ratio, c->stream);
+        HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof + 1], c->stream));
+        c->nprof++;
+        c->prof_vox += L.N();
+        c->prof_nodes += L.Ny();
+    } else {
+        launch_image_pass(a, c->p.ratio, c->stream);
+    }
+    HIPCHK(c, hipGetLastError());
+    NodePassArgs b{};
+    b.y = y;
+    b.part = c->part;
+    b.grad = grad;
+    b.spart = c->spart;
+    b.gpart = c->gpart;
+    b.nx = L.my[0];
+    b.ny = L.my[1];
+    b.nz = L.my[2];
+    b.ntx = a.ntx;
+    b.nty = a.nty;
+    b.ntz = a.ntz;
+    b.bx = kTX / c->p.ratio;
+    b.by = kTY / c->p.ratio;
+    b.bz = kTZ / c->p.ratio;
+    b.nbx = tiles(L.my[0], kNX);
+    b.nby = tiles(L.my[1], kNY);
+    b.nbz = tiles(L.my[2], kNZ);
+    b.hyx = L.hy[0];
+    b.hyy = L.hy[1];
+    b.hyz = L.hy[2];
+    b.ihy2x = static_cast<float>(1.0 / (L.hy[0] * L.hy[0]));
+    b.ihy2y = static_cast<float>(1.0 / (L.hy[1] * L.hy[1]));
+    b.ihy2z = static_cast<float>(1.0 / (L.hy[2] * L.hy[2]));
+    const double hbary = L.hy[0] * L.hy[1] * L.hy[2];
+    b.alpha_hbary = static_cast<float>(c->p.alpha * hbary);
+    b.alpha = static_cast<float>(c->p.alpha);
+    b.want_grad = want ? 1 : 0;
+    launch_node_pass(b, c->stream);
+    HIPCHK(c, hipGetLastError());
+    ReduceArgs r{};
+    r.dpart = c->dpart;
+    r.nd = static_cast<int>(img_tiles(L));
+    r.spart = c->spart;
+    r.ns = static_cast<int>(node_blocks(L));
+    r.gpart = c->gpart;
+    r.ng = want ? r.ns : 0;
+    r.half_hbar = 0.5 * L.h[0] * L.h[1] * L.h[2];
+    r.half_hbary = 0.5 * hbary;
+    r.alpha = c->p.alpha;
+    r.out = c->jds;
+    launch_reduce(r, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return NGF_OK;
+}
+
+ngf_status read_jds(ngf_ctx* c) {
+    HIPCHK(c, hipMemcpyAsync(c->host_jds, c->jds, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NGF_OK;
+}
+
+ngf_status check_level(const ngf_ctx* c, int level) {
+    if (c->lv.empty()) return NGF_E_STATE;
+    if (level < 0 || level >= static_cast<int>(c->lv.size())) return NGF_E_LEVEL;
+    return NGF_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* ngf_version(void) { return "ngfreg 0.1 gfx950"; }
+
+ngf_status ngf_create(const ngf_params* p, void* stream, ngf_ctx** out) {
+    if (!out || !p) return NGF_E_ARG;
+    *out = nullptr;
+    std::string why;
+    if (!params_ok(p, &why)) return NGF_E_ARG;
+    ngf_ctx* c = new (std::nothrow) ngf_ctx();
+    if (!c) return NGF_E_OOM;
+    c->p = *p;
+    c->stream = static_cast<hipStream_t>(stream);
+    ngf_status s = NGF_OK;
+    auto chk = [&](hipError_t e) {
+        if (e != hipSuccess && s == NGF_OK) s = NGF_E_HIP;
+    };
+    chk(hipStreamCreateWithFlags(&c->side[0], hipStreamNonBlocking));
+    chk(hipStreamCreateWithFlags(&c->side[1], hipStreamNonBlocking));
+    for (int i = 0; i < 3; ++i) chk(hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming));
+    chk(hipMalloc(reinterpret_cast<void**>(&c->jds), 8 * sizeof(double)));
+    chk(hipHostMalloc(reinterpret_cast<void**>(&c->host_jds), 8 * sizeof(double),
+                      hipHostMallocDefault));
+    chk(hipMalloc(reinterpret_cast<void**>(&c->st), sizeof(LbState)));
+    chk(hipHostMalloc(reinterpret_cast<void**>(&c->host_st), sizeof(LbState),
+                      hipHostMallocDefault));
+    chk(hipMalloc(reinterpret_cast<void**>(&c->dflag), sizeof(int)));
+    if (s != NGF_OK) {
+        ngf_destroy(c);
+        return s;
+    }
+    *out = c;
+    return NGF_OK;
+}
+
+void ngf_destroy(ngf_ctx* c) {
+    if (!c) return;
+    if (c->stream || c->side[0]) (void)hipStreamSynchronize(c->stream);
+    for (hipStream_t s : c->side)
+        if (s) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    for (hipEvent_t e : c->join)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    free_pyramid(c);
+    for (void* p : {static_cast<void*>(c->part), static_cast<void*>(c->dpart),
+                    static_cast<void*>(c->spart), static_cast<void*>(c->gpart),
+                    static_cast<void*>(c->jds), static_cast<void*>(c->dflag),
+                    static_cast<void*>(c->ly), static_cast<void*>(c->lg),
+                    static_cast<void*>(c->lyt), static_cast<void*>(c->lgt),
+                    static_cast<void*>(c->ld), static_cast<void*>(c->ltmp),
+                    static_cast<void*>(c->hist), static_cast<void*>(c->st),
+                    static_cast<void*>(c->dotpart), static_cast<void*>(c->pair_img)})
+        dfree(p);
+    if (c->host_jds) (void)hipHostFree(c->host_jds);
+    if (c->host_st) (void)hipHostFree(c->host_st);
+    delete c;
+}
+
+const char* ngf_last_error(const ngf_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+ngf_status ngf_set_params(ngf_ctx* c, const ngf_params* p) {
+    if (!c || !p) return NGF_E_ARG;
+    std::string why;
+    if (!params_ok(p, &why)) return fail(c, NGF_E_ARG, why);
+    if (!c->lv.empty() && (p->levels != c->p.levels || p->ratio != c->p.ratio))
+        return fail(c, NGF_E_STATE, "levels and ratio are fixed once a pyramid is built");
+    c->p = *p;
+    return NGF_OK;
+}
+
+ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const ngf_grid* g,
+                             int32_t host_ptrs) {
+    if (!c) return NGF_E_ARG;
+    if (!R || !T || !g) return fail(c, NGF_E_ARG, "null R, T or grid");
+    const int L = c->p.levels, r = c->p.ratio;
+    const int64_t div = static_cast<int64_t>(r) << (L - 1);
+    int64_t N = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (!(std::isfinite(g->h[d]) && g->h[d] > 0.0))
+            return fail(c, NGF_E_ARG, "spacing must be positive");
+        if (g->m[d] <= 0 || g->m[d] % div != 0)
+            return fail(c, NGF_E_SHAPE, "each m_d must be divisible by ratio * 2^(levels-1)");
+        const int mc = g->m[d] >> (L - 1);
+        if (mc < 4 || mc / r < 2)
+            return fail(c, NGF_E_SHAPE, "coarsest level needs >= 4 cells and >= 2 node cells");
+        N *= g->m[d];
+    }
+    if (N >= (static_cast<int64_t>(1) << 31)) return fail(c, NGF_E_SHAPE, "image too large");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_pyramid(c);
+    c->lb_level = -1;
+    c->lv.resize(L);
+    for (int l = 0; l < L; ++l) {
+        Level& lv = c->lv[l];
+        for (int d = 0; d < 3; ++d) {
+            lv.m[d] = g->m[d] >> l;
+            lv.h[d] = g->h[d] * static_cast<double>(1 << l);
+            lv.my[d] = lv.m[d] / r + 1;
+            lv.hy[d] = lv.m[d] * lv.h[d] / (lv.my[d] - 1);
+        }
+        const size_t n = static_cast<size_t>(lv.N());
+        if (dalloc(c, &lv.R, n) != NGF_OK || dalloc(c, &lv.T, n) != NGF_OK) return NGF_E_OOM;
+        c->owned.push_back(lv.R);
+        c->owned.push_back(lv.T);
+        for (int d = 0; d < 3; ++d) {
+            if (dalloc(c, &lv.j0[d], lv.m[d]) != NGF_OK || dalloc(c, &lv.w0[d], lv.m[d]) != NGF_OK ||
+                dalloc(c, &lv.w1[d], lv.m[d]) != NGF_OK)
+                return NGF_E_OOM;
+            c->owned.push_back(lv.j0[d]);
+            c->owned.push_back(lv.w0[d]);
+            c->owned.push_back(lv.w1[d]);
+        }
+    }
+    if (ensure_scratch(c, c->lv[0]) != NGF_OK) return NGF_E_OOM;
+    if (ensure_lbfgs(c, static_cast<size_t>(3 * c->lv[0].Ny())) != NGF_OK) return NGF_E_OOM;
+
+    // R on side stream 0, T on side stream 1, each: copy level 0, then the
+    // successive 2x2x2 means; both join the context stream.
+    const size_t bytes0 = static_cast<size_t>(c->lv[0].N()) * sizeof(float);
+    HIPCHK(c, hipEventRecord(c->join[0], c->stream));
+    for (int k = 0; k < 2; ++k) {
+        hipStream_t s = c->side[k];
+        HIPCHK(c, hipStreamWaitEvent(s, c->join[0], 0));
+        const float* src = k == 0 ? R : T;
+        float* dst0 = k == 0 ? c->lv[0].R : c->lv[0].T;
+        HIPCHK(c, hipMemcpyAsync(dst0, src, bytes0,
+                                 host_ptrs ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+        for (int l = 1; l < L; ++l) {
+            const Level& a = c->lv[l - 1];
+            float* out = k == 0 ? c->lv[l].R : c->lv[l].T;
+            launch_downsample(k == 0 ? a.R : a.T, out, a.m[0], a.m[1], a.m[2], s);
+        }
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipEventRecord(c->join[1 + k], s));
+    }
+    for (int l = 0; l < L; ++l)
+        for (int d = 0; d < 3; ++d)
+            launch_index_map(c->lv[l].j0[d], c->lv[l].w0[d], c->lv[l].w1[d], c->lv[l].m[d],
+                             c->lv[l].my[d], c->stream);
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->join[1], 0));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->join[2], 0));
+    // reject non-finite inputs
+    int zero = 0;
+    HIPCHK(c, hipMemcpyAsync(c->dflag, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    launch_check_finite(c->lv[0].R, c->lv[0].N(), c->dflag, c->stream);
+    launch_check_finite(c->lv[0].T, c->lv[0].N(), c->dflag, c->stream);
+    int bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bad) {
+        free_pyramid(c);
+        return fail(c, NGF_E_NONFINITE, "R or T holds NaN or infinity");
+    }
+    return NGF_OK;
+}
+
+ngf_status ngf_level_info(const ngf_ctx* c, int32_t level, ngf_grid* img, ngf_grid* def) {
+    if (!c) return NGF_E_ARG;
+    const ngf_status s = check_level(c, level);
+    if (s != NGF_OK) return s;
+    const Level& L = c->lv[level];
+    for (int d = 0; d < 3; ++d) {
+        if (img) {
+            img->m[d] = L.m[d];
+            img->h[d] = L.h[d];
+        }
+        if (def) {
+            def->m[d] = L.my[d];
+            def->h[d] = L.hy[d];
+        }
+    }
+    return NGF_OK;
+}
+
+ngf_status ngf_level_images(ngf_ctx* c, int32_t level, float* R_out, float* T_out) {
+    if (!c) return NGF_E_ARG;
+    const ngf_status s = check_level(c, level);
+    if (s != NGF_OK) return fail(c, s, "no pyramid or bad level");
+    const Level& L = c->lv[level];
+    const size_t b = static_cast<size_t>(L.N()) * sizeof(float);
+    if (R_out) HIPCHK(c, hipMemcpyAsync(R_out, L.R, b, hipMemcpyDeviceToDevice, c->stream));
+    if (T_out) HIPCHK(c, hipMemcpyAsync(T_out, L.T, b, hipMemcpyDeviceToDevice, c->stream));
+    return NGF_OK;
+}
+
+ngf_status ngf_index_map(ngf_ctx* c, int32_t level, int32_t axis, int32_t* j0, float* w0,
+                         float* w1) {
+    if (!c) return NGF_E_ARG;
+    const ngf_status s = check_level(c, level);
+    if (s != NGF_OK) return fail(c, s, "no pyramid or bad level");
+    if (axis < 0 || axis > 2 || !j0 || !w0 || !w1) return fail(c, NGF_E_ARG, "bad axis or null");
+    const Level& L = c->lv[level];
+    const size_t m = static_cast<size_t>(L.m[axis]);
+    HIPCHK(c, hipMemcpyAsync(j0, L.j0[axis], m * 4, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(w0, L.w0[axis], m * 4, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(w1, L.w1[axis], m * 4, hipMemcpyDeviceToDevice, c->stream));
+    return NGF_OK;
+}
+
+ngf_status ngf_identity(ngf_ctx* c, int32_t level, float* y) {
+    if (!c) return NGF_E_ARG;
+    const ngf_status s = check_level(c, level);
+    if (s != NGF_OK) return fail(c, s, "no pyramid or bad level");
+    if (!y) return fail(c, NGF_E_ARG, "null y");
+    const Level& L = c->lv[level];
+    launch_identity(y, L.my[0], L.my[1], L.my[2], L.hy[0], L.hy[1], L.hy[2], c->stream);
+    HIPCHK(c, hipGetLastError());
+    return NGF_OK;
+}
+
+ngf_status ngf_eval_J_grad(ngf_ctx* c, int32_t level, const float* y, double* J, float* grad,
+                           double* DS) {
+    if (!c) return NGF_E_ARG;
+    const ngf_status s = check_level(c, level);
+    if (s != NGF_OK) return fail(c, s, "no pyramid or bad level");
+    if (!y) return fail(c, NGF_E_ARG, "null y");
+    const Level& L = c->lv[level];
+    ngf_status e = enqueue_eval(c, L, L.R, L.T, y, grad);
+    if (e != NGF_OK) return e;
+    if (J || DS) {
+        if (read_jds(c) != NGF_OK) return NGF_E_HIP;
+        if (J) *J = c->host_jds[0];
+        if (DS) {
+            DS[0] = c->host_jds[1];
+            DS[1] = c->host_jds[2];
+        }
+        if (!std::isfinite(c->host_jds[0])) return fail(c, NGF_E_NONFINITE, "J is not finite");
+    }
+    return NGF_OK;
+}
+
+ngf_status ngf_eval_J_device(ngf_ctx* c, const double** JDS) {
+    if (!c || !JDS) return NGF_E_ARG;
+    *JDS = c->jds;
+    return NGF_OK;
+}
+
+ngf_status ngf_lbfgs_reset(ngf_ctx* c, int32_t level, const float* y0) {
+    if (!c) return NGF_E_ARG;
+    const ngf_status s = check_level(c, level);
+    if (s != NGF_OK) return fail(c, s, "no pyramid or bad level");
+    if (!y0) return fail(c, NGF_E_ARG, "null y0");
+    const Level& L = c->lv[level];
+    const size_t n = static_cast<size_t>(3 * L.Ny());
+    if (y0 != c->ly)
+        HIPCHK(c, hipMemcpyAsync(c->ly, y0, n * sizeof(float), hipMemcpyDeviceToDevice,
+                                 c->stream));
+    ngf_status e = enqueue_eval(c, L, L.R, L.T, c->ly, c->lg);
+    if (e != NGF_OK) return e;
+    const double hmin = std::min(L.h[0], std::min(L.h[1], L.h[2]));
+    launch_lb_init(c->st, c->p.lbfgs_mem, hmin, c->jds, c->stream);
+    HIPCHK(c, hipGetLastError());
+    if (read_jds(c) != NGF_OK) return NGF_E_HIP;
+    c->lb_level = level;
+    c->lb_J = c->host_jds[0];
+    c->lb_gmax = c->host_jds[3];
+    c->lb_evals = 1;
+    if (!std::isfinite(c->lb_J)) return fail(c, NGF_E_NONFINITE, "J(y0) is not finite");
+    return NGF_OK;
+}
+
+ngf_status ngf_lbfgs_step(ngf_ctx* c, double* J, int32_t* info) {
+    if (!c) return NGF_E_ARG;
+    if (c->lb_level < 0 || c->lb_level >= static_cast<int>(c->lv.size()))
+        return fail(c, NGF_E_STATE, "ngf_lbfgs_reset first");
+    const Level& L = c->lv[c->lb_level];
+    const int64_t n = 3 * L.Ny();
+    int32_t inf = NGF_INFO_OK;
+    if (!std::isfinite(c->lb_gmax)) {
+        inf = NGF_INFO_NONFINITE;
+    } else if (c->lb_gmax == 0.0) {
+        inf = NGF_INFO_CONVERGED;
+    } else {
+        launch_lb_solve(c->st, c->stream);
+        launch_lb_combine(c->st, c->hist, n, c->ly, c->lg, c->ld, c->lyt, c->stream);
+        HIPCHK(c, hipGetLastError());
+        const double c1 = 1e-4;
+        double t = 1.0, gtd = 0.0;
+        bool ok = false;
+        for (int h = 0; h <= 10; ++h) {
+            if (h > 0)
+                launch_lb_axpy(c->ly, c->ld, static_cast<float>(t), c->lyt, n, c->stream);
+            ngf_status e = enqueue_eval(c, L, L.R, L.T, c->lyt, c->lgt);
+            if (e != NGF_OK) return e;
+            c->lb_evals++;
+            HIPCHK(c, hipMemcpyAsync(c->host_st, c->st, 8 * sizeof(double),
+                                     hipMemcpyDeviceToHost, c->stream));
+            if (read_jds(c) != NGF_OK) return NGF_E_HIP;
+            if (h == 0) gtd = c->host_st->gtd;
+            const double Jt = c->host_jds[0];
+            if (std::isfinite(Jt) && Jt <= c->lb_J + c1 * t * gtd) {
+                ok = true;
+                break;
+            }
+            t *= 0.5;
+        }
+        if (!ok) {
+            inf = NGF_INFO_LINESEARCH_FAIL;
+        } else {
+            const int nb = lb_dot_blocks(n);
+            launch_lb_update_dots(c->st, c->hist, n, c->ly, c->lyt, c->lg, c->lgt, c->dotpart,
+                                  nb, c->stream);
+            launch_lb_gram_update(c->st, c->dotpart, nb, c->jds, c->stream);
+            HIPCHK(c, hipGetLastError());
+            std::swap(c->ly, c->lyt);
+            std::swap(c->lg, c->lgt);
+            c->lb_J = c->host_jds[0];
+            c->lb_gmax = c->host_jds[3];
+        }
+    }
+    if (J) *J = c->lb_J;
+    if (info) *info = inf;
+    return NGF_OK;
+}
+
+ngf_status ngf_lbfgs_get(ngf_ctx* c, float* y, float* grad, double* J) {
+    if (!c) return NGF_E_ARG;
+    if (c->lb_level < 0) return fail(c, NGF_E_STATE, "ngf_lbfgs_reset first");
+    const size_t n = static_cast<size_t>(3 * c->lv[c->lb_level].Ny());
+    if (y) HIPCHK(c, hipMemcpyAsync(y, c->ly, n * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (grad) HIPCHK(c, hipMemcpyAsync(grad, c->lg, n * 4, hipMemcpyDeviceToDevice, c->stream));
+    if (J) *J = c->lb_J;
+    return NGF_OK;
+}
+
+ngf_status ngf_prolongate(ngf_ctx* c, int32_t coarse_level, const float* y_c, float* y_f) {
+    if (!c) return NGF_E_ARG;
+    const ngf_status s = check_level(c, coarse_level);
+    if (s != NGF_OK) return fail(c, s, "no pyramid or bad level");
+    if (coarse_level == 0) return fail(c, NGF_E_LEVEL, "level 0 has no finer level");
+    if (!y_c || !y_f) return fail(c, NGF_E_ARG, "null pointer");
+    const Level& C = c->lv[coarse_level];
+    const Level& F = c->lv[coarse_level - 1];
+    for (int d = 0; d < 3; ++d)
+        if (F.my[d] - 1 != 2 * (C.my[d] - 1))
+            return fail(c, NGF_E_SHAPE, "grids are not 2:1 aligned");
+    launch_prolongate(y_c, y_f, C.my[0], C.my[1], C.my[2], c->stream);
+    HIPCHK(c, hipGetLastError());
+    return NGF_OK;
+}
+
+ngf_status ngf_register_levels(ngf_ctx* c, float* y_out, ngf_report* rep) {
+    if (!c) return NGF_E_ARG;
+    if (c->lv.empty()) return fail(c, NGF_E_STATE, "no pyramid");
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->levels = static_cast<int32_t>(c->lv.size());
+    }
+    const int L = static_cast<int>(c->lv.size());
+    for (int lev = L - 1; lev >= 0; --lev) {
+        const Level& lv = c->lv[lev];
+        if (lev == L - 1) {
+            launch_identity(c->ltmp, lv.my[0], lv.my[1], lv.my[2], lv.hy[0], lv.hy[1], lv.hy[2],
+                            c->stream);
+        } else {
+            const Level& C = c->lv[lev + 1];
+            launch_prolongate(c->ly, c->ltmp, C.my[0], C.my[1], C.my[2], c->stream);
+        }
+        HIPCHK(c, hipGetLastError());
+        ngf_status e = ngf_lbfgs_reset(c, lev, c->ltmp);
+        if (e != NGF_OK) return e;
+        int it = 0;
+        int32_t info = NGF_INFO_MAX_ITER;
+        while (it < c->p.max_iter) {
+            const double J_old = c->lb_J;
+            int32_t inf = 0;
+            double Jn = 0.0;
+            e = ngf_lbfgs_step(c, &Jn, &inf);
+            if (e != NGF_OK) return e;
+            if (inf != NGF_INFO_OK) {
+                info = inf;
+                break;
+            }
+            ++it;
+            if (c->p.early_stop && (J_old - Jn) <= c->p.tol_J * (1.0 + std::fabs(J_old))) {
+                info = NGF_INFO_CONVERGED;
+                break;
+            }
+        }
+        if (rep) {
+            rep->iters[lev] = it;
+            rep->evals[lev] = c->lb_evals;
+            rep->J[lev] = c->lb_J;
+            rep->info[lev] = info;
+        }
+    }
+    if (y_out) {
+        const size_t n = static_cast<size_t>(3 * c->lv[0].Ny());
+        HIPCHK(c, hipMemcpyAsync(y_out, c->ly, n * 4, hipMemcpyDeviceToDevice, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NGF_OK;
+}
+
+ngf_status ngf_register(ngf_ctx* c, const float* R, const float* T, const ngf_grid* g,
+                        float* y_out, int32_t host_ptrs, ngf_report* rep) {
+    if (!c) return NGF_E_ARG;
+    ngf_status e = ngf_build_pyramid(c, R, T, g, host_ptrs);
+    if (e != NGF_OK) return e;
+    if (!host_ptrs) return ngf_register_levels(c, y_out, rep);
+    e = ngf_register_levels(c, nullptr, rep);
+    if (e != NGF_OK) return e;
+    if (y_out) {
+        const size_t n = static_cast<size_t>(3 * c->lv[0].Ny());
+        HIPCHK(c, hipMemcpyAsync(y_out, c->ly, n * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return NGF_OK;
+}
+
+ngf_status ngf_set_profiling(ngf_ctx* c, int32_t enable) {
+    if (!c) return NGF_E_ARG;
+    if (enable && c->ev.empty()) {
+        c->ev.resize(2 * kProfMax, nullptr);
+        for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
+    }
+    c->prof = enable != 0;
+    c->nprof = 0;
+    c->prof_vox = 0;
+    c->prof_nodes = 0;
+    return NGF_OK;
+}
+
+ngf_status ngf_kernel_time(ngf_ctx* c, int32_t* launches, double* total_ms, int64_t* voxels,
+                           int64_t* nodes) {
+    if (!c) return NGF_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (int i = 0; i < c->nprof; ++i) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+        tot += ms;
+    }
+    if (launches) *launches = c->nprof;
+    if (total_ms) *total_ms = tot;
+    if (voxels) *voxels = c->prof_vox;
+    if (nodes) *nodes = c->prof_nodes;
+    c->nprof = 0;
+    c->prof_vox = 0;
+    c->prof_nodes = 0;
+    return NGF_OK;
+}
+
+ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], const float* R,
+                         const float* T, const float* y, double* J, float* grad_y,
+                         float* grad_T) {
+    (void)g;
+    (void)my;
+    (void)R;
+    (void)T;
+    (void)y;
+    (void)J;
+    (void)grad_y;
+    (void)grad_T;
+    return fail(c, NGF_E_STATE, "ngf_eval_pair is not built yet");
+}
+
+}  // extern "C"

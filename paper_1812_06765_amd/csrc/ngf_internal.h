@@ -1,0 +1,130 @@
+// Internal declarations shared by the HIP kernels and the host side of the
+// library.  Not part of the public ABI (include/ngfreg.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ngf {
+
+constexpr int kThreads = 256;      // threads per workgroup (four wave64s)
+constexpr int kMaxMem = 8;         // largest L-BFGS memory
+constexpr int kSlots = kMaxMem + 1;             // ring slots (one spare)
+constexpr int kBasis = 2 * kSlots + 1;          // s slots, t slots, gradient
+constexpr int kBasisG = 2 * kSlots;             // basis index of the gradient
+
+// Image-pass tile (voxels per axis).  Tiles are aligned to the deformation
+// grid: each extent is a multiple of the grid ratio.
+constexpr int kTX = 8, kTY = 8, kTZ = 32;
+// Node-pass tile (nodes per axis).
+constexpr int kNX = 4, kNY = 8, kNZ = 32;
+
+// One pyramid level as the kernels see it.
+struct LevelView {
+    int m[3];          // image cells
+    int my[3];         // deformation nodes
+    double h[3];       // image spacing
+    double hy[3];      // node spacing
+    const float* R;
+    const float* T;
+    const int32_t* j0[3];  // index maps (per axis, m entries)
+    const float* w0[3];
+    const float* w1[3];
+};
+
+struct ImagePassArgs {
+    const float* R;
+    const float* T;
+    const float* y;        // [3][my]
+    const int32_t* j0x; const int32_t* j0y; const int32_t* j0z;
+    const float* w0x; const float* w0y; const float* w0z;
+    const float* w1x; const float* w1y; const float* w1z;
+    float* part;           // P^T partial sums per tile, [tile][3][(BX+1)(BY+1)(BZ+1)]
+    double* dpart;         // sum over the tile of (1 - r^2), one per tile
+    int mx, my, mz;        // image cells
+    int nx, ny, nz;        // deformation nodes
+    int ntx, nty, ntz;     // tiles per axis
+    double hx, hy, hz;     // spacing (float64: continuous index of the warp)
+    float fihx, fihy, fihz;        // 1 / h in float32
+    float i2hx, i2hy, i2hz;        // 1 / (2 h)
+    float tau, rho;
+    float hbar;            // h_x h_y h_z
+    int want_grad;         // 0: value only
+};
+
+struct NodePassArgs {
+    const float* y;        // [3][my]
+    const float* part;     // image-pass partial sums
+    float* grad;           // [3][my] output (may be null when want_grad == 0)
+    double* spart;         // per block: sum of (A u)^2
+    double* gpart;         // per block: [0] max |grad|, [1] sum grad^2
+    int nx, ny, nz;
+    int ntx, nty, ntz;     // image-pass tiles per axis
+    int bx, by, bz;        // node cells per image tile per axis
+    int nbx, nby, nbz;     // node-pass blocks per axis
+    double hyx, hyy, hyz;  // node spacing (float64, for X = j h^y)
+    float ihy2x, ihy2y, ihy2z;  // 1 / (h^y)^2
+    float alpha_hbary;     // alpha * hbar^y
+    float alpha;
+    int want_grad;
+};
+
+struct ReduceArgs {
+    const double* dpart; int nd;
+    const double* spart; int ns;
+    const double* gpart; int ng;   // pairs (max, sumsq); ng == 0: skip
+    double half_hbar, half_hbary, alpha;
+    double* out;                    // {J, D, S, max|g|, |g|^2}
+};
+
+// L-BFGS device state; lives in device memory, read and written by the
+// vector kernels and the single-thread solver.
+struct LbState {
+    // read back by the host after every trial evaluation (first 8 doubles):
+    double J, D, S, gmax, gnorm2;   // copy of the last evaluation
+    double gtd;                     // g^T d of the current direction
+    double flags;                   // bit 0: memory reset, bit 1: zero gradient
+    double count_d;                 // stored pairs (as double, for the host)
+    // device-only:
+    int count;
+    int order[kSlots];              // slots of stored pairs, oldest first
+    int free_slot;
+    int mem;
+    double hmin;
+    double G[kBasis * kBasis];      // inner products of the basis vectors
+    double coef[kBasis];            // direction coefficients over the basis
+};
+
+// kernels (definitions in the .hip files), launched from the host code
+void launch_downsample(const float* src, float* dst, int mx, int my, int mz, hipStream_t s);
+void launch_index_map(int32_t* j0, float* w0, float* w1, int m, int my, hipStream_t s);
+void launch_identity(float* y, int nx, int ny, int nz, double hx, double hy, double hz,
+                     hipStream_t s);
+void launch_prolongate(const float* yc, float* yf, int cx, int cy, int cz, hipStream_t s);
+void launch_image_pass(const ImagePassArgs& a, int ratio, hipStream_t s);
+void launch_node_pass(const NodePassArgs& a, hipStream_t s);
+void launch_reduce(const ReduceArgs& a, hipStream_t s);
+void launch_check_finite(const float* v, int64_t n, int* flag, hipStream_t s);
+
+// L-BFGS vector kernels
+void launch_lb_solve(LbState* st, hipStream_t s);
+void launch_lb_combine(LbState* st, const float* hist, int64_t n, const float* y,
+                       const float* g, float* d, float* yt, hipStream_t s);
+void launch_lb_axpy(const float* y, const float* d, float t, float* yt, int64_t n,
+                    hipStream_t s);
+void launch_lb_update_dots(LbState* st, float* hist, int64_t n, const float* y,
+                           const float* yt, const float* g, const float* gt,
+                           double* dotpart, int nblocks, hipStream_t s);
+void launch_lb_gram_update(LbState* st, const double* dotpart, int nblocks,
+                           const double* jds, hipStream_t s);
+void launch_lb_init(LbState* st, int mem, double hmin, const double* jds, hipStream_t s);
+int lb_dot_blocks(int64_t n);
+
+// autograd form (scatter adjoints)
+void launch_pair_pass(const ImagePassArgs& a, float* gy_img, float* gT, hipStream_t s);
+void launch_scatter_PT(const float* dimg, float* gy, int mx, int my, int mz, int nx, int ny,
+                       int nz, const int32_t* j0x, const int32_t* j0y, const int32_t* j0z,
+                       const float* w0x, const float* w0y, const float* w0z,
+                       const float* w1x, const float* w1y, const float* w1z, hipStream_t s);
+
+}  // namespace ngf

@@ -1,0 +1,330 @@
+"""Python binding of the C ABI in ``include/ngfreg.h`` (argument marshalling only).
+
+Every computation runs in the HIP library ``libngfreg.so`` built from
+``csrc/``; this module only checks tensor shapes, dtypes and devices, passes
+raw device pointers and the current HIP stream, and turns status codes into
+exceptions.  There is no fallback: if the library is missing or no GPU is
+visible, the calls raise.
+
+Method names follow the C ABI without the ``ngf_`` prefix.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libngfreg.so")
+
+OK, E_ARG, E_SHAPE, E_STATE, E_LEVEL, E_OOM, E_HIP, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
+INFO_OK, INFO_CONVERGED, INFO_MAX_ITER, INFO_LINESEARCH_FAIL, INFO_NONFINITE = 0, 1, 2, 3, 4
+MAX_LEVELS = 12
+STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_SHAPE", -3: "E_STATE", -4: "E_LEVEL",
+                -5: "E_OOM", -6: "E_HIP", -7: "E_NONFINITE"}
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("tau", ctypes.c_double), ("rho", ctypes.c_double),
+                ("levels", ctypes.c_int32), ("ratio", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("lbfgs_mem", ctypes.c_int32),
+                ("tol_J", ctypes.c_double), ("early_stop", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("iters", ctypes.c_int32 * MAX_LEVELS),
+                ("evals", ctypes.c_int32 * MAX_LEVELS), ("info", ctypes.c_int32 * MAX_LEVELS),
+                ("J", ctypes.c_double * MAX_LEVELS)]
+
+
+class NgfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def load():
+    """Load libngfreg.so (after torch, so that it binds to torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1812_06765_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, f64 = ctypes.c_int32, ctypes.c_double
+    sig = {
+        "ngf_version": ([], ctypes.c_char_p),
+        "ngf_create": ([ctypes.POINTER(Params), _P, ctypes.POINTER(_P)], i32),
+        "ngf_destroy": ([_P], None),
+        "ngf_last_error": ([_P], ctypes.c_char_p),
+        "ngf_set_params": ([_P, ctypes.POINTER(Params)], i32),
+        "ngf_build_pyramid": ([_P, _P, _P, ctypes.POINTER(Grid), i32], i32),
+        "ngf_level_info": ([_P, i32, ctypes.POINTER(Grid), ctypes.POINTER(Grid)], i32),
+        "ngf_level_images": ([_P, i32, _P, _P], i32),
+        "ngf_index_map": ([_P, i32, i32, _P, _P, _P], i32),
+        "ngf_identity": ([_P, i32, _P], i32),
+        "ngf_eval_J_grad": ([_P, i32, _P, ctypes.POINTER(f64), _P, ctypes.POINTER(f64)], i32),
+        "ngf_eval_J_device": ([_P, ctypes.POINTER(_P)], i32),
+        "ngf_lbfgs_reset": ([_P, i32, _P], i32),
+        "ngf_lbfgs_step": ([_P, ctypes.POINTER(f64), ctypes.POINTER(i32)], i32),
+        "ngf_lbfgs_get": ([_P, _P, _P, ctypes.POINTER(f64)], i32),
+        "ngf_prolongate": ([_P, i32, _P, _P], i32),
+        "ngf_register": ([_P, _P, _P, ctypes.POINTER(Grid), _P, i32, ctypes.POINTER(Report)], i32),
+        "ngf_register_levels": ([_P, _P, ctypes.POINTER(Report)], i32),
+        "ngf_eval_pair": ([_P, ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_int32 * 3), _P, _P,
+                           _P, ctypes.POINTER(f64), _P, _P], i32),
+        "ngf_set_profiling": ([_P, i32], i32),
+        "ngf_kernel_time": ([_P, ctypes.POINTER(i32), ctypes.POINTER(f64),
+                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+                            i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _grid(m, h) -> Grid:
+    g = Grid()
+    for d in range(3):
+        g.m[d] = int(m[d])
+        g.h[d] = float(h[d])
+    return g
+
+
+@dataclass
+class LevelInfo:
+    m: tuple
+    h: tuple
+    my: tuple
+    hy: tuple
+
+
+class Context:
+    """An ngf_ctx bound to the current torch HIP stream of ``device``."""
+
+    def __init__(self, alpha=0.1, tau=1.0, rho=1.0, levels=1, ratio=2, max_iter=50,
+                 lbfgs_mem=5, tol_J=1e-6, early_stop=False, device="cuda"):
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the ngf library has no CPU path")
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.p = Params(float(alpha), float(tau), float(rho), int(levels), int(ratio),
+                        int(max_iter), int(lbfgs_mem), float(tol_J), int(bool(early_stop)), 0)
+        h = _P()
+        st = self.lib.ngf_create(ctypes.byref(self.p), ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(h))
+        if st != OK:
+            raise NgfError(st, "ngf_create failed")
+        self.h = h
+        self.levels = int(levels)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ngf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, st):
+        if st != OK:
+            msg = self.lib.ngf_last_error(self.h).decode()
+            raise NgfError(st, msg)
+
+    def _f32(self, t, shape=None, name="tensor"):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float32 and t.is_cuda
+                and t.is_contiguous()):
+            raise TypeError(f"{name} must be a contiguous float32 tensor on the GPU")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        return t
+
+    # -- parameters -------------------------------------------------------
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            setattr(self.p, k, type(getattr(self.p, k))(v))
+        self._chk(self.lib.ngf_set_params(self.h, ctypes.byref(self.p)))
+
+    # -- pyramid -----------------------------------------------------------
+    def build_pyramid(self, R, T, h=(1.0, 1.0, 1.0)):
+        host = not R.is_cuda
+        if host:
+            R = R.detach().to(torch.float32).contiguous()
+            T = T.detach().to(torch.float32).contiguous()
+        else:
+            self._f32(R, name="R")
+            self._f32(T, R.shape, name="T")
+        if tuple(R.shape) != tuple(T.shape) or R.dim() != 3:
+            raise ValueError("R and T must be 3D arrays of one shape")
+        g = _grid(R.shape, h)
+        self._chk(self.lib.ngf_build_pyramid(self.h, _ptr(R), _ptr(T), ctypes.byref(g),
+                                             int(host)))
+
+    def level_info(self, level) -> LevelInfo:
+        gi, gd = Grid(), Grid()
+        self._chk(self.lib.ngf_level_info(self.h, int(level), ctypes.byref(gi), ctypes.byref(gd)))
+        return LevelInfo(tuple(gi.m), tuple(gi.h), tuple(gd.m), tuple(gd.h))
+
+    def level_images(self, level):
+        li = self.level_info(level)
+        R = torch.empty(li.m, dtype=torch.float32, device=self.device)
+        T = torch.empty(li.m, dtype=torch.float32, device=self.device)
+        self._chk(self.lib.ngf_level_images(self.h, int(level), _ptr(R), _ptr(T)))
+        return R, T
+
+    def index_map(self, level, axis):
+        m = self.level_info(level).m[axis]
+        j0 = torch.empty(m, dtype=torch.int32, device=self.device)
+        w0 = torch.empty(m, dtype=torch.float32, device=self.device)
+        w1 = torch.empty(m, dtype=torch.float32, device=self.device)
+        self._chk(self.lib.ngf_index_map(self.h, int(level), int(axis), _ptr(j0), _ptr(w0),
+                                         _ptr(w1)))
+        return j0, w0, w1
+
+    def identity(self, level):
+        li = self.level_info(level)
+        y = torch.empty((3,) + li.my, dtype=torch.float32, device=self.device)
+        self._chk(self.lib.ngf_identity(self.h, int(level), _ptr(y)))
+        return y
+
+    # -- evaluation --------------------------------------------------------
+    def eval_J_grad(self, level, y, want_grad=True, out=None):
+        """Returns (J, grad or None, (D, S)); J and (D, S) are Python floats."""
+        li = self.level_info(level)
+        self._f32(y, (3,) + li.my, "y")
+        g = None
+        if want_grad:
+            g = out if out is not None else torch.empty_like(y)
+            self._f32(g, y.shape, "grad")
+        J = ctypes.c_double()
+        DS = (ctypes.c_double * 2)()
+        self._chk(self.lib.ngf_eval_J_grad(self.h, int(level), _ptr(y), ctypes.byref(J), _ptr(g),
+                                           DS))
+        return J.value, g, (DS[0], DS[1])
+
+    def eval_J_grad_async(self, level, y, grad):
+        """Enqueue an evaluation without synchronising (J stays on the device)."""
+        self._chk(self.lib.ngf_eval_J_grad(self.h, int(level), _ptr(y), None, _ptr(grad), None))
+
+    # -- L-BFGS ------------------------------------------------------------
+    def lbfgs_reset(self, level, y0):
+        self._f32(y0, (3,) + self.level_info(level).my, "y0")
+        self._chk(self.lib.ngf_lbfgs_reset(self.h, int(level), _ptr(y0)))
+
+    def lbfgs_step(self):
+        J = ctypes.c_double()
+        info = ctypes.c_int32()
+        self._chk(self.lib.ngf_lbfgs_step(self.h, ctypes.byref(J), ctypes.byref(info)))
+        return J.value, info.value
+
+    def lbfgs_get(self, level):
+        my = self.level_info(level).my
+        y = torch.empty((3,) + my, dtype=torch.float32, device=self.device)
+        g = torch.empty_like(y)
+        J = ctypes.c_double()
+        self._chk(self.lib.ngf_lbfgs_get(self.h, _ptr(y), _ptr(g), ctypes.byref(J)))
+        return y, g, J.value
+
+    def prolongate(self, coarse_level, yc):
+        fine = self.level_info(coarse_level - 1).my
+        yf = torch.empty((3,) + fine, dtype=torch.float32, device=self.device)
+        self._chk(self.lib.ngf_prolongate(self.h, int(coarse_level), _ptr(yc), _ptr(yf)))
+        return yf
+
+    # -- registration --------------------------------------------------------
+    @staticmethod
+    def _report(rep: Report):
+        return [dict(level=lev, iters=rep.iters[lev], evals=rep.evals[lev], J=rep.J[lev],
+                     info=rep.info[lev]) for lev in range(rep.levels)]
+
+    def register(self, R, T, h=(1.0, 1.0, 1.0)):
+        """Full registration from R, T (device tensors, or CPU tensors for the
+        host-pointer path).  Returns (y at level 0, per-level report)."""
+        host = not R.is_cuda
+        if host:
+            R = R.detach().to(torch.float32).contiguous()
+            T = T.detach().to(torch.float32).contiguous()
+        else:
+            self._f32(R, name="R")
+            self._f32(T, R.shape, name="T")
+        g = _grid(R.shape, h)
+        my = tuple(int(R.shape[d]) // self.p.ratio + 1 for d in range(3))
+        y = torch.empty((3,) + my, dtype=torch.float32,
+                        device="cpu" if host else self.device)
+        if host:
+            y = y.pin_memory()
+        rep = Report()
+        self._chk(self.lib.ngf_register(self.h, _ptr(R), _ptr(T), ctypes.byref(g), _ptr(y),
+                                        int(host), ctypes.byref(rep)))
+        return y, self._report(rep)
+
+    def register_levels(self, out=None):
+        my = self.level_info(0).my
+        y = out if out is not None else torch.empty((3,) + my, dtype=torch.float32,
+                                                    device=self.device)
+        rep = Report()
+        self._chk(self.lib.ngf_register_levels(self.h, _ptr(y), ctypes.byref(rep)))
+        return y, self._report(rep)
+
+    # -- differentiation form -------------------------------------------------
+    def eval_pair(self, R, T, y, h=(1.0, 1.0, 1.0), grad_y=True, grad_T=True):
+        """J and gradients with respect to y and T on an explicit pair."""
+        self._f32(R, name="R")
+        self._f32(T, R.shape, name="T")
+        my = tuple(int(R.shape[d]) // self.p.ratio + 1 for d in range(3))
+        self._f32(y, (3,) + my, "y")
+        g = _grid(R.shape, h)
+        myc = (ctypes.c_int32 * 3)(*my)
+        gy = torch.empty_like(y) if grad_y else None
+        gT = torch.empty_like(T) if grad_T else None
+        J = ctypes.c_double()
+        self._chk(self.lib.ngf_eval_pair(self.h, ctypes.byref(g), ctypes.byref(myc), _ptr(R),
+                                         _ptr(T), _ptr(y), ctypes.byref(J), _ptr(gy), _ptr(gT)))
+        return J.value, gy, gT
+
+    # -- profiling -----------------------------------------------------------
+    def set_profiling(self, enable=True):
+        self._chk(self.lib.ngf_set_profiling(self.h, int(bool(enable))))
+
+    def kernel_time(self):
+        """(launches, total ms, voxels, nodes) of the recorded image-pass launches."""
+        n = ctypes.c_int32()
+        ms = ctypes.c_double()
+        vox = ctypes.c_int64()
+        nod = ctypes.c_int64()
+        self._chk(self.lib.ngf_kernel_time(self.h, ctypes.byref(n), ctypes.byref(ms),
+                                           ctypes.byref(vox), ctypes.byref(nod)))
+        return n.value, ms.value, vox.value, nod.value
+
+
+def version() -> str:
+    return load().ngf_version().decode()

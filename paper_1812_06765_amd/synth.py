@@ -129,7 +129,7 @@ class BSplineField:
             self._basis(d, np.arange(self.m[d], dtype=np.float64) + 0.5) for d in range(3)
         )
         out = np.einsum("cijk,xi,yj,zk->cxyz", self.coef, bx, by, bz, optimize=True)
-        return self.scale * out
+        return np.ascontiguousarray(self.scale * out)
 
     def __call__(self, p: np.ndarray) -> np.ndarray:
         shp = p.shape[1:]
@@ -219,7 +219,8 @@ def blob_phantom_pair(m=(32, 32, 32), h=(1.0, 1.0, 1.0), seed_R=1, seed_u=2,
     R = _blob_phantom_value(x, m, blobs) + rng.normal(0.0, noise, size=tuple(m))
     field = SinusoidField(m, max_disp, seed_u)
     T = _blob_phantom_value(x + field(x), m, blobs) + rng.normal(0.0, noise, size=tuple(m))
-    return Pair(R.astype(np.float32), T.astype(np.float32), field, tuple(m), tuple(h),
+    return Pair(np.ascontiguousarray(R, dtype=np.float32),
+                np.ascontiguousarray(T, dtype=np.float32), field, tuple(m), tuple(h),
                 (seed_R, seed_u))
 
 
@@ -254,7 +255,8 @@ def ct_phantom_pair(m=(128, 128, 128), h=(1.0, 1.0, 1.0), seed_R=3, seed_u=4,
     R = ct_phantom_value(x, m) + rng.normal(0.0, noise, size=tuple(m))
     field = BSplineField(m, cp_spacing, max_disp, seed_u)
     T = ct_phantom_value(x + field.on_grid(), m) + rng.normal(0.0, noise, size=tuple(m))
-    return Pair(R.astype(np.float32), T.astype(np.float32), field, tuple(m), tuple(h),
+    return Pair(np.ascontiguousarray(R, dtype=np.float32),
+                np.ascontiguousarray(T, dtype=np.float32), field, tuple(m), tuple(h),
                 (seed_R, seed_u))
 
 

@@ -1,0 +1,67 @@
+"""The C-ABI library loads and exports every symbol the public header declares;
+argument checks that run before any HIP call.  No GPU needed."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ngfreg.h")
+LIB = os.path.join(ROOT, "paper_1812_06765_amd", "libngfreg.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:ngf_status|void|const char\*)\s+(ngf_\w+)\s*\(",
+                                 text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1812_06765_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("ngf_build_pyramid", "ngf_eval_J_grad", "ngf_lbfgs_step", "ngf_register",
+              "ngf_eval_pair"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_argument_checks_without_gpu(lib):
+    lib.ngf_version.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.ngf_version()
+    from paper_1812_06765_amd.ngf import Params, E_ARG
+    lib.ngf_create.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p,
+                               ctypes.POINTER(ctypes.c_void_p)]
+    lib.ngf_create.restype = ctypes.c_int32
+    h = ctypes.c_void_p()
+    good = dict(alpha=0.1, tau=1.0, rho=1.0, levels=3, ratio=2, max_iter=5, lbfgs_mem=5,
+                tol_J=1e-6, early_stop=0, reserved=0)
+    for key, bad in (("alpha", -1.0), ("tau", 0.0), ("rho", float("nan")), ("levels", 0),
+                     ("levels", 13), ("ratio", 3), ("lbfgs_mem", 0), ("lbfgs_mem", 9),
+                     ("max_iter", -1)):
+        p = Params(**{**good, key: bad})
+        assert lib.ngf_create(ctypes.byref(p), None, ctypes.byref(h)) == E_ARG, key
+    assert lib.ngf_create(None, None, ctypes.byref(h)) == E_ARG
+    p = Params(**good)
+    assert lib.ngf_create(ctypes.byref(p), None, None) == E_ARG
+
+
+def test_build_sources_and_flags():
+    from paper_1812_06765_amd import build
+    srcs = [os.path.basename(s) for s in build.sources()]
+    assert {"k_eval.hip", "k_grid.hip", "k_lbfgs.hip", "ngf_api.hip"} <= set(srcs)
+    assert "--offload-arch=gfx950" in build.CFLAGS
+    i = build.CFLAGS.index("-target-feature")
+    assert build.CFLAGS[i + 2] == "-packed-fp32-ops"

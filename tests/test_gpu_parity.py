@@ -1,0 +1,279 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI.
+
+Bars: pyramid, index maps, identity and prolongation bit-exact; J within a
+relative 1e-5 and grad J within a relative L2 error of 1e-4 at the same
+float32 y (widened exactly for the oracle).  Inputs are the seeded phantoms
+at the shapes of the workloads, plus ragged and anisotropic grids that leave
+partial tiles on every axis.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1812_06765_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+J_RTOL = 1e-5
+G_RTOL = 1e-4
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(ngf, **kw):
+    return ngf.Context(**kw)
+
+
+def _y(prob, amp, seed, spacing=8.0):
+    """float32 y = identity + smooth field of peak norm ``amp`` (physical)."""
+    d = synth.smooth_node_perturbation(prob.my, spacing, amp, seed) if amp > 0 else 0.0
+    return (prob.identity() + d).astype(np.float32)
+
+
+def _check_eval(ngf, ctx, level, prob, y32, tag):
+    _say(f"[parity] {tag} level={level} m={prob.m} my={prob.my}")
+    J, g, (D, S) = ctx.eval_J_grad(level, _t(y32))
+    Jo, go, (Do, So) = O.eval_J_grad(prob, y32.astype(np.float64))
+    g = _np(g).astype(np.float64)
+    assert np.all(np.isfinite(g))
+    assert abs(J - Jo) <= J_RTOL * abs(Jo), (tag, J, Jo)
+    assert abs(D - Do) <= J_RTOL * abs(Do) + 1e-12, (tag, D, Do)
+    assert abs(S - So) <= 1e-4 * abs(So) + 1e-9 * abs(Jo), (tag, S, So)
+    err = np.linalg.norm(g - go) / np.linalg.norm(go)
+    assert err <= G_RTOL, (tag, err)
+    # value-only evaluation gives the same J
+    Jv, gv, _ = ctx.eval_J_grad(level, _t(y32), want_grad=False)
+    assert gv is None and Jv == J
+    return J, g
+
+
+def test_index_maps_identity_and_pyramid_bit_exact(gpu_lib):
+    ngf = gpu_lib
+    pr = synth.ct_phantom_pair((64, 48, 32), seed_R=3, seed_u=4)
+    h = (1.0, 1.25, 2.0)
+    for ratio in (2, 4):
+        _say(f"[bitexact] ratio={ratio}")
+        ctx = _ctx(ngf, levels=3, ratio=ratio, tau=10.0, rho=10.0)
+        ctx.build_pyramid(_t(pr.R), _t(pr.T), h)
+        Rs, Ts = O.pyramid(pr.R, pr.T, 3)
+        shapes = O.level_shapes(pr.R.shape, h, 3, ratio)
+        for lev in range(3):
+            R, T = ctx.level_images(lev)
+            assert np.array_equal(_np(R), Rs[lev]) and np.array_equal(_np(T), Ts[lev])
+            li = ctx.level_info(lev)
+            m, hl, my = shapes[lev]
+            assert li.m == m and li.my == my and li.h == hl
+            for ax in range(3):
+                j0, w0, w1 = (_np(v) for v in ctx.index_map(lev, ax))
+                oj, ow0, ow1 = O.index_map_f32(m[ax], my[ax])
+                assert np.array_equal(j0, oj) and np.array_equal(w0, ow0)
+                assert np.array_equal(w1, ow1)
+            X = _np(ctx.identity(lev))
+            assert np.array_equal(X, O.identity(m, hl, my).astype(np.float32))
+        ctx.close()
+
+
+def test_host_pointer_pyramid_equals_device(gpu_lib):
+    import torch
+    ngf = gpu_lib
+    pr = synth.blob_phantom_pair((32, 32, 32))
+    a = _ctx(ngf, levels=2)
+    a.build_pyramid(torch.from_numpy(pr.R), torch.from_numpy(pr.T))
+    b = _ctx(ngf, levels=2)
+    b.build_pyramid(_t(pr.R), _t(pr.T))
+    for lev in range(2):
+        for x, y in zip(a.level_images(lev), b.level_images(lev)):
+            assert torch.equal(x, y)
+
+
+def test_prolongation_bit_exact(gpu_lib):
+    ngf = gpu_lib
+    pr = synth.blob_phantom_pair((32, 48, 64))
+    ctx = _ctx(ngf, levels=3)
+    ctx.build_pyramid(_t(pr.R), _t(pr.T))
+    rng = np.random.default_rng(3)
+    for lev in (2, 1):
+        li = ctx.level_info(lev)
+        yc = (O.identity(li.m, li.h, li.my)
+              + rng.standard_normal((3,) + li.my) * 0.7).astype(np.float32)
+        yf = _np(ctx.prolongate(lev, _t(yc)))
+        assert np.array_equal(yf, O.prolongate(yc.astype(np.float64)).astype(np.float32))
+
+
+def test_eval_parity_blob32(gpu_lib):
+    ngf = gpu_lib
+    pr = synth.blob_phantom_pair((32, 32, 32), seed_R=1, seed_u=2, max_disp=2.0)
+    ctx = _ctx(ngf, alpha=0.1, tau=0.1, rho=0.1, levels=1)
+    ctx.build_pyramid(_t(pr.R), _t(pr.T))
+    prob = O.Problem(pr.R, pr.T, (1.0, 1.0, 1.0), (17, 17, 17), 0.1, 0.1, 0.1)
+    for amp, seed in ((0.0, 0), (1.5, 7), (4.0, 8)):
+        _check_eval(ngf, ctx, 0, prob, _y(prob, amp, seed), f"blob32 amp={amp}")
+    # points pushed far outside the domain (clamped warp, zero slope)
+    y = prob.identity().copy()
+    y[0] *= 1.4
+    y[1] -= 3.0
+    _check_eval(ngf, ctx, 0, prob, y.astype(np.float32), "blob32 outside")
+
+
+def test_eval_parity_ct_pyramid_levels(gpu_lib):
+    ngf = gpu_lib
+    pr = synth.ct_phantom_pair((128, 128, 128), seed_R=3, seed_u=4)
+    ctx = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=3)
+    ctx.build_pyramid(_t(pr.R), _t(pr.T))
+    Rs, Ts = O.pyramid(pr.R, pr.T, 3)
+    for lev, (m, h, my) in enumerate(O.level_shapes(pr.R.shape, (1.0, 1.0, 1.0), 3)):
+        prob = O.Problem(Rs[lev], Ts[lev], h, my, 0.1, 10.0, 10.0)
+        for amp, seed in ((0.0, 0), (2.0 * h[0], 11 + lev)):
+            _check_eval(ngf, ctx, lev, prob, _y(prob, amp, seed), f"ct128 amp={amp}")
+
+
+@pytest.mark.parametrize("m,h,ratio", [((44, 36, 40), (1.0, 1.5, 0.75), 2),
+                                       ((24, 16, 72), (2.0, 1.0, 1.0), 2),
+                                       ((64, 48, 32), (1.0, 1.0, 2.0), 4),
+                                       ((16, 16, 16), (1.0, 1.0, 1.0), 4)])
+def test_eval_parity_ragged_anisotropic(gpu_lib, m, h, ratio):
+    ngf = gpu_lib
+    pr = synth.ct_phantom_pair(m, h, seed_R=21, seed_u=22, max_disp=3.0, cp_spacing=8.0)
+    ctx = _ctx(ngf, alpha=0.05, tau=10.0, rho=10.0, levels=1, ratio=ratio)
+    ctx.build_pyramid(_t(pr.R), _t(pr.T), h)
+    my = tuple(v // ratio + 1 for v in m)
+    prob = O.Problem(pr.R, pr.T, h, my, 0.05, 10.0, 10.0)
+    for amp, seed in ((0.0, 0), (1.5, 31)):
+        _check_eval(ngf, ctx, 0, prob, _y(prob, amp, seed, spacing=4.0), f"ragged {m} r{ratio}")
+
+
+def test_identical_images_give_zero(gpu_lib):
+    ngf = gpu_lib
+    pr = synth.ct_phantom_pair((64, 64, 64), seed_R=5, seed_u=6)
+    ctx = _ctx(ngf, alpha=0.0, tau=10.0, rho=10.0, levels=1)
+    ctx.build_pyramid(_t(pr.R), _t(pr.R))
+    J, g, (D, S) = ctx.eval_J_grad(0, ctx.identity(0))
+    # Lagrange's form of 1 - r^2 is exactly zero for identical gradients
+    assert J == 0.0 and D == 0.0 and S == 0.0
+    assert float(g.abs().max()) == 0.0
+
+
+def test_eval_deterministic(gpu_lib):
+    ngf = gpu_lib
+    pr = synth.ct_phantom_pair((64, 64, 64), seed_R=5, seed_u=6)
+    ctx = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=1)
+    ctx.build_pyramid(_t(pr.R), _t(pr.T))
+    prob = O.Problem(pr.R, pr.T, (1.0, 1.0, 1.0), (33, 33, 33), 0.1, 10.0, 10.0)
+    y = _t(_y(prob, 2.0, 4))
+    J1, g1, _ = ctx.eval_J_grad(0, y)
+    J2, g2, _ = ctx.eval_J_grad(0, y)
+    assert J1 == J2 and bool((g1 == g2).all())
+
+
+def test_lbfgs_steps_follow_oracle(gpu_lib):
+    ngf = gpu_lib
+    pr = synth.blob_phantom_pair((32, 32, 32), seed_R=1, seed_u=2, max_disp=2.0)
+    ctx = _ctx(ngf, alpha=0.1, tau=0.1, rho=0.1, levels=1, lbfgs_mem=5)
+    ctx.build_pyramid(_t(pr.R), _t(pr.T))
+    prob = O.Problem(pr.R, pr.T, (1.0, 1.0, 1.0), (17, 17, 17), 0.1, 0.1, 0.1)
+    X = prob.identity()
+    ctx.lbfgs_reset(0, _t(X))
+    opt = O.LBFGS(lambda v: O.eval_J_grad(prob, v)[:2], X.astype(np.float32).astype(np.float64),
+                  mem=5, h_min=1.0)
+    for k in range(6):
+        J, info = ctx.lbfgs_step()
+        st, _ = opt.step()
+        _say(f"[lbfgs] step {k} gpu J={J} oracle J={opt.J}")
+        assert info == ngf.INFO_OK and st == O.INFO["OK"]
+        assert abs(J - opt.J) <= 1e-4 * abs(opt.J) * (k + 1)
+        y, g, Jg = ctx.lbfgs_get(0)
+        assert Jg == J
+        du = _np(y).astype(np.float64) - X
+        duo = opt.y - X
+        assert np.linalg.norm(du - duo) <= 1e-3 * (k + 1) * np.linalg.norm(duo)
+
+
+def test_register_blob32_against_oracle(gpu_lib):
+    """Full single-level registration: same iterations as the oracle's run, J
+    close, and both move y towards the known inverse deformation."""
+    ngf = gpu_lib
+    m = (32, 32, 32)
+    pr = synth.blob_phantom_pair(m, seed_R=1, seed_u=2, max_disp=2.0)
+    ctx = _ctx(ngf, alpha=0.1, tau=0.1, rho=0.1, levels=1, max_iter=20, lbfgs_mem=5)
+    y, rep = ctx.register(_t(pr.R), _t(pr.T))
+    yo, repo = O.register(pr.R, pr.T, (1.0, 1.0, 1.0), levels=1, alpha=0.1, tau=0.1, rho=0.1,
+                          max_iter=20, mem=5)
+    _say(f"[register] gpu {rep} oracle {repo}")
+    assert rep[0]["iters"] == 20 and repo[0][1] == 20
+    assert abs(rep[0]["J"] - repo[0][3]) <= 5e-3 * abs(repo[0][3])
+    zstar = synth.invert_displacement(pr.field, synth.voxel_centres(m))
+    body = pr.R > 0.3
+    my = (17, 17, 17)
+
+    def err(yy):
+        yh = O.apply_P(yy, m, my)
+        return np.sqrt(((yh - zstar) ** 2).sum(0))[body].mean()
+
+    e0 = err(O.identity(m, (1.0, 1.0, 1.0), my))
+    eg, eo = err(_np(y).astype(np.float64)), err(yo)
+    _say(f"[register] mean error identity {e0:.4f} gpu {eg:.4f} oracle {eo:.4f}")
+    assert eg < 0.6 * e0 and abs(eg - eo) < 0.05 * e0
+
+
+def test_register_multilevel_and_host_path(gpu_lib):
+    import torch
+    ngf = gpu_lib
+    pr = synth.ct_phantom_pair((128, 128, 128), seed_R=3, seed_u=4)
+    ctx = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=3, max_iter=10)
+    y_dev, rep = ctx.register(_t(pr.R), _t(pr.T))
+    assert len(rep) == 3 and all(r["iters"] >= 1 for r in rep)
+    ctx2 = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=3, max_iter=10)
+    y_host, rep2 = ctx2.register(torch.from_numpy(pr.R), torch.from_numpy(pr.T))
+    assert torch.equal(y_dev.cpu(), y_host)
+    assert [r["J"] for r in rep] == [r["J"] for r in rep2]
+
+
+def test_error_paths(gpu_lib):
+    ngf = gpu_lib
+    import torch
+    ctx = _ctx(ngf, levels=3)
+    with pytest.raises(ngf.NgfError) as e:
+        ctx.eval_J_grad(0, torch.zeros((3, 17, 17, 17), device="cuda"))
+    assert e.value.status in (ngf.E_STATE,)
+    R = torch.zeros((30, 32, 32), device="cuda")
+    with pytest.raises(ngf.NgfError) as e:
+        ctx.build_pyramid(R, R)
+    assert e.value.status == ngf.E_SHAPE
+    R = torch.zeros((8, 8, 8), device="cuda")
+    with pytest.raises(ngf.NgfError) as e:
+        ctx.build_pyramid(R, R)  # coarsest level would have 2 cells per axis
+    assert e.value.status == ngf.E_SHAPE
+    R = torch.zeros((32, 32, 32), device="cuda")
+    bad = R.clone()
+    bad[3, 4, 5] = float("nan")
+    with pytest.raises(ngf.NgfError) as e:
+        ctx.build_pyramid(R, bad)
+    assert e.value.status == ngf.E_NONFINITE
+    ctx.build_pyramid(R, R)
+    with pytest.raises(ngf.NgfError) as e:
+        ctx.level_info(3)
+    assert e.value.status == ngf.E_LEVEL
+    with pytest.raises(ngf.NgfError) as e:
+        ctx.prolongate(0, torch.zeros((3, 17, 17, 17), device="cuda"))
+    assert e.value.status == ngf.E_LEVEL
+    with pytest.raises(ngf.NgfError) as e:
+        ctx.lbfgs_step()
+    assert e.value.status == ngf.E_STATE
+    with pytest.raises(ngf.NgfError) as e:
+        ctx.set_params(ratio=4)
+    assert e.value.status == ngf.E_STATE
