@@ -37,7 +37,7 @@ METRIC = "J+∇J evals/s and full-registration seconds at 256^3; HBM GB/s vs pea
 
 def _src_hash():
     h = hashlib.sha256()
-    for f in ("k_eval.hip",):
+    for f in ("k_eval.hip", "k_march.hip", "ngf_internal.h"):
         with open(os.path.join(ROOT, "paper_1812_06765_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=50)
     ap.add_argument("--finest-evals", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only copy 1 GiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the registration of one pair runs on one "
@@ -91,8 +93,17 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
+
+    if args.pmc_probe:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": "copy", "bytes_read": x.numel() * 4,
+                          "bytes_written": y.numel() * 4}), flush=True)
+        return
 
     from paper_1812_06765_amd import ngf, synth
 
@@ -171,7 +182,7 @@ def main():
                    "compulsory_bytes": finest_bytes,
                    "effective_GBs": finest_bytes * args.finest_evals / tf / 1e9},
         "roofline": {
-            "kernel": "k_image_pass (fused P, warp, NGF, adjoint, tile P^T)",
+            "kernel": "image pass (k_image_pass or k_image_march, as autotuned per level)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -142,6 +142,18 @@ ngf_status ngf_set_params(ngf_ctx* ctx, const ngf_params* p);
 ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
                              const ngf_grid* g, int32_t host_ptrs);
 
+/* Image-grid kernel of the evaluation.  `variant`: -1 = autotune (default:
+ * at ngf_build_pyramid every level times each variant over three evaluations
+ * at the identity and keeps the fastest; choices are cached per image shape
+ * in the context and, if the environment variable NGF_TUNE_CACHE names a
+ * file, appended to and read from that file); 0 = 3D tiles of 8x8x32 voxels
+ * with a two-voxel halo; 1, 2, 3 = x-marching over 16x64 (y, z) tiles in
+ * chunks of 8, 20 or 32 planes.  All variants compute the same quantities;
+ * only the summation order of the P^T partial sums differs.  Applies at once
+ * to a built pyramid.  ngf_get_kernel reports a level's choice. */
+ngf_status ngf_set_kernel(ngf_ctx* ctx, int32_t variant);
+ngf_status ngf_get_kernel(const ngf_ctx* ctx, int32_t level, int32_t* variant);
+
 /* Number of pyramid levels and the grids of one level: `img` gets the image
  * grid, `def` the deformation grid (m = node counts, h = node spacing).
  * Either output may be NULL. */
@@ -212,20 +224,42 @@ ngf_status ngf_register(ngf_ctx* ctx, const float* R, const float* T, const ngf_
  * (device-resident inputs; the pyramid step is not repeated). */
 ngf_status ngf_register_levels(ngf_ctx* ctx, float* y_out, ngf_report* rep);
 
-/* Differentiation form: J(y; R, T) and its gradients with respect to y and to
- * the template T on an explicit image pair (not the pyramid), for an autograd
- * wrapper.  dJ/dT[k] = sum_i e[i] W(i -> k), the transpose of the warp applied
- * to the NGF sensitivity e of each image point; both P^T and dJ/dT are
- * evaluated by scatter with float32 atomic additions (image-point major), so
- * results are reproducible only up to rounding.
- *   g, my      image grid and deformation-grid node counts
- *   R, T, y    device inputs; J host double (NULL: no synchronisation)
+/* Differentiation form (for an autograd wrapper): J(y; R, T) on an explicit
+ * image pair (not the pyramid) and its gradients with respect to y and to
+ * the template T.  The backward is a scatter: each image tile adds its P^T
+ * block into grad_y with float atomic additions, and every image point adds
+ * e[i] W(i -> k) into grad_T[k] for the 8 corners k of its warp cell (the
+ * transpose of the trilinear warp, with e = G^T v the NGF sensitivity of
+ * the warped template), so these gradients are reproducible only up to
+ * rounding; alpha grad S is added by the node pass.  Sec. 2.1 (Eq. 1),
+ * Sec. 2.2 (Eq. 2 and the matrix-free chain rule).
+ *   g, my      image grid; my[d] must be m[d]/ratio + 1 (else NGF_E_SHAPE)
+ *   R, T, y    device inputs in the usual layouts
+ *   gscale     device double multiplying both gradients (the upstream
+ *              gradient of an autograd graph), or NULL for 1
+ *   J          host double (the call then synchronises) or NULL
+ *   J_dev      device double receiving J without synchronising, or NULL
  *   grad_y     device float32 like y, or NULL; grad_T device float32 like T,
- *              or NULL (with both NULL only J is computed)
- * May allocate scratch on the first call for a larger grid. */
+ *              or NULL; both NULL: only J is computed
+ * Allocates index maps and scratch on the first call for a new grid. */
 ngf_status ngf_eval_pair(ngf_ctx* ctx, const ngf_grid* g, const int32_t my[3],
-                         const float* R, const float* T, const float* y, double* J,
+                         const float* R, const float* T, const float* y,
+                         const double* gscale, double* J, double* J_dev,
                          float* grad_y, float* grad_T);
+
+/* Grid conversion as standalone operators on a level's grids (Sec. 2.2,
+ * "Grid conversion"; the evaluation fuses them and does not call these).
+ *   ngf_apply_P:  yhat = P y, yhat float32 [3][m_x][m_y][m_z] (float64 sums)
+ *   ngf_apply_PT: out = P^T z, z like yhat, out like y; `scheme` selects how
+ *     the write conflicts of P^T are avoided: 0 = gather, one thread per node
+ *     summing its index sets (Eq. 3, the paper's scheme); 1 = scatter with
+ *     float atomic additions, one thread per image point (the earlier GPU
+ *     scheme the paper cites); 2 = red-black: four colour phases over the
+ *     (x, y) cells, one thread per cell column scattering serially (the
+ *     earlier CPU scheme).  Results agree up to the order of float32 sums. */
+ngf_status ngf_apply_P(ngf_ctx* ctx, int32_t level, const float* y, float* yhat);
+ngf_status ngf_apply_PT(ngf_ctx* ctx, int32_t level, const float* z, float* out,
+                        int32_t scheme);
 
 /* Profiling aid: when enabled, the library records HIP events around every
  * launch of the fused image-grid kernel (the dominant kernel of an

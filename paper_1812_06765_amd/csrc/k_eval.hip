@@ -72,8 +72,10 @@ struct AxisCell {
     float s;
 };
 
-__device__ inline AxisCell axis_cell(double yhat, double h, int m) {
-    double xi = yhat / h - 0.5;
+__device__ inline AxisCell axis_cell(double yhat, double h, double ih, bool pow2h, int m) {
+    // with a power-of-two spacing the reciprocal is exact and the product
+    // rounds exactly like the quotient
+    double xi = pow2h ? fma(yhat, ih, -0.5) : yhat / h - 0.5;
     const double hi = static_cast<double>(m - 1);
     const float s = (xi >= 0.0 && xi <= hi) ? 1.0f : 0.0f;
     xi = fmin(fmax(xi, 0.0), hi);
@@ -111,7 +113,11 @@ struct ImageTile {
     static_assert(LDS_FLOATS * 4 <= 65536, "image tile fits 64 KiB of LDS");
 };
 
-template <int TX, int TY, int TZ, int RATIO, bool GRAD>
+// ATOMIC (differentiation form): instead of writing tile partials, stage 4
+// adds each tile's P^T block into a.gy_atomic with float atomics, and stage 3
+// scatters e W(i -> k) into a.gT_atomic (the transpose of the warp), both
+// scaled by *a.gscale.
+template <int TX, int TY, int TZ, int RATIO, bool GRAD, bool ATOMIC>
 __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
     using L = ImageTile<TX, TY, TZ, RATIO>;
     extern __shared__ float smem[];
@@ -147,7 +153,8 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
 
     // ---- stage 1: P and the warp ----------------------------------------
     // y_hat at image voxel (gx,gy,gz) (already clamped into the domain)
-    auto warp_at = [&](int gx, int gy, int gz, float* dT) -> float {
+    auto warp_at = [&](int gx, int gy, int gz, float* dT, int* cb = nullptr,
+                       float* cf = nullptr) -> float {
         const int jx = a.j0x[gx], jy = a.j0y[gy], jz = a.j0z[gz];
         const double ax1 = a.w1x[gx], ay1 = a.w1y[gy], az1 = a.w1z[gz];
         const double ax0 = a.w0x[gx], ay0 = a.w0y[gy], az0 = a.w0z[gz];
@@ -166,10 +173,16 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
             const double c0 = ay0 * c00 + ay1 * c01, c1 = ay0 * c10 + ay1 * c11;
             yh[c] = ax0 * c0 + ax1 * c1;
         }
-        const AxisCell cx = axis_cell(yh[0], a.hx, mx);
-        const AxisCell cy = axis_cell(yh[1], a.hy, my);
-        const AxisCell cz = axis_cell(yh[2], a.hz, mz);
+        const AxisCell cx = axis_cell(yh[0], a.hx, a.ihx, a.pow2h, mx);
+        const AxisCell cy = axis_cell(yh[1], a.hy, a.ihy, a.pow2h, my);
+        const AxisCell cz = axis_cell(yh[2], a.hz, a.ihz, a.pow2h, mz);
         const float* Tb = a.T + cx.i0 * sxT + cy.i0 * mz + cz.i0;
+        if (ATOMIC && cb != nullptr) {
+            *cb = cx.i0 * sxT + cy.i0 * mz + cz.i0;
+            cf[0] = cx.f;
+            cf[1] = cy.f;
+            cf[2] = cz.f;
+        }
         const float v000 = Tb[0], v001 = Tb[1], v010 = Tb[mz], v011 = Tb[mz + 1];
         const float v100 = Tb[sxT], v101 = Tb[sxT + 1], v110 = Tb[sxT + mz],
                     v111 = Tb[sxT + mz + 1];
@@ -192,12 +205,16 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
     };
 
     float dTk[L::KT][3];
+    int cbk[ATOMIC ? L::KT : 1];
+    float cfk[ATOMIC ? L::KT : 1][3];
 #pragma unroll
     for (int k = 0; k < L::KT; ++k) {
         const int t = threadIdx.x + k * kThreads;
         const int lz = t % TZ, ly = (t / TZ) % TY, lx = t / (TZ * TY);
         const int gx = min(x0 + lx, mx - 1), gy = min(y0 + ly, my - 1), gz = min(z0 + lz, mz - 1);
-        const float v = warp_at(gx, gy, gz, dTk[k]);
+        const float v = ATOMIC ? warp_at(gx, gy, gz, dTk[k], &cbk[ATOMIC ? k : 0],
+                                         cfk[ATOMIC ? k : 0])
+                               : warp_at(gx, gy, gz, dTk[k]);
         sTy[((lx + 2) * L::H2Y + (ly + 2)) * L::H2Z + (lz + 2)] = v;
     }
     // halo shell of the two-voxel box: x slabs, then y slabs, then z slabs
@@ -308,6 +325,7 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
     const double dtot = block_sum(dsum, red);
     if (threadIdx.x == 0) a.dpart[tile] = dtot;
     if (!GRAD) return;
+    const float gscale = (ATOMIC && a.gscale != nullptr) ? static_cast<float>(*a.gscale) : 1.0f;
     __syncthreads();
 
     // ---- stage 3: e = G^T v and dD/dy_hat on the tile ---------------------
@@ -323,8 +341,26 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
         sG[t] = e * dTk[k][0];
         sG[L::NT + t] = e * dTk[k][1];
         sG[2 * L::NT + t] = e * dTk[k][2];
+        if (ATOMIC && a.gT_atomic != nullptr && in) {
+            // dD/dT[k] += e W(i -> k) over the 8 corners of this voxel's cell
+            const float es = e * gscale;
+            const int b = cbk[ATOMIC ? k : 0];
+            const float fx = cfk[ATOMIC ? k : 0][0], fy = cfk[ATOMIC ? k : 0][1],
+                        fz = cfk[ATOMIC ? k : 0][2];
+            const float qx = 1.0f - fx, qy = 1.0f - fy, qz = 1.0f - fz;
+            float* G = a.gT_atomic + b;
+            atomicAdd(G, es * qx * qy * qz);
+            atomicAdd(G + 1, es * qx * qy * fz);
+            atomicAdd(G + mz, es * qx * fy * qz);
+            atomicAdd(G + mz + 1, es * qx * fy * fz);
+            atomicAdd(G + sxT, es * fx * qy * qz);
+            atomicAdd(G + sxT + 1, es * fx * qy * fz);
+            atomicAdd(G + sxT + mz, es * fx * fy * qz);
+            atomicAdd(G + sxT + mz + 1, es * fx * fy * fz);
+        }
     }
     __syncthreads();
+    if (ATOMIC && a.gy_atomic == nullptr) return;
 
     // ---- stage 4: P^T restricted to the tile (separable: z, y, x) ---------
     float* sGz = sA;             // [3][TX][TY][PZ]
@@ -374,7 +410,14 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
             const float w = (a.j0x[ix] == jx) ? a.w0x[ix] : a.w1x[ix];
             acc = fmaf(w, sGy[((c * TX + lx) * L::PY + ny) * L::PZ + nz], acc);
         }
-        out[i] = acc;
+        if (ATOMIC) {
+            const int jy = jy0 + ny, jz = jz0 + nz;
+            if (jx < a.nx && jy < a.ny && jz < a.nz)
+                atomicAdd(a.gy_atomic + c * (a.nx * a.ny * a.nz) + (jx * a.ny + jy) * a.nz + jz,
+                          acc * gscale);
+        } else {
+            out[i] = acc;
+        }
     }
 }
 
@@ -403,6 +446,7 @@ __global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
 
     double ssum = 0.0, gmax = 0.0, g2 = 0.0;
     const double hyd[3] = {a.hyx, a.hyy, a.hyz};
+    const float sc = (!a.gather && a.gscale != nullptr) ? static_cast<float>(*a.gscale) : 1.0f;
     for (int c = 0; c < 3; ++c) {
         const float* yc = a.y + c * nn;
         for (int i = threadIdx.x; i < NB2; i += kThreads) {
@@ -445,11 +489,13 @@ __global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
             const float lyy = at(gx, gyc, gz) - 2.0f * au + at(gx, gym, gz);
             const float lzz = at(gx, gy, gzc) - 2.0f * au + at(gx, gy, gzm);
             const float aau = fmaf(lxx, a.ihy2x, fmaf(lyy, a.ihy2y, lzz * a.ihy2z));
-            // gather the image-tile partials of this node (completes Eq. 3)
+            // gather the image-tile partials of this node (completes Eq. 3), or
+            // take grad D accumulated by the scatter form
             float gd = 0.0f;
+            if (!a.gather) gd = a.grad[c * nn + (gx * ny + gy) * nz + gz];
             const int txh = gx / a.bx, tyh = gy / a.by, tzh = gz / a.bz;
             const int rx = gx - txh * a.bx, ry = gy - tyh * a.by, rz = gz - tzh * a.bz;
-            for (int ox = 0; ox < 2; ++ox) {
+            for (int ox = 0; ox < (a.gather ? 2 : 0); ++ox) {
                 const int ttx = txh - ox, llx = rx + ox * a.bx;
                 if (ttx < 0 || ttx >= a.ntx || (ox == 1 && rx != 0)) continue;
                 for (int oy = 0; oy < 2; ++oy) {
@@ -464,7 +510,7 @@ __global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
                     }
                 }
             }
-            const float g = fmaf(a.alpha_hbary, aau, gd);
+            const float g = fmaf(a.alpha_hbary * sc, aau, gd);
             a.grad[c * nn + (gx * ny + gy) * nz + gz] = g;
             gmax = fmax(gmax, static_cast<double>(fabsf(g)));
             g2 += static_cast<double>(g) * static_cast<double>(g);
@@ -489,11 +535,20 @@ void launch_image_ratio(const ImagePassArgs& a, hipStream_t s) {
     const int blocks = a.ntx * a.nty * a.ntz;
     const size_t lds = sizeof(float) * L::LDS_FLOATS;
     if (a.want_grad)
-        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, true>), dim3(blocks),
+        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, true, false>), dim3(blocks),
                            dim3(kThreads), lds, s, a);
     else
-        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, false>), dim3(blocks),
+        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, false, false>), dim3(blocks),
                            dim3(kThreads), lds, s, a);
+}
+
+template <int RATIO>
+void launch_image_ratio_atomic(const ImagePassArgs& a, hipStream_t s) {
+    using L = ImageTile<kTX, kTY, kTZ, RATIO>;
+    const int blocks = a.ntx * a.nty * a.ntz;
+    const size_t lds = sizeof(float) * L::LDS_FLOATS;
+    hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, true, true>), dim3(blocks),
+                       dim3(kThreads), lds, s, a);
 }
 
 }  // namespace
@@ -504,6 +559,13 @@ void launch_image_pass(const ImagePassArgs& a, int ratio, hipStream_t s) {
         case 4: launch_image_ratio<4>(a, s); break;
         default: break;
     }
+}
+
+void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s) {
+    if (ratio == 2)
+        launch_image_ratio_atomic<2>(a, s);
+    else if (ratio == 4)
+        launch_image_ratio_atomic<4>(a, s);
 }
 
 void launch_node_pass(const NodePassArgs& a, hipStream_t s) {

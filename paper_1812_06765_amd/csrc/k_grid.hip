@@ -113,6 +113,12 @@ __global__ __launch_bounds__(kThreads) void k_check_finite(const float* __restri
     if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
+__global__ __launch_bounds__(kThreads) void k_fill(float* p, int64_t n, float v) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
 // Fixed-order sums of the per-block partials: thread t adds entries t,
 // t + 256, ... in order, then a fixed tree over the 256 thread sums.
 __device__ double block_sum_fixed(const double* a, int n, double* sh) {
@@ -195,6 +201,10 @@ void launch_prolongate(const float* yc, float* yf, int cx, int cy, int cz, hipSt
 void launch_check_finite(const float* v, int64_t n, int* flag, hipStream_t s) {
     hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, kThreads, 4096)), dim3(kThreads), 0, s,
                        v, n, flag);
+}
+
+void launch_fill(float* p, int64_t n, float v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, p, n, v);
 }
 
 void launch_reduce(const ReduceArgs& a, hipStream_t s) {

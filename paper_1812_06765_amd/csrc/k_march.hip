@@ -1,0 +1,459 @@
+// Image-grid pass, marching form.  Same arithmetic as k_image_pass (P and the
+// warp with float64 coordinates, NGF term of Eq. 2, its adjoint stencil, the
+// tile-local part of the P^T gather of Eq. 3), organised for fewer redundant
+// voxels: a workgroup owns a (y, z) tile of TY x TZ voxels and a chunk of CX
+// planes along x (the slowest axis) and walks the planes in order, keeping
+// rolling planes in LDS.  Halos then exist only inside a plane (two voxels
+// for the warped template, one for v) plus four planes per chunk, instead of
+// in all three directions.
+//
+// Per step k (plane p_w = x0 - 2 + k enters):
+//   W  warp plane p_w (tile + in-plane halo 2); stage R of plane p_w - 1
+//   V  NGF on plane p_v = p_w - 1 (tile + in-plane face halo 1): D term, v
+//   E  adjoint on plane p_e = p_w - 2 (tile): e = G^T v, dD/dy_hat = e dT
+//   Z  P^T along z of plane p_e
+//   Y  P^T along y, then along x into two register accumulators (the two
+//      node planes the image plane touches); build the x-interpolated node
+//      plane used by the next W
+// Ghost planes of the x adjoint stencil (x = -1, x = m_x) are not computed:
+// E substitutes v_x(-1) = -v_x(0) and v_x(m_x) = -v_x(m_x - 1) directly.
+//
+// The P^T partial sums are written in the tile layout the node pass reads:
+// tile (chunk, ty, tz) owns node block [x0/R, x0/R + CX/R] x [...] x [...].
+#include "ngf_internal.h"
+
+#include <math.h>
+
+#include <type_traits>
+
+namespace ngf {
+
+namespace {
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ inline double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+template <int TY, int TZ, int R>
+struct March {
+    static constexpr int H2Y = TY + 4, H2Z = TZ + 4, NH2 = H2Y * H2Z;
+    static constexpr int H1Y = TY + 2, H1Z = TZ + 2;
+    static constexpr int NI = TY * TZ, KP = NI / kThreads;
+    static constexpr int NRING2 = NH2 - NI;             // in-plane halo-2 ring
+    static constexpr int NRING1 = 2 * TZ + 2 * TY;      // in-plane face halo-1 ring
+    static constexpr int BY = TY / R, BZ = TZ / R, PY = BY + 1, PZ = BZ + 1;
+    static constexpr int NOUT = 3 * PY * PZ, KO = (NOUT + kThreads - 1) / kThreads;
+    static constexpr int NQY = TY / R + 4, NQZ = TZ / R + 4, NQ = NQY * NQZ;
+    static constexpr int GZ = 3 * TY * PZ;
+    // LDS layout (floats)
+    static constexpr int OFF_TY = 0;                          // 3 x NH2
+    static constexpr int OFF_R = OFF_TY + 3 * NH2;            // NH2
+    static constexpr int OFF_VX = OFF_R + NH2;                // 3 x NI
+    static constexpr int OFF_VY = OFF_VX + 3 * NI;            // 2 x H1Y x TZ
+    static constexpr int OFF_VZ = OFF_VY + 2 * H1Y * TZ;      // 2 x TY x H1Z
+    static constexpr int OFF_G = OFF_VZ + 2 * TY * H1Z;       // max(3 NI, 2 x 3 NQ): sG or Q
+    static constexpr int SZ_G = (3 * NI > 6 * NQ ? 3 * NI : 6 * NQ);
+    static constexpr int OFF_GZ = OFF_G + SZ_G;               // GZ
+    static constexpr int LDS_FLOATS = OFF_GZ + GZ;
+    static_assert(NI % kThreads == 0, "tile plane must be a multiple of the workgroup");
+    static_assert(TY % R == 0 && TZ % R == 0, "ratio-aligned tile");
+    static_assert((OFF_G % 2) == 0, "double alignment of Q");
+    static_assert(NRING1 <= kThreads, "face ring in one pass");
+    static_assert(LDS_FLOATS * 4 <= 81920, "two workgroups per CU");
+};
+
+// image index -> node index and the two weights along one axis, for a
+// power-of-two ratio: voxel i = q R + k lies at node coordinate q + (2k+1)/(2R)
+template <int R>
+__device__ inline int node_of(int i) {
+    return i / R;
+}
+template <int R>
+__device__ inline float w1_of(int i) {
+    return static_cast<float>(2 * (i % R) + 1) * (0.5f / R);
+}
+
+template <int TY, int TZ, int R, bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int CX) {
+    using L = March<TY, TZ, R>;
+    extern __shared__ float smem[];
+    float* sTy = smem + L::OFF_TY;
+    float* sR = smem + L::OFF_R;
+    float* sVx = smem + L::OFF_VX;
+    float* sVy = smem + L::OFF_VY;
+    float* sVz = smem + L::OFF_VZ;
+    float* sG = smem + L::OFF_G;
+    double* sQ = reinterpret_cast<double*>(smem + L::OFF_G);
+    float* sGz = smem + L::OFF_GZ;
+    __shared__ double red[4];
+
+    // tile decode, spread over the XCDs so that neighbouring tiles share an L2
+    const int ntiles = a.ntx * a.nty * a.ntz;
+    int tile = blockIdx.x;
+    if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+    const int tz = tile % a.ntz;
+    const int ty = (tile / a.ntz) % a.nty;
+    const int tx = tile / (a.ntz * a.nty);
+    const int x0 = tx * CX, y0 = ty * TY, z0 = tz * TZ;
+    const int mx = a.mx, my = a.my, mz = a.mz;
+    const int sxT = my * mz;
+    const int nnod = a.nx * a.ny * a.nz;
+    const int qly = max(y0 - 2, 0) / R, qlz = max(z0 - 2, 0) / R;
+    const int jx_first = x0 / R;
+    const int xend = min(x0 + CX, mx);  // first plane past the chunk (in the domain)
+
+    // x-interpolated node plane for image plane p (clamped), float64, into sQ
+    auto build_q = [&](int p) {
+        const int pc = clampi(p, 0, mx - 1);
+        const int jx = node_of<R>(pc);
+        const double w1 = w1_of<R>(pc), w0 = 1.0 - w1;
+        for (int i = threadIdx.x; i < 3 * L::NQ; i += kThreads) {
+            const int c = i / L::NQ;
+            const int r = i - c * L::NQ;
+            const int qz = r % L::NQZ, qy = r / L::NQZ;
+            const int gy = min(qly + qy, a.ny - 1), gz = min(qlz + qz, a.nz - 1);
+            const float* yc = a.y + c * nnod + gy * a.nz + gz;
+            const double v0 = yc[jx * a.ny * a.nz], v1 = yc[(jx + 1) * a.ny * a.nz];
+            sQ[i] = w0 * v0 + w1 * v1;
+        }
+    };
+
+    // warp at in-plane position (gy, gz) (clamped into the domain) of plane p
+    // (clamped), from the x-interpolated node plane
+    auto warp_at = [&](int pc, int gy, int gz, float* dT) -> float {
+        const int jy = node_of<R>(gy), jz = node_of<R>(gz);
+        const double wy1 = w1_of<R>(gy), wz1 = w1_of<R>(gz);
+        const double wy0 = 1.0 - wy1, wz0 = 1.0 - wz1;
+        const int q = (jy - qly) * L::NQZ + (jz - qlz);
+        double yh[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double* Q = sQ + c * L::NQ + q;
+            const double c0 = wz0 * Q[0] + wz1 * Q[1];
+            const double c1 = wz0 * Q[L::NQZ] + wz1 * Q[L::NQZ + 1];
+            yh[c] = wy0 * c0 + wy1 * c1;
+        }
+        // continuous template index y_hat / h - 1/2; a power-of-two spacing has
+        // an exact reciprocal, any other is divided (correctly rounded)
+        int i0[3];
+        float f[3], s[3];
+        const double hh[3] = {a.hx, a.hy, a.hz};
+        const double ih[3] = {a.ihx, a.ihy, a.ihz};
+        const int mm[3] = {mx, my, mz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double xi = a.pow2h ? fma(yh[d], ih[d], -0.5) : yh[d] / hh[d] - 0.5;
+            const double hi = static_cast<double>(mm[d] - 1);
+            s[d] = (xi >= 0.0 && xi <= hi) ? 1.0f : 0.0f;
+            xi = fmin(fmax(xi, 0.0), hi);
+            const double fl = fmin(floor(xi), static_cast<double>(mm[d] - 2));
+            i0[d] = static_cast<int>(fl);
+            f[d] = static_cast<float>(xi - fl);
+        }
+        (void)pc;
+        const float* Tb = a.T + i0[0] * sxT + i0[1] * mz + i0[2];
+        const float v000 = Tb[0], v001 = Tb[1], v010 = Tb[mz], v011 = Tb[mz + 1];
+        const float v100 = Tb[sxT], v101 = Tb[sxT + 1], v110 = Tb[sxT + mz],
+                    v111 = Tb[sxT + mz + 1];
+        const float qx = 1.0f - f[0], qy = 1.0f - f[1], qz = 1.0f - f[2];
+        const float c00 = fmaf(f[2], v001, qz * v000), c01 = fmaf(f[2], v011, qz * v010);
+        const float c10 = fmaf(f[2], v101, qz * v100), c11 = fmaf(f[2], v111, qz * v110);
+        const float c0 = fmaf(f[1], c01, qy * c00), c1 = fmaf(f[1], c11, qy * c10);
+        if (GRAD && dT != nullptr) {
+            const float d0 = c01 - c00, d1 = c11 - c10;
+            const float e00 = v001 - v000, e01 = v011 - v010, e10 = v101 - v100,
+                        e11 = v111 - v110;
+            dT[0] = (c1 - c0) * (s[0] * a.fihx);
+            dT[1] = fmaf(f[0], d1, qx * d0) * (s[1] * a.fihy);
+            const float ez0 = fmaf(f[1], e01, qy * e00), ez1 = fmaf(f[1], e11, qy * e10);
+            dT[2] = fmaf(f[0], ez1, qx * ez0) * (s[2] * a.fihz);
+        }
+        return fmaf(f[0], c1, qx * c0);
+    };
+
+    float dTr[3][L::KP][3];  // dT of the last three warped planes (slot = k mod 3)
+    float acc0[L::KO], acc1[L::KO];
+#pragma unroll
+    for (int o = 0; o < L::KO; ++o) acc0[o] = acc1[o] = 0.0f;
+    int jA = jx_first;
+    double dsum = 0.0;
+    float* part = a.part + static_cast<int64_t>(tile) * 3 * (CX / R + 1) * L::PY * L::PZ;
+    const int NPc = (CX / R + 1) * L::PY * L::PZ;
+
+    auto flush = [&](int j, const float* acc) {
+        const int lx = j - jx_first;
+        if (lx < 0 || lx > CX / R) return;
+#pragma unroll
+        for (int o = 0; o < L::KO; ++o) {
+            const int i = threadIdx.x + o * kThreads;
+            if (i < L::NOUT) {
+                const int c = i / (L::PY * L::PZ);
+                const int r = i - c * (L::PY * L::PZ);
+                part[c * NPc + lx * (L::PY * L::PZ) + r] = acc[o];
+            }
+        }
+    };
+
+    build_q(x0 - 2);
+    __syncthreads();
+
+    auto step = [&](const int k, auto Sc) {
+        constexpr int S = decltype(Sc)::value;
+        // ---------------- W: warp plane pw, stage R of plane pw - 1 --------
+        const int pw = x0 - 2 + k;
+        const int pwc = clampi(pw, 0, mx - 1);
+        float* Ty = sTy + S * L::NH2;
+        const bool wgrad = GRAD && pw >= x0 && pw < xend;
+#pragma unroll
+        for (int kk = 0; kk < L::KP; ++kk) {
+            const int t = threadIdx.x + kk * kThreads;
+            const int ly = t / TZ, lz = t % TZ;
+            const int gy = min(y0 + ly, my - 1), gz = min(z0 + lz, mz - 1);
+            Ty[(ly + 2) * L::H2Z + (lz + 2)] =
+                warp_at(pwc, gy, gz, wgrad ? dTr[S][kk] : nullptr);
+        }
+        for (int s = threadIdx.x; s < L::NRING2; s += kThreads) {
+            int by, bz;
+            if (s < 4 * L::H2Z) {
+                const int row = s / L::H2Z;
+                by = row < 2 ? row : TY + row;
+                bz = s - row * L::H2Z;
+            } else {
+                const int q = s - 4 * L::H2Z;
+                const int col = q & 3;
+                by = 2 + (q >> 2);
+                bz = col < 2 ? col : TZ + col;
+            }
+            const int gy = clampi(y0 - 2 + by, 0, my - 1), gz = clampi(z0 - 2 + bz, 0, mz - 1);
+            Ty[by * L::H2Z + bz] = warp_at(pwc, gy, gz, nullptr);
+        }
+        const int pv = pw - 1;
+        const bool vok = pv >= max(x0 - 1, 0) && pv <= min(x0 + CX, mx - 1);
+        if (vok) {
+            const float* Rp = a.R + pv * sxT;
+            for (int i = threadIdx.x; i < L::NH2; i += kThreads) {
+                const int by = i / L::H2Z, bz = i - by * L::H2Z;
+                const int gy = clampi(y0 - 2 + by, 0, my - 1), gz = clampi(z0 - 2 + bz, 0, mz - 1);
+                sR[i] = Rp[gy * mz + gz];
+            }
+        }
+        __syncthreads();
+
+        // ---------------- V: NGF on plane pv ------------------------------
+        if (vok) {
+            const float* Tm = sTy + ((S + 1) % 3) * L::NH2;  // plane pv - 1 (slot of k - 2)
+            const float* T0 = sTy + ((S + 2) % 3) * L::NH2;  // plane pv     (slot of k - 1)
+            const float* Tp = Ty;                            // plane pv + 1 (slot of k)
+            const float* Rm = a.R + max(pv - 1, 0) * sxT;
+            const float* Rq = a.R + min(pv + 1, mx - 1) * sxT;
+            const bool dtile = pv >= x0 && pv < xend;
+            float* Vx = sVx + (pv % 3) * L::NI;
+            float* Vy = sVy + (pv & 1) * (L::H1Y * TZ);
+            float* Vz = sVz + (pv & 1) * (TY * L::H1Z);
+            auto ngf_at = [&](int b1y, int b1z, bool inner) {
+                const int gy = y0 - 1 + b1y, gz = z0 - 1 + b1z;
+                const int cy = clampi(gy, 0, my - 1), cz = clampi(gz, 0, mz - 1);
+                const int p = (cy - y0 + 2) * L::H2Z + (cz - z0 + 2);
+                const float tau = a.tau, rho = a.rho;
+                const float gTx = (Tp[p] - Tm[p]) * a.i2hx;
+                const float gTy = (T0[p + L::H2Z] - T0[p - L::H2Z]) * a.i2hy;
+                const float gTz = (T0[p + 1] - T0[p - 1]) * a.i2hz;
+                const float gRx = (Rq[cy * mz + cz] - Rm[cy * mz + cz]) * a.i2hx;
+                const float gRy = (sR[p + L::H2Z] - sR[p - L::H2Z]) * a.i2hy;
+                const float gRz = (sR[p + 1] - sR[p - 1]) * a.i2hz;
+                const float aa = fmaf(gTx, gTx, fmaf(gTy, gTy, fmaf(gTz, gTz, tau * tau)));
+                const float bb = fmaf(gRx, gRx, fmaf(gRy, gRy, fmaf(gRz, gRz, rho * rho)));
+                const float ab = fmaf(gTx, gRx, fmaf(gTy, gRy, fmaf(gTz, gRz, tau * rho)));
+                const float iaa = 1.0f / aa, ibb = 1.0f / bb;
+                if (inner && dtile && gy < my && gz < mz) {
+                    float q1, q2, q3, q4, q5, q6;
+                    {
+#pragma clang fp contract(off)
+                        q1 = gTx * gRy - gTy * gRx;
+                        q2 = gTx * gRz - gTz * gRx;
+                        q3 = gTy * gRz - gTz * gRy;
+                        q4 = gTx * rho - tau * gRx;
+                        q5 = gTy * rho - tau * gRy;
+                        q6 = gTz * rho - tau * gRz;
+                    }
+                    const float lag = fmaf(q1, q1, fmaf(q2, q2, fmaf(q3, q3,
+                                          fmaf(q4, q4, fmaf(q5, q5, q6 * q6)))));
+                    dsum += static_cast<double>(lag * iaa * ibb);
+                }
+                if (GRAD) {
+                    const float k1 = ab / aa;
+                    const float coef = -a.hbar * ab * iaa * ibb;
+                    float vx = coef * fmaf(-k1, gTx, gRx);
+                    float vy = coef * fmaf(-k1, gTy, gRy);
+                    float vz = coef * fmaf(-k1, gTz, gRz);
+                    if (gy != cy) vy = -vy;  // mirrored ghost of the y adjoint stencil
+                    if (gz != cz) vz = -vz;
+                    const int hy = (b1y == 0 || b1y == TY + 1), hz = (b1z == 0 || b1z == TZ + 1);
+                    if (!hy && !hz) Vx[(b1y - 1) * TZ + (b1z - 1)] = vx;
+                    if (!hz) Vy[b1y * TZ + (b1z - 1)] = vy;
+                    if (!hy) Vz[(b1y - 1) * L::H1Z + b1z] = vz;
+                }
+            };
+#pragma unroll
+            for (int kk = 0; kk < L::KP; ++kk) {
+                const int t = threadIdx.x + kk * kThreads;
+                ngf_at(t / TZ + 1, t % TZ + 1, true);
+            }
+            if (GRAD && threadIdx.x < L::NRING1) {
+                const int s = threadIdx.x;
+                int b1y, b1z;
+                if (s < 2 * TZ) {
+                    b1y = s < TZ ? 0 : TY + 1;
+                    b1z = 1 + (s % TZ);
+                } else {
+                    const int q = s - 2 * TZ;
+                    b1y = 1 + (q >> 1);
+                    b1z = (q & 1) ? TZ + 1 : 0;
+                }
+                ngf_at(b1y, b1z, false);
+            }
+        }
+        if (!GRAD) {
+            __syncthreads();
+            if (k + 1 < CX + 4) build_q(pw + 1);
+            __syncthreads();
+            return;
+        }
+        __syncthreads();
+
+        // ---------------- E: adjoint on plane pe --------------------------
+        const int pe = pw - 2;
+        const bool eok = pe >= x0 && pe < xend;
+        if (eok) {
+            const float* V0 = sVx + (pe % 3) * L::NI;
+            const float* Vm = pe - 1 >= 0 ? sVx + ((pe + 2) % 3) * L::NI : nullptr;
+            const float* Vp = pe + 1 <= mx - 1 ? sVx + ((pe + 1) % 3) * L::NI : nullptr;
+            const float* Vy = sVy + (pe & 1) * (L::H1Y * TZ);
+            const float* Vz = sVz + (pe & 1) * (TY * L::H1Z);
+            const int SE = (S + 1) % 3;  // dT of plane pe was stored at step k - 2
+#pragma unroll
+            for (int kk = 0; kk < L::KP; ++kk) {
+                const int t = threadIdx.x + kk * kThreads;
+                const int ly = t / TZ, lz = t % TZ;
+                const float vxm = Vm ? Vm[t] : -V0[t];
+                const float vxp = Vp ? Vp[t] : -V0[t];
+                const float ex = vxm - vxp;
+                const float ey = Vy[ly * TZ + lz] - Vy[(ly + 2) * TZ + lz];
+                const float ez = Vz[ly * L::H1Z + lz] - Vz[ly * L::H1Z + lz + 2];
+                const bool in = (y0 + ly < my) && (z0 + lz < mz);
+                const float e = in ? fmaf(ex, a.i2hx, fmaf(ey, a.i2hy, ez * a.i2hz)) : 0.0f;
+                float dd[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    // static slot selection keeps dTr in registers
+                    dd[c] = SE == 0 ? dTr[0][kk][c] : (SE == 1 ? dTr[1][kk][c] : dTr[2][kk][c]);
+                }
+                sG[t] = e * dd[0];
+                sG[L::NI + t] = e * dd[1];
+                sG[2 * L::NI + t] = e * dd[2];
+            }
+        }
+        __syncthreads();
+
+        // ---------------- Z: P^T along z ----------------------------------
+        const int jz0 = z0 / R, jy0 = y0 / R;
+        if (eok) {
+            for (int i = threadIdx.x; i < L::GZ; i += kThreads) {
+                const int nz = i % L::PZ;
+                const int r = i / L::PZ;  // (c, ly)
+                const int lo = max(0, R * (nz - 1)), hi = min(TZ, R * (nz + 1));
+                const float* g = sG + r * TZ;
+                float acc = 0.0f;
+                for (int lz = lo; lz < hi; ++lz) {
+                    const int iz = z0 + lz;
+                    const float w1 = w1_of<R>(iz);
+                    acc = fmaf(node_of<R>(iz) == jz0 + nz ? 1.0f - w1 : w1, g[lz], acc);
+                }
+                sGz[i] = acc;
+            }
+        }
+        __syncthreads();
+
+        // ---------------- Y: P^T along y, then x into the accumulators -----
+        if (eok) {
+            const int jx = node_of<R>(pe);
+            const float wx1 = w1_of<R>(pe), wx0 = 1.0f - wx1;
+            if (jx > jA) {  // node plane jA has all its image planes: write it
+                flush(jA, acc0);
+#pragma unroll
+                for (int o = 0; o < L::KO; ++o) {
+                    acc0[o] = acc1[o];
+                    acc1[o] = 0.0f;
+                }
+                jA += 1;
+            }
+#pragma unroll
+            for (int o = 0; o < L::KO; ++o) {
+                const int i = threadIdx.x + o * kThreads;
+                if (i < L::NOUT) {
+                    const int nz = i % L::PZ;
+                    const int ny = (i / L::PZ) % L::PY;
+                    const int c = i / (L::PZ * L::PY);
+                    const int lo = max(0, R * (ny - 1)), hi = min(TY, R * (ny + 1));
+                    float v = 0.0f;
+                    for (int ly = lo; ly < hi; ++ly) {
+                        const int iy = y0 + ly;
+                        const float w1 = w1_of<R>(iy);
+                        v = fmaf(node_of<R>(iy) == jy0 + ny ? 1.0f - w1 : w1,
+                                 sGz[(c * TY + ly) * L::PZ + nz], v);
+                    }
+                    acc0[o] = fmaf(wx0, v, acc0[o]);
+                    acc1[o] = fmaf(wx1, v, acc1[o]);
+                }
+            }
+        }
+        if (k + 1 < CX + 4) build_q(pw + 1);  // sG is no longer read: Q may overwrite it
+        __syncthreads();
+    };
+
+    for (int k = 0; k < CX + 4; k += 3) {
+        step(k, std::integral_constant<int, 0>());
+        step(k + 1, std::integral_constant<int, 1>());
+        step(k + 2, std::integral_constant<int, 2>());
+    }
+    if (GRAD) {
+        flush(jA, acc0);
+        flush(jA + 1, acc1);
+    }
+    const double dt = [&] {
+        double v = wave_sum(dsum);
+        const int w = threadIdx.x >> 6;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[w] = v;
+        __syncthreads();
+        return (red[0] + red[1]) + (red[2] + red[3]);
+    }();
+    if (threadIdx.x == 0) a.dpart[tile] = dt;
+}
+
+template <int TY, int TZ, int R>
+void launch_march_t(const ImagePassArgs& a, int cx, hipStream_t s) {
+    using L = March<TY, TZ, R>;
+    const int blocks = a.ntx * a.nty * a.ntz;
+    const size_t lds = sizeof(float) * L::LDS_FLOATS;
+    if (a.want_grad)
+        hipLaunchKernelGGL((k_image_march<TY, TZ, R, true>), dim3(blocks), dim3(kThreads), lds, s,
+                           a, cx);
+    else
+        hipLaunchKernelGGL((k_image_march<TY, TZ, R, false>), dim3(blocks), dim3(kThreads), lds,
+                           s, a, cx);
+}
+
+}  // namespace
+
+void launch_image_march(const ImagePassArgs& a, int ratio, int cx, hipStream_t s) {
+    if (ratio == 2)
+        launch_march_t<kMY, kMZ, 2>(a, cx, s);
+    else if (ratio == 4)
+        launch_march_t<kMY, kMZ, 4>(a, cx, s);
+}
+
+}  // namespace ngf

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -29,6 +30,7 @@ struct Level {
     int32_t* j0[3] = {nullptr, nullptr, nullptr};
     float* w0[3] = {nullptr, nullptr, nullptr};
     float* w1[3] = {nullptr, nullptr, nullptr};
+    int variant = kTile3D;  // image-pass variant (autotuned or forced)
     int64_t N() const { return static_cast<int64_t>(m[0]) * m[1] * m[2]; }
     int64_t Ny() const { return static_cast<int64_t>(my[0]) * my[1] * my[2]; }
 };
@@ -79,9 +81,14 @@ struct ngf_ctx {
     double lb_gmax = 0.0;
     int lb_evals = 0;
 
-    // pair form scratch
-    float* pair_img = nullptr;
-    size_t pair_img_cap = 0;
+    // image-pass variant: -1 = autotune, else forced for every level
+    int forced_variant = -1;
+    bool tune_loaded = false;
+    std::vector<std::pair<std::string, int>> tune_cache;  // shape key -> variant
+
+    // differentiation form: grid and index maps of the last explicit pair
+    Level pair;
+    std::vector<void*> pair_owned;
 
     // profiling of the image-pass kernel
     bool prof = false;
@@ -135,22 +142,48 @@ bool params_ok(const ngf_params* p, std::string* why) {
 
 int tiles(int m, int t) { return (m + t - 1) / t; }
 
-int64_t part_floats(const Level& L, int ratio) {
-    const int64_t nt = static_cast<int64_t>(tiles(L.m[0], kTX)) * tiles(L.m[1], kTY) *
-                       tiles(L.m[2], kTZ);
-    const int64_t np = static_cast<int64_t>(kTX / ratio + 1) * (kTY / ratio + 1) *
-                       (kTZ / ratio + 1);
-    return nt * 3 * np;
+// Tile geometry of an image-pass variant: image tile extent per axis.
+struct Geo {
+    int tx, ty, tz;
+    int ntx, nty, ntz;
+    int64_t ntiles() const { return static_cast<int64_t>(ntx) * nty * ntz; }
+};
+Geo geometry(const Level& L, int variant) {
+    Geo g{};
+    if (variant == kTile3D) {
+        g.tx = kTX;
+        g.ty = kTY;
+        g.tz = kTZ;
+    } else {
+        g.tx = march_cx(variant);
+        g.ty = kMY;
+        g.tz = kMZ;
+    }
+    g.ntx = tiles(L.m[0], g.tx);
+    g.nty = tiles(L.m[1], g.ty);
+    g.ntz = tiles(L.m[2], g.tz);
+    return g;
 }
-int64_t img_tiles(const Level& L) {
-    return static_cast<int64_t>(tiles(L.m[0], kTX)) * tiles(L.m[1], kTY) * tiles(L.m[2], kTZ);
+int64_t part_floats(const Level& L, int ratio, int variant) {
+    const Geo g = geometry(L, variant);
+    const int64_t np = static_cast<int64_t>(g.tx / ratio + 1) * (g.ty / ratio + 1) *
+                       (g.tz / ratio + 1);
+    return g.ntiles() * 3 * np;
+}
+bool pow2(double h) {
+    int e = 0;
+    return std::frexp(h, &e) == 0.5;
 }
 int64_t node_blocks(const Level& L) {
     return static_cast<int64_t>(tiles(L.my[0], kNX)) * tiles(L.my[1], kNY) * tiles(L.my[2], kNZ);
 }
 
 ngf_status ensure_scratch(ngf_ctx* c, const Level& L) {
-    const size_t pf = static_cast<size_t>(part_floats(L, c->p.ratio));
+    size_t pf = 0, nt = 0;
+    for (int v = 0; v < kNumVariants; ++v) {
+        pf = std::max(pf, static_cast<size_t>(part_floats(L, c->p.ratio, v)));
+        nt = std::max(nt, static_cast<size_t>(geometry(L, v).ntiles()));
+    }
     if (pf > c->part_cap) {
         dfree(c->part);
         c->part = nullptr;
@@ -158,7 +191,6 @@ ngf_status ensure_scratch(ngf_ctx* c, const Level& L) {
         if (dalloc(c, &c->part, pf) != NGF_OK) return NGF_E_OOM;
         c->part_cap = pf;
     }
-    const size_t nt = static_cast<size_t>(img_tiles(L));
     if (nt > c->dpart_cap) {
         dfree(c->dpart);
         c->dpart = nullptr;
@@ -227,12 +259,17 @@ ImagePassArgs image_args(ngf_ctx* c, const Level& L, const float* R, const float
     a.nx = L.my[0];
     a.ny = L.my[1];
     a.nz = L.my[2];
-    a.ntx = tiles(L.m[0], kTX);
-    a.nty = tiles(L.m[1], kTY);
-    a.ntz = tiles(L.m[2], kTZ);
+    const Geo g = geometry(L, L.variant);
+    a.ntx = g.ntx;
+    a.nty = g.nty;
+    a.ntz = g.ntz;
     a.hx = L.h[0];
     a.hy = L.h[1];
     a.hz = L.h[2];
+    a.ihx = 1.0 / L.h[0];
+    a.ihy = 1.0 / L.h[1];
+    a.ihz = 1.0 / L.h[2];
+    a.pow2h = pow2(L.h[0]) && pow2(L.h[1]) && pow2(L.h[2]);
     a.fihx = static_cast<float>(1.0 / L.h[0]);
     a.fihy = static_cast<float>(1.0 / L.h[1]);
     a.fihz = static_cast<float>(1.0 / L.h[2]);
@@ -252,15 +289,21 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
                         const float* y, float* grad) {
     const bool want = grad != nullptr;
     ImagePassArgs a = image_args(c, L, R, T, y, want);
+    auto launch = [&] {
+        if (L.variant == kTile3D)
+            launch_image_pass(a, c->p.ratio, c->stream);
+        else
+            launch_image_march(a, c->p.ratio, march_cx(L.variant), c->stream);
+    };
     if (c->prof && c->nprof < kProfMax) {
         HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof], c->stream));
-        launch_image_pass(a, c->p.ratio, c->stream);
+        launch();
         HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof + 1], c->stream));
         c->nprof++;
         c->prof_vox += L.N();
         c->prof_nodes += L.Ny();
     } else {
-        launch_image_pass(a, c->p.ratio, c->stream);
+        launch();
     }
     HIPCHK(c, hipGetLastError());
     NodePassArgs b{};
@@ -275,9 +318,10 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
     b.ntx = a.ntx;
     b.nty = a.nty;
     b.ntz = a.ntz;
-    b.bx = kTX / c->p.ratio;
-    b.by = kTY / c->p.ratio;
-    b.bz = kTZ / c->p.ratio;
+    const Geo g = geometry(L, L.variant);
+    b.bx = g.tx / c->p.ratio;
+    b.by = g.ty / c->p.ratio;
+    b.bz = g.tz / c->p.ratio;
     b.nbx = tiles(L.my[0], kNX);
     b.nby = tiles(L.my[1], kNY);
     b.nbz = tiles(L.my[2], kNZ);
@@ -291,11 +335,13 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
     b.alpha_hbary = static_cast<float>(c->p.alpha * hbary);
     b.alpha = static_cast<float>(c->p.alpha);
     b.want_grad = want ? 1 : 0;
+    b.gather = 1;
+    b.gscale = nullptr;
     launch_node_pass(b, c->stream);
     HIPCHK(c, hipGetLastError());
     ReduceArgs r{};
     r.dpart = c->dpart;
-    r.nd = static_cast<int>(img_tiles(L));
+    r.nd = static_cast<int>(g.ntiles());
     r.spart = c->spart;
     r.ns = static_cast<int>(node_blocks(L));
     r.gpart = c->gpart;
@@ -314,6 +360,95 @@ ngf_status read_jds(ngf_ctx* c) {
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return NGF_OK;
+}
+
+std::string tune_key(const Level& L, int ratio) {
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "gfx950 %d %d %d r%d", L.m[0], L.m[1], L.m[2], ratio);
+    return buf;
+}
+
+void tune_cache_load(ngf_ctx* c) {
+    const char* path = std::getenv("NGF_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[32];
+    int m0, m1, m2, r, v;
+    while (std::fscanf(f, "%31s %d %d %d r%d %d", arch, &m0, &m1, &m2, &r, &v) == 6) {
+        if (v < 0 || v >= kNumVariants) continue;
+        char buf[96];
+        std::snprintf(buf, sizeof(buf), "%s %d %d %d r%d", arch, m0, m1, m2, r);
+        c->tune_cache.emplace_back(buf, v);
+    }
+    std::fclose(f);
+}
+
+void tune_cache_store(const std::string& key, int v) {
+    const char* path = std::getenv("NGF_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d\n", key.c_str(), v);
+    std::fclose(f);
+}
+
+// Pick the image-pass variant of every level: forced, cached for this shape,
+// or the fastest of all variants over three timed evaluations at the identity
+// (whole evaluation: image pass, node pass and reduction).
+ngf_status autotune(ngf_ctx* c) {
+    if (c->forced_variant >= 0) {
+        for (Level& L : c->lv) L.variant = c->forced_variant;
+        return NGF_OK;
+    }
+    if (!c->tune_loaded) {
+        tune_cache_load(c);
+        c->tune_loaded = true;
+    }
+    const bool prof = c->prof;
+    c->prof = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    ngf_status st = NGF_OK;
+    for (Level& L : c->lv) {
+        const std::string key = tune_key(L, c->p.ratio);
+        int found = -1;
+        for (auto& kv : c->tune_cache)
+            if (kv.first == key) found = kv.second;
+        if (found >= 0) {
+            L.variant = found;
+            continue;
+        }
+        launch_identity(c->ltmp, L.my[0], L.my[1], L.my[2], L.hy[0], L.hy[1], L.hy[2],
+                        c->stream);
+        int best = kTile3D;
+        float best_ms = 1e30f;
+        for (int v = 0; v < kNumVariants && st == NGF_OK; ++v) {
+            L.variant = v;
+            st = enqueue_eval(c, L, L.R, L.T, c->ltmp, c->lgt);
+            if (st != NGF_OK) break;
+            if (hipEventRecord(e0, c->stream) != hipSuccess) st = NGF_E_HIP;
+            for (int r = 0; r < 3 && st == NGF_OK; ++r)
+                st = enqueue_eval(c, L, L.R, L.T, c->ltmp, c->lgt);
+            if (st == NGF_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = NGF_E_HIP;
+            float ms = 0.0f;
+            if (st == NGF_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = fail(c, NGF_E_HIP, "autotune timing failed");
+            if (st == NGF_OK && ms < best_ms) {
+                best_ms = ms;
+                best = v;
+            }
+        }
+        L.variant = best;
+        c->tune_cache.emplace_back(key, best);
+        tune_cache_store(key, best);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->prof = prof;
+    return st;
 }
 
 ngf_status check_level(const ngf_ctx* c, int level) {
@@ -382,8 +517,9 @@ void ngf_destroy(ngf_ctx* c) {
                     static_cast<void*>(c->lyt), static_cast<void*>(c->lgt),
                     static_cast<void*>(c->ld), static_cast<void*>(c->ltmp),
                     static_cast<void*>(c->hist), static_cast<void*>(c->st),
-                    static_cast<void*>(c->dotpart), static_cast<void*>(c->pair_img)})
+                    static_cast<void*>(c->dotpart)})
         dfree(p);
+    for (void* p : c->pair_owned) dfree(p);
     if (c->host_jds) (void)hipHostFree(c->host_jds);
     if (c->host_st) (void)hipHostFree(c->host_st);
     delete c;
@@ -484,6 +620,31 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
         free_pyramid(c);
         return fail(c, NGF_E_NONFINITE, "R or T holds NaN or infinity");
     }
+    const ngf_status ts = autotune(c);
+    if (ts != NGF_OK) return ts;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NGF_OK;
+}
+
+ngf_status ngf_set_kernel(ngf_ctx* c, int32_t variant) {
+    if (!c) return NGF_E_ARG;
+    if (variant < -1 || variant >= kNumVariants) return fail(c, NGF_E_ARG, "unknown variant");
+    c->forced_variant = variant;
+    if (!c->lv.empty()) {
+        if (variant >= 0) {
+            for (Level& L : c->lv) L.variant = variant;
+        } else {
+            return autotune(c);
+        }
+    }
+    return NGF_OK;
+}
+
+ngf_status ngf_get_kernel(const ngf_ctx* c, int32_t level, int32_t* variant) {
+    if (!c || !variant) return NGF_E_ARG;
+    const ngf_status s = check_level(c, level);
+    if (s != NGF_OK) return s;
+    *variant = c->lv[level].variant;
     return NGF_OK;
 }
 
@@ -741,6 +902,30 @@ ngf_status ngf_register(ngf_ctx* c, const float* R, const float* T, const ngf_gr
     return NGF_OK;
 }
 
+ngf_status ngf_apply_P(ngf_ctx* c, int32_t level, const float* y, float* yhat) {
+    if (!c) return NGF_E_ARG;
+    const ngf_status s = check_level(c, level);
+    if (s != NGF_OK) return fail(c, s, "no pyramid or bad level");
+    if (!y || !yhat) return fail(c, NGF_E_ARG, "null pointer");
+    const Level& L = c->lv[level];
+    launch_apply_P(L.j0, L.w0, L.w1, L.m, L.my, y, yhat, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return NGF_OK;
+}
+
+ngf_status ngf_apply_PT(ngf_ctx* c, int32_t level, const float* z, float* out, int32_t scheme) {
+    if (!c) return NGF_E_ARG;
+    const ngf_status s = check_level(c, level);
+    if (s != NGF_OK) return fail(c, s, "no pyramid or bad level");
+    if (!z || !out) return fail(c, NGF_E_ARG, "null pointer");
+    if (scheme < 0 || scheme > 2) return fail(c, NGF_E_ARG, "scheme must be 0, 1 or 2");
+    const Level& L = c->lv[level];
+    if (scheme != 0) launch_fill(out, 3 * L.Ny(), 0.0f, c->stream);
+    launch_apply_PT(L.j0, L.w0, L.w1, L.m, L.my, z, out, scheme, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return NGF_OK;
+}
+
 ngf_status ngf_set_profiling(ngf_ctx* c, int32_t enable) {
     if (!c) return NGF_E_ARG;
     if (enable && c->ev.empty()) {
@@ -775,17 +960,103 @@ ngf_status ngf_kernel_time(ngf_ctx* c, int32_t* launches, double* total_ms, int6
 }
 
 ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], const float* R,
-                         const float* T, const float* y, double* J, float* grad_y,
-                         float* grad_T) {
-    (void)g;
-    (void)my;
-    (void)R;
-    (void)T;
-    (void)y;
-    (void)J;
-    (void)grad_y;
-    (void)grad_T;
-    return fail(c, NGF_E_STATE, "ngf_eval_pair is not built yet");
+                         const float* T, const float* y, const double* gscale, double* J,
+                         double* J_dev, float* grad_y, float* grad_T) {
+    if (!c) return NGF_E_ARG;
+    if (!g || !my || !R || !T || !y) return fail(c, NGF_E_ARG, "null argument");
+    const int r = c->p.ratio;
+    int64_t N = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (!(std::isfinite(g->h[d]) && g->h[d] > 0.0)) return fail(c, NGF_E_ARG, "bad spacing");
+        if (g->m[d] < 4 || g->m[d] % r != 0 || my[d] != g->m[d] / r + 1)
+            return fail(c, NGF_E_SHAPE, "need m_d >= 4, divisible by ratio, my_d = m_d/ratio + 1");
+        N *= g->m[d];
+    }
+    if (N >= (static_cast<int64_t>(1) << 31)) return fail(c, NGF_E_SHAPE, "image too large");
+    Level& P = c->pair;
+    bool same = true;
+    for (int d = 0; d < 3; ++d) same = same && P.m[d] == g->m[d] && P.h[d] == g->h[d];
+    if (!same || P.j0[0] == nullptr) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (void* p : c->pair_owned) dfree(p);
+        c->pair_owned.clear();
+        for (int d = 0; d < 3; ++d) {
+            P.m[d] = g->m[d];
+            P.h[d] = g->h[d];
+            P.my[d] = my[d];
+            P.hy[d] = P.m[d] * P.h[d] / (P.my[d] - 1);
+            if (dalloc(c, &P.j0[d], P.m[d]) != NGF_OK || dalloc(c, &P.w0[d], P.m[d]) != NGF_OK ||
+                dalloc(c, &P.w1[d], P.m[d]) != NGF_OK)
+                return NGF_E_OOM;
+            c->pair_owned.push_back(P.j0[d]);
+            c->pair_owned.push_back(P.w0[d]);
+            c->pair_owned.push_back(P.w1[d]);
+            launch_index_map(P.j0[d], P.w0[d], P.w1[d], P.m[d], P.my[d], c->stream);
+        }
+        HIPCHK(c, hipGetLastError());
+    }
+    P.variant = kTile3D;  // the scatter form lives in the 3D-tile kernel
+    if (ensure_scratch(c, P) != NGF_OK) return NGF_E_OOM;
+    const bool want = grad_y != nullptr || grad_T != nullptr;
+    if (grad_y) launch_fill(grad_y, 3 * P.Ny(), 0.0f, c->stream);
+    if (grad_T) launch_fill(grad_T, P.N(), 0.0f, c->stream);
+    ImagePassArgs a = image_args(c, P, R, T, y, want);
+    a.gy_atomic = grad_y;
+    a.gT_atomic = grad_T;
+    a.gscale = gscale;
+    if (want)
+        launch_image_pass_atomic(a, r, c->stream);
+    else
+        launch_image_pass(a, r, c->stream);
+    HIPCHK(c, hipGetLastError());
+    NodePassArgs b{};
+    b.y = y;
+    b.part = nullptr;
+    b.grad = grad_y;
+    b.spart = c->spart;
+    b.gpart = c->gpart;
+    b.nx = P.my[0];
+    b.ny = P.my[1];
+    b.nz = P.my[2];
+    b.nbx = tiles(P.my[0], kNX);
+    b.nby = tiles(P.my[1], kNY);
+    b.nbz = tiles(P.my[2], kNZ);
+    b.hyx = P.hy[0];
+    b.hyy = P.hy[1];
+    b.hyz = P.hy[2];
+    b.ihy2x = static_cast<float>(1.0 / (P.hy[0] * P.hy[0]));
+    b.ihy2y = static_cast<float>(1.0 / (P.hy[1] * P.hy[1]));
+    b.ihy2z = static_cast<float>(1.0 / (P.hy[2] * P.hy[2]));
+    const double hbary = P.hy[0] * P.hy[1] * P.hy[2];
+    b.alpha_hbary = static_cast<float>(c->p.alpha * hbary);
+    b.alpha = static_cast<float>(c->p.alpha);
+    b.want_grad = grad_y ? 1 : 0;
+    b.gather = 0;
+    b.gscale = gscale;
+    launch_node_pass(b, c->stream);
+    HIPCHK(c, hipGetLastError());
+    ReduceArgs rd{};
+    rd.dpart = c->dpart;
+    rd.nd = static_cast<int>(geometry(P, kTile3D).ntiles());
+    rd.spart = c->spart;
+    rd.ns = static_cast<int>(node_blocks(P));
+    rd.gpart = c->gpart;
+    rd.ng = grad_y ? rd.ns : 0;
+    rd.half_hbar = 0.5 * P.h[0] * P.h[1] * P.h[2];
+    rd.half_hbary = 0.5 * hbary;
+    rd.alpha = c->p.alpha;
+    rd.out = c->jds;
+    launch_reduce(rd, c->stream);
+    HIPCHK(c, hipGetLastError());
+    if (J_dev)
+        HIPCHK(c, hipMemcpyAsync(J_dev, c->jds, sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream));
+    if (J) {
+        if (read_jds(c) != NGF_OK) return NGF_E_HIP;
+        *J = c->host_jds[0];
+        if (!std::isfinite(*J)) return fail(c, NGF_E_NONFINITE, "J is not finite");
+    }
+    return NGF_OK;
 }
 
 }  // extern "C"

@@ -16,8 +16,14 @@ constexpr int kBasisG = 2 * kSlots;             // basis index of the gradient
 // Image-pass tile (voxels per axis).  Tiles are aligned to the deformation
 // grid: each extent is a multiple of the grid ratio.
 constexpr int kTX = 8, kTY = 8, kTZ = 32;
+// Marching image pass: (y, z) tile; the x chunk is a run-time choice.
+constexpr int kMY = 16, kMZ = 64;
 // Node-pass tile (nodes per axis).
 constexpr int kNX = 4, kNY = 8, kNZ = 32;
+
+// Image-pass variants the autotuner chooses from.
+enum Variant { kTile3D = 0, kMarch8 = 1, kMarch20 = 2, kMarch32 = 3, kNumVariants = 4 };
+inline int march_cx(int v) { return v == kMarch8 ? 8 : (v == kMarch20 ? 20 : 32); }
 
 // One pyramid level as the kernels see it.
 struct LevelView {
@@ -45,11 +51,17 @@ struct ImagePassArgs {
     int nx, ny, nz;        // deformation nodes
     int ntx, nty, ntz;     // tiles per axis
     double hx, hy, hz;     // spacing (float64: continuous index of the warp)
+    double ihx, ihy, ihz;  // 1 / h, used only when every h is a power of two
+    int pow2h;             // 1: every spacing is a power of two (exact reciprocal)
     float fihx, fihy, fihz;        // 1 / h in float32
     float i2hx, i2hy, i2hz;        // 1 / (2 h)
     float tau, rho;
     float hbar;            // h_x h_y h_z
     int want_grad;         // 0: value only
+    // differentiation form: P^T and dJ/dT by atomic scatter (null: not wanted)
+    float* gy_atomic;      // [3][my], accumulated in place (zeroed beforehand)
+    float* gT_atomic;      // [mx][my][mz], accumulated in place (zeroed beforehand)
+    const double* gscale;  // device scalar multiplying both (null: 1)
 };
 
 struct NodePassArgs {
@@ -67,6 +79,8 @@ struct NodePassArgs {
     float alpha_hbary;     // alpha * hbar^y
     float alpha;
     int want_grad;
+    int gather;            // 1: sum the image-tile partials; 0: grad already holds grad D
+    const double* gscale;  // device scalar multiplying alpha grad S when gather == 0
 };
 
 struct ReduceArgs {
@@ -102,9 +116,20 @@ void launch_identity(float* y, int nx, int ny, int nz, double hx, double hy, dou
                      hipStream_t s);
 void launch_prolongate(const float* yc, float* yf, int cx, int cy, int cz, hipStream_t s);
 void launch_image_pass(const ImagePassArgs& a, int ratio, hipStream_t s);
+void launch_image_march(const ImagePassArgs& a, int ratio, int cx, hipStream_t s);
 void launch_node_pass(const NodePassArgs& a, hipStream_t s);
 void launch_reduce(const ReduceArgs& a, hipStream_t s);
 void launch_check_finite(const float* v, int64_t n, int* flag, hipStream_t s);
+void launch_fill(float* p, int64_t n, float v, hipStream_t s);
+void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s);
+
+// standalone grid conversion (P, and P^T by gather / atomic scatter / red-black)
+void launch_apply_P(const int32_t* const j0[3], const float* const w0[3],
+                    const float* const w1[3], const int m[3], const int n[3], const float* y,
+                    float* yh, hipStream_t s);
+void launch_apply_PT(const int32_t* const j0[3], const float* const w0[3],
+                     const float* const w1[3], const int m[3], const int n[3], const float* z,
+                     float* out, int scheme, hipStream_t s);
 
 // L-BFGS vector kernels
 void launch_lb_solve(LbState* st, hipStream_t s);
@@ -120,11 +145,5 @@ void launch_lb_gram_update(LbState* st, const double* dotpart, int nblocks,
 void launch_lb_init(LbState* st, int mem, double hmin, const double* jds, hipStream_t s);
 int lb_dot_blocks(int64_t n);
 
-// autograd form (scatter adjoints)
-void launch_pair_pass(const ImagePassArgs& a, float* gy_img, float* gT, hipStream_t s);
-void launch_scatter_PT(const float* dimg, float* gy, int mx, int my, int mz, int nx, int ny,
-                       int nz, const int32_t* j0x, const int32_t* j0y, const int32_t* j0z,
-                       const float* w0x, const float* w0y, const float* w0z,
-                       const float* w1x, const float* w1y, const float* w1z, hipStream_t s);
 
 }  // namespace ngf

@@ -84,8 +84,12 @@ def load():
         "ngf_register": ([_P, _P, _P, ctypes.POINTER(Grid), _P, i32, ctypes.POINTER(Report)], i32),
         "ngf_register_levels": ([_P, _P, ctypes.POINTER(Report)], i32),
         "ngf_eval_pair": ([_P, ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_int32 * 3), _P, _P,
-                           _P, ctypes.POINTER(f64), _P, _P], i32),
+                           _P, _P, ctypes.POINTER(f64), _P, _P, _P], i32),
         "ngf_set_profiling": ([_P, i32], i32),
+        "ngf_set_kernel": ([_P, i32], i32),
+        "ngf_apply_P": ([_P, i32, _P, _P], i32),
+        "ngf_apply_PT": ([_P, i32, _P, _P, i32], i32),
+        "ngf_get_kernel": ([_P, i32, ctypes.POINTER(i32)], i32),
         "ngf_kernel_time": ([_P, ctypes.POINTER(i32), ctypes.POINTER(f64),
                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
                             i32),
@@ -296,8 +300,15 @@ class Context:
         return y, self._report(rep)
 
     # -- differentiation form -------------------------------------------------
-    def eval_pair(self, R, T, y, h=(1.0, 1.0, 1.0), grad_y=True, grad_T=True):
-        """J and gradients with respect to y and T on an explicit pair."""
+    def eval_pair(self, R, T, y, h=(1.0, 1.0, 1.0), grad_y=True, grad_T=True, gscale=None,
+                  J_dev=None, sync=True):
+        """J and gradients with respect to y and T on an explicit pair.
+
+        Returns (J or None, grad_y or None, grad_T or None).  ``gscale`` is an
+        optional device float64 scalar multiplying both gradients; ``J_dev``
+        an optional device float64 scalar receiving J; with ``sync=False`` J
+        is not brought to the host.
+        """
         self._f32(R, name="R")
         self._f32(T, R.shape, name="T")
         my = tuple(int(R.shape[d]) // self.p.ratio + 1 for d in range(3))
@@ -306,10 +317,46 @@ class Context:
         myc = (ctypes.c_int32 * 3)(*my)
         gy = torch.empty_like(y) if grad_y else None
         gT = torch.empty_like(T) if grad_T else None
+        for t, name in ((gscale, "gscale"), (J_dev, "J_dev")):
+            if t is not None and not (t.dtype == torch.float64 and t.is_cuda and t.numel() == 1):
+                raise TypeError(f"{name} must be a one-element float64 tensor on the GPU")
         J = ctypes.c_double()
         self._chk(self.lib.ngf_eval_pair(self.h, ctypes.byref(g), ctypes.byref(myc), _ptr(R),
-                                         _ptr(T), _ptr(y), ctypes.byref(J), _ptr(gy), _ptr(gT)))
-        return J.value, gy, gT
+                                         _ptr(T), _ptr(y), _ptr(gscale),
+                                         ctypes.byref(J) if sync else None, _ptr(J_dev),
+                                         _ptr(gy), _ptr(gT)))
+        return (J.value if sync else None), gy, gT
+
+    # -- standalone grid conversion -----------------------------------------
+    PT_SCHEMES = {"gather": 0, "atomic": 1, "redblack": 2}
+
+    def apply_P(self, level, y):
+        li = self.level_info(level)
+        self._f32(y, (3,) + li.my, "y")
+        yh = torch.empty((3,) + li.m, dtype=torch.float32, device=self.device)
+        self._chk(self.lib.ngf_apply_P(self.h, int(level), _ptr(y), _ptr(yh)))
+        return yh
+
+    def apply_PT(self, level, z, scheme="gather"):
+        li = self.level_info(level)
+        self._f32(z, (3,) + li.m, "z")
+        out = torch.empty((3,) + li.my, dtype=torch.float32, device=self.device)
+        self._chk(self.lib.ngf_apply_PT(self.h, int(level), _ptr(z), _ptr(out),
+                                        int(self.PT_SCHEMES.get(scheme, scheme))))
+        return out
+
+    # -- kernel choice --------------------------------------------------------
+    VARIANTS = {"auto": -1, "tile3d": 0, "march8": 1, "march20": 2, "march32": 3}
+
+    def set_kernel(self, variant):
+        """Image-pass variant: 'auto' (autotune), 'tile3d', 'march8/20/32', or its number."""
+        v = self.VARIANTS.get(variant, variant)
+        self._chk(self.lib.ngf_set_kernel(self.h, int(v)))
+
+    def get_kernel(self, level):
+        v = ctypes.c_int32()
+        self._chk(self.lib.ngf_get_kernel(self.h, int(level), ctypes.byref(v)))
+        return v.value
 
     # -- profiling -----------------------------------------------------------
     def set_profiling(self, enable=True):

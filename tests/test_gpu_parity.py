@@ -45,21 +45,31 @@ def _y(prob, amp, seed, spacing=8.0):
     return (prob.identity() + d).astype(np.float32)
 
 
-def _check_eval(ngf, ctx, level, prob, y32, tag):
-    _say(f"[parity] {tag} level={level} m={prob.m} my={prob.my}")
-    J, g, (D, S) = ctx.eval_J_grad(level, _t(y32))
+VARIANTS = ("tile3d", "march8", "march20", "march32")
+
+
+def _check_eval(ngf, ctx, level, prob, y32, tag, variants=VARIANTS):
+    """Every image-pass variant against the oracle at the same y."""
     Jo, go, (Do, So) = O.eval_J_grad(prob, y32.astype(np.float64))
-    g = _np(g).astype(np.float64)
-    assert np.all(np.isfinite(g))
-    assert abs(J - Jo) <= J_RTOL * abs(Jo), (tag, J, Jo)
-    assert abs(D - Do) <= J_RTOL * abs(Do) + 1e-12, (tag, D, Do)
-    assert abs(S - So) <= 1e-4 * abs(So) + 1e-9 * abs(Jo), (tag, S, So)
-    err = np.linalg.norm(g - go) / np.linalg.norm(go)
-    assert err <= G_RTOL, (tag, err)
-    # value-only evaluation gives the same J
-    Jv, gv, _ = ctx.eval_J_grad(level, _t(y32), want_grad=False)
-    assert gv is None and Jv == J
-    return J, g
+    chosen = ctx.get_kernel(level)
+    out = {}
+    for v in variants:
+        _say(f"[parity] {tag} level={level} m={prob.m} my={prob.my} kernel={v}")
+        ctx.set_kernel(v)
+        J, g, (D, S) = ctx.eval_J_grad(level, _t(y32))
+        g = _np(g).astype(np.float64)
+        assert np.all(np.isfinite(g))
+        assert abs(J - Jo) <= J_RTOL * abs(Jo), (tag, v, J, Jo)
+        assert abs(D - Do) <= J_RTOL * abs(Do) + 1e-12, (tag, v, D, Do)
+        assert abs(S - So) <= 1e-4 * abs(So) + 1e-9 * abs(Jo), (tag, v, S, So)
+        err = np.linalg.norm(g - go) / np.linalg.norm(go)
+        assert err <= G_RTOL, (tag, v, err)
+        # value-only evaluation gives the same J
+        Jv, gv, _ = ctx.eval_J_grad(level, _t(y32), want_grad=False)
+        assert gv is None and abs(Jv - J) <= 1e-12 * abs(J)
+        out[v] = (J, g)
+    ctx.set_kernel(chosen)
+    return out
 
 
 def test_index_maps_identity_and_pyramid_bit_exact(gpu_lib):
@@ -144,8 +154,10 @@ def test_eval_parity_ct_pyramid_levels(gpu_lib):
 
 @pytest.mark.parametrize("m,h,ratio", [((44, 36, 40), (1.0, 1.5, 0.75), 2),
                                        ((24, 16, 72), (2.0, 1.0, 1.0), 2),
+                                       ((36, 20, 132), (1.0, 1.0, 1.0), 2),
                                        ((64, 48, 32), (1.0, 1.0, 2.0), 4),
-                                       ((16, 16, 16), (1.0, 1.0, 1.0), 4)])
+                                       ((16, 16, 16), (1.0, 1.0, 1.0), 4),
+                                       ((28, 24, 68), (0.5, 2.0, 1.0), 4)])
 def test_eval_parity_ragged_anisotropic(gpu_lib, m, h, ratio):
     ngf = gpu_lib
     pr = synth.ct_phantom_pair(m, h, seed_R=21, seed_u=22, max_disp=3.0, cp_spacing=8.0)
@@ -157,15 +169,31 @@ def test_eval_parity_ragged_anisotropic(gpu_lib, m, h, ratio):
         _check_eval(ngf, ctx, 0, prob, _y(prob, amp, seed, spacing=4.0), f"ragged {m} r{ratio}")
 
 
-def test_identical_images_give_zero(gpu_lib):
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_identical_images_give_zero(gpu_lib, variant):
     ngf = gpu_lib
     pr = synth.ct_phantom_pair((64, 64, 64), seed_R=5, seed_u=6)
     ctx = _ctx(ngf, alpha=0.0, tau=10.0, rho=10.0, levels=1)
     ctx.build_pyramid(_t(pr.R), _t(pr.R))
+    ctx.set_kernel(variant)
     J, g, (D, S) = ctx.eval_J_grad(0, ctx.identity(0))
     # Lagrange's form of 1 - r^2 is exactly zero for identical gradients
     assert J == 0.0 and D == 0.0 and S == 0.0
     assert float(g.abs().max()) == 0.0
+
+
+def test_autotuner_choice_is_valid_and_cached(gpu_lib):
+    ngf = gpu_lib
+    pr = synth.ct_phantom_pair((128, 128, 128), seed_R=3, seed_u=4)
+    ctx = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=3)
+    ctx.build_pyramid(_t(pr.R), _t(pr.T))
+    first = [ctx.get_kernel(lev) for lev in range(3)]
+    assert all(v in (0, 1, 2, 3) for v in first)
+    ctx.build_pyramid(_t(pr.R), _t(pr.T))  # same shapes: cached choice
+    assert [ctx.get_kernel(lev) for lev in range(3)] == first
+    _say(f"[autotune] 128^3 pyramid choices {first}")
+    ctx.set_kernel("march32")
+    assert [ctx.get_kernel(lev) for lev in range(3)] == [3, 3, 3]
 
 
 def test_eval_deterministic(gpu_lib):
@@ -277,3 +305,24 @@ def test_error_paths(gpu_lib):
     with pytest.raises(ngf.NgfError) as e:
         ctx.set_params(ratio=4)
     assert e.value.status == ngf.E_STATE
+
+
+@pytest.mark.parametrize("m,ratio", [((48, 40, 36), 2), ((64, 32, 48), 4)])
+def test_grid_conversion_operators(gpu_lib, m, ratio):
+    """P and the three P^T schemes against the oracle's P and Eq. 3 gather."""
+    ngf = gpu_lib
+    pr = synth.blob_phantom_pair(m)
+    ctx = _ctx(ngf, levels=1, ratio=ratio)
+    ctx.build_pyramid(_t(pr.R), _t(pr.T), (1.0, 0.5, 2.0))
+    li = ctx.level_info(0)
+    rng = np.random.default_rng(17)
+    y = rng.standard_normal((3,) + li.my).astype(np.float32)
+    z = rng.standard_normal((3,) + li.m).astype(np.float32)
+    yh = _np(ctx.apply_P(0, _t(y))).astype(np.float64)
+    want = O.apply_P(y.astype(np.float64), li.m, li.my)
+    assert np.max(np.abs(yh - want)) <= 1e-6 * np.abs(want).max()
+    wantT = O.apply_PT(z.astype(np.float64), li.m, li.my)
+    for scheme in ("gather", "atomic", "redblack"):
+        _say(f"[gridconv] {m} ratio={ratio} P^T {scheme}")
+        out = _np(ctx.apply_PT(0, _t(z), scheme)).astype(np.float64)
+        assert np.max(np.abs(out - wantT)) <= 1e-5 * np.abs(wantT).max(), scheme
