@@ -106,6 +106,8 @@ typedef struct {
     int32_t evals[NGF_MAX_LEVELS];
     int32_t info[NGF_MAX_LEVELS];
     double J[NGF_MAX_LEVELS];
+    double ms[NGF_MAX_LEVELS]; /* host wall time of the level: start of the
+                                  level to its last queued work done */
 } ngf_report;
 
 /* Library version string (static storage). */
@@ -142,13 +144,16 @@ ngf_status ngf_set_params(ngf_ctx* ctx, const ngf_params* p);
 ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
                              const ngf_grid* g, int32_t host_ptrs);
 
-/* Image-grid kernel of the evaluation.  `variant`: -1 = autotune (default:
+/* Image-grid kernel of the evaluation.  `variant`: -2 = by level size (no
+ * timing runs: at least 8 Mi voxels -> 3, at least 1 Mi -> 4, else 7);
+ * -1 = autotune (default:
  * at ngf_build_pyramid every level times each variant over three evaluations
  * at the identity and keeps the fastest; choices are cached per image shape
  * in the context and, if the environment variable NGF_TUNE_CACHE names a
  * file, appended to and read from that file); 0 = 3D tiles of 8x8x32 voxels
  * with a two-voxel halo; 1, 2, 3 = x-marching over 16x64 (y, z) tiles in
- * chunks of 8, 20 or 32 planes.  All variants compute the same quantities;
+ * chunks of 8, 20 or 32 planes; 4, 5, 6 = the same over 16x32 tiles; 7 = 3D
+ * tiles of 4x8x32 voxels.  All variants compute the same quantities;
  * only the summation order of the P^T partial sums differs.  Applies at once
  * to a built pyramid.  ngf_get_kernel reports a level's choice. */
 ngf_status ngf_set_kernel(ngf_ctx* ctx, int32_t variant);
@@ -271,6 +276,39 @@ ngf_status ngf_apply_PT(ngf_ctx* ctx, int32_t level, const float* z, float* out,
 ngf_status ngf_set_profiling(ngf_ctx* ctx, int32_t enable);
 ngf_status ngf_kernel_time(ngf_ctx* ctx, int32_t* launches, double* total_ms,
                            int64_t* voxels, int64_t* nodes);
+
+/* Batched form: many independent registrations (one image pair each, any
+ * mix of shapes) on one device, each computed as by ngf_register (Sec. 2:
+ * pyramid, multi-level L-BFGS on Eq. 1).  A host scheduler hands pairs,
+ * largest voxel count first, to `workers` threads (1..16); each worker owns
+ * a context on its own non-blocking stream of the device current at
+ * ngf_batch_create, so pairs run concurrently on the device.  Every pair's
+ * result equals the single-pair ngf_register result for the same
+ * image-pass variant bit for bit.
+ *   ngf_batch_create      params as for ngf_create; the image-pass variant
+ *                         defaults to -2 (by level size; timed selection
+ *                         would be disturbed by the concurrent pairs)
+ *   ngf_batch_set_kernel  variant as for ngf_set_kernel, for every worker
+ *   ngf_batch_register    npairs >= 0; R[i], T[i]: device float32 images of
+ *                         grids[i]; y_out[i]: device float32
+ *                         [3][m0/ratio+1][m1/ratio+1][m2/ratio+1]; `stream`
+ *                         (hipStream_t, NULL = null stream): the call first
+ *                         waits for the work queued there, so the inputs may
+ *                         come from it; reports: NULL or npairs entries.
+ *                         Synchronous: returns when every pair is done.  On
+ *                         failure no further pairs are started, the status
+ *                         of the first failed pair (by index) is returned and
+ *                         ngf_batch_last_error names it; outputs of the other
+ *                         pairs are then unspecified. */
+#define NGF_BATCH_MAX_WORKERS 16
+typedef struct ngf_batch ngf_batch;
+ngf_status ngf_batch_create(const ngf_params* p, int32_t workers, ngf_batch** out);
+void ngf_batch_destroy(ngf_batch* b);
+const char* ngf_batch_last_error(const ngf_batch* b);
+ngf_status ngf_batch_set_kernel(ngf_batch* b, int32_t variant);
+ngf_status ngf_batch_register(ngf_batch* b, int32_t npairs, const float* const* R,
+                              const float* const* T, const ngf_grid* grids,
+                              float* const* y_out, void* stream, ngf_report* reports);
 
 #ifdef __cplusplus
 }

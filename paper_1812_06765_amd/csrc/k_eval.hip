@@ -30,6 +30,16 @@ namespace {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// n / d for 0 <= n < 2^22, d >= 1, with inv = 1/d in float32: the product is
+// within one of the quotient, and one integer correction makes it exact.
+// (An integer division by a run-time divisor costs tens of instructions.)
+__device__ inline int div_small(int n, int d, float inv) {
+    int q = static_cast<int>(static_cast<float>(n) * inv);
+    if (q * d > n) q -= 1;
+    if ((q + 1) * d <= n) q += 1;
+    return q;
+}
+
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     return v;
@@ -72,10 +82,11 @@ struct AxisCell {
     float s;
 };
 
-__device__ inline AxisCell axis_cell(double yhat, double h, double ih, bool pow2h, int m) {
+template <bool POW2>
+__device__ inline AxisCell axis_cell(double yhat, double h, double ih, int m) {
     // with a power-of-two spacing the reciprocal is exact and the product
     // rounds exactly like the quotient
-    double xi = pow2h ? fma(yhat, ih, -0.5) : yhat / h - 0.5;
+    double xi = POW2 ? fma(yhat, ih, -0.5) : yhat / h - 0.5;
     const double hi = static_cast<double>(m - 1);
     const float s = (xi >= 0.0 && xi <= hi) ? 1.0f : 0.0f;
     xi = fmin(fmax(xi, 0.0), hi);
@@ -117,8 +128,8 @@ struct ImageTile {
 // adds each tile's P^T block into a.gy_atomic with float atomics, and stage 3
 // scatters e W(i -> k) into a.gT_atomic (the transpose of the warp), both
 // scaled by *a.gscale.
-template <int TX, int TY, int TZ, int RATIO, bool GRAD, bool ATOMIC>
-__global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
+template <int TX, int TY, int TZ, int RATIO, bool GRAD, bool ATOMIC, bool POW2>
+__device__ __forceinline__ void image_body(const ImagePassArgs& a, int block) {
     using L = ImageTile<TX, TY, TZ, RATIO>;
     extern __shared__ float smem[];
     float* sA = smem;                  // nodes, then v, then P^T staging
@@ -126,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
     float* sG = sTy;                   // dD/dy_hat on the tile (after v is formed)
     __shared__ double red[4];
 
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile(block, a.ntx * a.nty * a.ntz);
     const int tz = tile % a.ntz;
     const int ty = (tile / a.ntz) % a.nty;
     const int tx = tile / (a.ntz * a.nty);
@@ -173,9 +184,9 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
             const double c0 = ay0 * c00 + ay1 * c01, c1 = ay0 * c10 + ay1 * c11;
             yh[c] = ax0 * c0 + ax1 * c1;
         }
-        const AxisCell cx = axis_cell(yh[0], a.hx, a.ihx, a.pow2h, mx);
-        const AxisCell cy = axis_cell(yh[1], a.hy, a.ihy, a.pow2h, my);
-        const AxisCell cz = axis_cell(yh[2], a.hz, a.ihz, a.pow2h, mz);
+        const AxisCell cx = axis_cell<POW2>(yh[0], a.hx, a.ihx, mx);
+        const AxisCell cy = axis_cell<POW2>(yh[1], a.hy, a.ihy, my);
+        const AxisCell cz = axis_cell<POW2>(yh[2], a.hz, a.ihz, mz);
         const float* Tb = a.T + cx.i0 * sxT + cy.i0 * mz + cz.i0;
         if (ATOMIC && cb != nullptr) {
             *cb = cx.i0 * sxT + cy.i0 * mz + cz.i0;
@@ -284,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
         const float aa = fmaf(gTx, gTx, fmaf(gTy, gTy, fmaf(gTz, gTz, tau * tau)));
         const float bb = fmaf(gRx, gRx, fmaf(gRy, gRy, fmaf(gRz, gRz, rho * rho)));
         const float ab = fmaf(gTx, gRx, fmaf(gTy, gRy, fmaf(gTz, gRz, tau * rho)));
-        const float iaa = 1.0f / aa, ibb = 1.0f / bb;
+        const float iaa = __builtin_amdgcn_rcpf(aa), ibb = __builtin_amdgcn_rcpf(bb);
         if (hx + hy + hz == 0 && gx < mx && gy < my && gz < mz) {
             // 1 - r^2 by Lagrange's identity on a = (grad T, tau), b = (grad R, rho):
             // |a|^2 |b|^2 - <a,b>^2 = sum_{p<q} (a_p b_q - a_q b_p)^2.  Each term is the
@@ -305,13 +316,21 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
             dsum += static_cast<double>(lag * iaa * ibb);
         }
         if (GRAD) {
-            // v = -hbar r/(nT nR) (grad R - (c/nT^2) grad T) = -hbar (ab/(aa bb)) (b - (ab/aa) a);
-            // ab/aa by a correctly rounded division is exactly 1 when a = b, so v = 0 there
-            const float k1 = ab / aa;
-            const float coef = -a.hbar * ab * iaa * ibb;
-            float vx = coef * fmaf(-k1, gTx, gRx);
-            float vy = coef * fmaf(-k1, gTy, gRy);
-            float vz = coef * fmaf(-k1, gTz, gRz);
+            // v = -hbar r/(nT nR) (grad R - (c/nT^2) grad T)
+            //   = -hbar ab/(aa^2 bb) (aa grad R - ab grad T),
+            // with unfused products so that v is exactly 0 when grad T = grad R
+            // (then ab = aa bit for bit and both products round alike)
+            const float coef = -a.hbar * ab * (iaa * iaa) * ibb;
+            float wx, wy, wz;
+            {
+#pragma clang fp contract(off)
+                wx = aa * gRx - ab * gTx;
+                wy = aa * gRy - ab * gTy;
+                wz = aa * gRz - ab * gTz;
+            }
+            float vx = coef * wx;
+            float vy = coef * wy;
+            float vz = coef * wz;
             // outside the domain, the adjoint stencil's end rows are realised by a
             // mirrored ghost: v_d(m) = -v_d(m-1), v_d(-1) = -v_d(0)
             if (gx != cxp) vx = -vx;
@@ -424,8 +443,14 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
 // ------------------------------------------------------------------------
 // node pass
 // ------------------------------------------------------------------------
+template <int TX, int TY, int TZ, int RATIO, bool GRAD, bool ATOMIC, bool POW2>
+__global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
+    image_body<TX, TY, TZ, RATIO, GRAD, ATOMIC, POW2>(a, blockIdx.x);
+}
+
 template <int NX, int NY, int NZ>
-__global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
+__device__ __forceinline__ void node_body(const NodePassArgs& a, int block) {
+    // one workgroup per (node tile, component)
     constexpr int B2X = NX + 4, B2Y = NY + 4, B2Z = NZ + 4, NB2 = B2X * B2Y * B2Z;
     constexpr int B1X = NX + 2, B1Y = NY + 2, B1Z = NZ + 2, NB1 = B1X * B1Y * B1Z;
     constexpr int NT = NX * NY * NZ, KT = NT / kThreads;
@@ -434,7 +459,10 @@ __global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
     __shared__ float sAu[NB1];
     __shared__ double red[4];
 
-    const int blk = blockIdx.x;
+    const int ntile = a.nbx * a.nby * a.nbz;
+    const int bid = xcd_tile(block, 3 * ntile);
+    const int c = bid / ntile;
+    const int blk = bid - c * ntile;
     const int bz = blk % a.nbz;
     const int byy = (blk / a.nbz) % a.nby;
     const int bx = blk / (a.nbz * a.nby);
@@ -443,103 +471,132 @@ __global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
     const int nn = nx * ny * nz;
     const int PX = a.bx + 1, PY = a.by + 1, PZ = a.bz + 1;
     const int NP = PX * PY * PZ;
-
-    double ssum = 0.0, gmax = 0.0, g2 = 0.0;
-    const double hyd[3] = {a.hyx, a.hyy, a.hyz};
     const float sc = (!a.gather && a.gscale != nullptr) ? static_cast<float>(*a.gscale) : 1.0f;
-    for (int c = 0; c < 3; ++c) {
-        const float* yc = a.y + c * nn;
-        for (int i = threadIdx.x; i < NB2; i += kThreads) {
-            const int z = i % B2Z, yy = (i / B2Z) % B2Y, x = i / (B2Z * B2Y);
-            const int gx = clampi(n0x - 2 + x, 0, nx - 1), gy = clampi(n0y - 2 + yy, 0, ny - 1),
-                      gz = clampi(n0z - 2 + z, 0, nz - 1);
-            const int gc = c == 0 ? gx : (c == 1 ? gy : gz);
-            const double X = static_cast<double>(gc) * hyd[c];
-            su[i] = static_cast<float>(static_cast<double>(yc[(gx * ny + gy) * nz + gz]) - X);
+
+    const float ibx = 1.0f / a.bx, iby = 1.0f / a.by, ibz = 1.0f / a.bz;
+    // grad D of this thread's nodes: issued first, it does not depend on LDS.
+    // Gather form: add the (at most 8) image-tile partials of the node, which
+    // completes Eq. 3; scatter form: grad already holds grad D.
+    float gd[KT];
+    for (int k = 0; k < KT; ++k) {
+        const int t = threadIdx.x + k * kThreads;
+        const int lz = t % NZ, ly = (t / NZ) % NY, lx = t / (NZ * NY);
+        const int gx = n0x + lx, gy = n0y + ly, gz = n0z + lz;
+        gd[k] = 0.0f;
+        if (!a.want_grad || gx >= nx || gy >= ny || gz >= nz) continue;
+        if (!a.gather) {
+            gd[k] = a.grad[c * nn + (gx * ny + gy) * nz + gz];
+            continue;
         }
-        __syncthreads();
-        for (int i = threadIdx.x; i < NB1; i += kThreads) {
-            const int z = i % B1Z, yy = (i / B1Z) % B1Y, x = i / (B1Z * B1Y);
-            const int gx = clampi(n0x - 1 + x, 0, nx - 1), gy = clampi(n0y - 1 + yy, 0, ny - 1),
-                      gz = clampi(n0z - 1 + z, 0, nz - 1);
-            const int p = ((gx - n0x + 2) * B2Y + (gy - n0y + 2)) * B2Z + (gz - n0z + 2);
-            const float u0 = su[p];
-            const float lx = su[p + B2Y * B2Z] - 2.0f * u0 + su[p - B2Y * B2Z];
-            const float ly = su[p + B2Z] - 2.0f * u0 + su[p - B2Z];
-            const float lz = su[p + 1] - 2.0f * u0 + su[p - 1];
-            sAu[i] = fmaf(lx, a.ihy2x, fmaf(ly, a.ihy2y, lz * a.ihy2z));
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KT; ++k) {
-            const int t = threadIdx.x + k * kThreads;
-            const int lz = t % NZ, ly = (t / NZ) % NY, lx = t / (NZ * NY);
-            const int gx = n0x + lx, gy = n0y + ly, gz = n0z + lz;
-            if (gx >= nx || gy >= ny || gz >= nz) continue;
-            const int gxc = min(gx + 1, nx - 1), gxm = max(gx - 1, 0);
-            const int gyc = min(gy + 1, ny - 1), gym = max(gy - 1, 0);
-            const int gzc = min(gz + 1, nz - 1), gzm = max(gz - 1, 0);
-            auto at = [&](int x, int y, int z) {
-                return sAu[((x - n0x + 1) * B1Y + (y - n0y + 1)) * B1Z + (z - n0z + 1)];
-            };
-            const float au = at(gx, gy, gz);
-            ssum += static_cast<double>(au) * static_cast<double>(au);
-            if (!a.want_grad) continue;
-            const float lxx = at(gxc, gy, gz) - 2.0f * au + at(gxm, gy, gz);
-            const float lyy = at(gx, gyc, gz) - 2.0f * au + at(gx, gym, gz);
-            const float lzz = at(gx, gy, gzc) - 2.0f * au + at(gx, gy, gzm);
-            const float aau = fmaf(lxx, a.ihy2x, fmaf(lyy, a.ihy2y, lzz * a.ihy2z));
-            // gather the image-tile partials of this node (completes Eq. 3), or
-            // take grad D accumulated by the scatter form
-            float gd = 0.0f;
-            if (!a.gather) gd = a.grad[c * nn + (gx * ny + gy) * nz + gz];
-            const int txh = gx / a.bx, tyh = gy / a.by, tzh = gz / a.bz;
-            const int rx = gx - txh * a.bx, ry = gy - tyh * a.by, rz = gz - tzh * a.bz;
-            for (int ox = 0; ox < (a.gather ? 2 : 0); ++ox) {
-                const int ttx = txh - ox, llx = rx + ox * a.bx;
-                if (ttx < 0 || ttx >= a.ntx || (ox == 1 && rx != 0)) continue;
-                for (int oy = 0; oy < 2; ++oy) {
-                    const int tty = tyh - oy, lly = ry + oy * a.by;
-                    if (tty < 0 || tty >= a.nty || (oy == 1 && ry != 0)) continue;
-                    for (int oz = 0; oz < 2; ++oz) {
-                        const int ttz = tzh - oz, llz = rz + oz * a.bz;
-                        if (ttz < 0 || ttz >= a.ntz || (oz == 1 && rz != 0)) continue;
-                        const int tile = (ttx * a.nty + tty) * a.ntz + ttz;
-                        gd += a.part[(static_cast<int64_t>(tile) * 3 + c) * NP +
-                                     (llx * PY + lly) * PZ + llz];
-                    }
+        const int txh = div_small(gx, a.bx, ibx), tyh = div_small(gy, a.by, iby),
+                  tzh = div_small(gz, a.bz, ibz);
+        const int rx = gx - txh * a.bx, ry = gy - tyh * a.by, rz = gz - tzh * a.bz;
+        const int nox = (rx == 0 && txh > 0) ? 2 : 1, noy = (ry == 0 && tyh > 0) ? 2 : 1,
+                  noz = (rz == 0 && tzh > 0) ? 2 : 1;
+        float acc = 0.0f;
+        for (int ox = 0; ox < nox; ++ox) {
+            const int ttx = txh - ox, llx = rx + ox * a.bx;
+            if (ttx >= a.ntx) continue;
+            for (int oy = 0; oy < noy; ++oy) {
+                const int tty = tyh - oy, lly = ry + oy * a.by;
+                if (tty >= a.nty) continue;
+                for (int oz = 0; oz < noz; ++oz) {
+                    const int ttz = tzh - oz, llz = rz + oz * a.bz;
+                    if (ttz >= a.ntz) continue;
+                    const int tile = (ttx * a.nty + tty) * a.ntz + ttz;
+                    acc += a.part[(static_cast<int64_t>(tile) * 3 + c) * NP +
+                                  (llx * PY + lly) * PZ + llz];
                 }
             }
-            const float g = fmaf(a.alpha_hbary * sc, aau, gd);
-            a.grad[c * nn + (gx * ny + gy) * nz + gz] = g;
-            gmax = fmax(gmax, static_cast<double>(fabsf(g)));
-            g2 += static_cast<double>(g) * static_cast<double>(g);
         }
-        __syncthreads();
+        gd[k] = acc;
+    }
+
+    // u = y - X on the tile and a two-node halo (replicated ghost nodes)
+    const float* yc = a.y + c * nn;
+    const double hyc = c == 0 ? a.hyx : (c == 1 ? a.hyy : a.hyz);
+    for (int i = threadIdx.x; i < NB2; i += kThreads) {
+        const int z = i % B2Z, yy = (i / B2Z) % B2Y, x = i / (B2Z * B2Y);
+        const int gx = clampi(n0x - 2 + x, 0, nx - 1), gy = clampi(n0y - 2 + yy, 0, ny - 1),
+                  gz = clampi(n0z - 2 + z, 0, nz - 1);
+        const int gc = c == 0 ? gx : (c == 1 ? gy : gz);
+        su[i] = static_cast<float>(static_cast<double>(yc[(gx * ny + gy) * nz + gz]) -
+                                   static_cast<double>(gc) * hyc);
+    }
+    __syncthreads();
+    // A u on the tile and a one-node halo (A u of the clamped node)
+    for (int i = threadIdx.x; i < NB1; i += kThreads) {
+        const int z = i % B1Z, yy = (i / B1Z) % B1Y, x = i / (B1Z * B1Y);
+        const int gx = clampi(n0x - 1 + x, 0, nx - 1), gy = clampi(n0y - 1 + yy, 0, ny - 1),
+                  gz = clampi(n0z - 1 + z, 0, nz - 1);
+        const int p = ((gx - n0x + 2) * B2Y + (gy - n0y + 2)) * B2Z + (gz - n0z + 2);
+        const float u0 = su[p];
+        const float lx = su[p + B2Y * B2Z] - 2.0f * u0 + su[p - B2Y * B2Z];
+        const float ly = su[p + B2Z] - 2.0f * u0 + su[p - B2Z];
+        const float lz = su[p + 1] - 2.0f * u0 + su[p - 1];
+        sAu[i] = fmaf(lx, a.ihy2x, fmaf(ly, a.ihy2y, lz * a.ihy2z));
+    }
+    __syncthreads();
+    double ssum = 0.0, gmax = 0.0, g2 = 0.0;
+    for (int k = 0; k < KT; ++k) {
+        const int t = threadIdx.x + k * kThreads;
+        const int lz = t % NZ, ly = (t / NZ) % NY, lx = t / (NZ * NY);
+        const int gx = n0x + lx, gy = n0y + ly, gz = n0z + lz;
+        if (gx >= nx || gy >= ny || gz >= nz) continue;
+        const int q = ((lx + 1) * B1Y + (ly + 1)) * B1Z + (lz + 1);
+        // neighbours of the node, clamped to the grid (replicated ghost nodes)
+        const int dxp = gx + 1 < nx ? B1Y * B1Z : 0, dxm = gx > 0 ? B1Y * B1Z : 0;
+        const int dyp = gy + 1 < ny ? B1Z : 0, dym = gy > 0 ? B1Z : 0;
+        const int dzp = gz + 1 < nz ? 1 : 0, dzm = gz > 0 ? 1 : 0;
+        const float au = sAu[q];
+        ssum += static_cast<double>(au) * static_cast<double>(au);
+        if (!a.want_grad) continue;
+        const float lxx = sAu[q + dxp] - 2.0f * au + sAu[q - dxm];
+        const float lyy = sAu[q + dyp] - 2.0f * au + sAu[q - dym];
+        const float lzz = sAu[q + dzp] - 2.0f * au + sAu[q - dzm];
+        const float aau = fmaf(lxx, a.ihy2x, fmaf(lyy, a.ihy2y, lzz * a.ihy2z));
+        const float g = fmaf(a.alpha_hbary * sc, aau, gd[k]);
+        a.grad[c * nn + (gx * ny + gy) * nz + gz] = g;
+        gmax = fmax(gmax, static_cast<double>(fabsf(g)));
+        g2 += static_cast<double>(g) * static_cast<double>(g);
     }
     const double st = block_sum(ssum, red);
-    if (threadIdx.x == 0) a.spart[blk] = st;
+    if (threadIdx.x == 0) a.spart[bid] = st;
     if (a.want_grad) {
         const double gm = block_max(gmax, red);
         const double gq = block_sum(g2, red);
         if (threadIdx.x == 0) {
-            a.gpart[2 * blk] = gm;
-            a.gpart[2 * blk + 1] = gq;
+            a.gpart[2 * bid] = gm;
+            a.gpart[2 * bid + 1] = gq;
         }
     }
 }
 
-template <int RATIO>
+template <int NX, int NY, int NZ>
+__global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
+    node_body<NX, NY, NZ>(a, blockIdx.x);
+}
+
+template <int TX, int RATIO>
 void launch_image_ratio(const ImagePassArgs& a, hipStream_t s) {
-    using L = ImageTile<kTX, kTY, kTZ, RATIO>;
+    using L = ImageTile<TX, kTY, kTZ, RATIO>;
     const int blocks = a.ntx * a.nty * a.ntz;
     const size_t lds = sizeof(float) * L::LDS_FLOATS;
-    if (a.want_grad)
-        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, true, false>), dim3(blocks),
-                           dim3(kThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, false, false>), dim3(blocks),
-                           dim3(kThreads), lds, s, a);
+    if (a.want_grad) {
+        if (a.pow2h)
+            hipLaunchKernelGGL((k_image_pass<TX, kTY, kTZ, RATIO, true, false, true>),
+                               dim3(blocks), dim3(kThreads), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_image_pass<TX, kTY, kTZ, RATIO, true, false, false>),
+                               dim3(blocks), dim3(kThreads), lds, s, a);
+    } else {
+        if (a.pow2h)
+            hipLaunchKernelGGL((k_image_pass<TX, kTY, kTZ, RATIO, false, false, true>),
+                               dim3(blocks), dim3(kThreads), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_image_pass<TX, kTY, kTZ, RATIO, false, false, false>),
+                               dim3(blocks), dim3(kThreads), lds, s, a);
+    }
 }
 
 template <int RATIO>
@@ -547,17 +604,27 @@ void launch_image_ratio_atomic(const ImagePassArgs& a, hipStream_t s) {
     using L = ImageTile<kTX, kTY, kTZ, RATIO>;
     const int blocks = a.ntx * a.nty * a.ntz;
     const size_t lds = sizeof(float) * L::LDS_FLOATS;
-    hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, true, true>), dim3(blocks),
-                       dim3(kThreads), lds, s, a);
+    if (a.pow2h)
+        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, true, true, true>), dim3(blocks),
+                           dim3(kThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, true, true, false>),
+                           dim3(blocks), dim3(kThreads), lds, s, a);
 }
 
 }  // namespace
 
-void launch_image_pass(const ImagePassArgs& a, int ratio, hipStream_t s) {
-    switch (ratio) {
-        case 2: launch_image_ratio<2>(a, s); break;
-        case 4: launch_image_ratio<4>(a, s); break;
-        default: break;
+void launch_image_pass(const ImagePassArgs& a, int ratio, hipStream_t s, bool small) {
+    if (ratio == 2) {
+        if (small)
+            launch_image_ratio<kSTX, 2>(a, s);
+        else
+            launch_image_ratio<kTX, 2>(a, s);
+    } else if (ratio == 4) {
+        if (small)
+            launch_image_ratio<kSTX, 4>(a, s);
+        else
+            launch_image_ratio<kTX, 4>(a, s);
     }
 }
 
@@ -569,7 +636,7 @@ void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s) 
 }
 
 void launch_node_pass(const NodePassArgs& a, hipStream_t s) {
-    const int blocks = a.nbx * a.nby * a.nbz;
+    const int blocks = 3 * a.nbx * a.nby * a.nbz;
     hipLaunchKernelGGL((k_node_pass<kNX, kNY, kNZ>), dim3(blocks), dim3(kThreads), 0, s, a);
 }
 

@@ -9,8 +9,9 @@
 // two-loop recursion; every inner product is accumulated in float64 and
 // reduced in a fixed order.
 //
-// Storage: hist holds kSlots pairs, slot k at hist + 2 k n (s) and
-// hist + (2 k + 1) n (t).  Basis index of s in slot k is k, of t in slot k is
+// Storage: hist holds kSlots pairs, slot k at hist + 2 k ld (s) and
+// hist + (2 k + 1) ld (t), with the row stride ld a multiple of 64 floats so
+// that every row is 16-byte aligned for vector loads.  Basis index of s in slot k is k, of t in slot k is
 // kSlots + k, of the gradient kBasisG.
 #include "ngf_internal.h"
 
@@ -21,6 +22,7 @@ namespace ngf {
 namespace {
 
 constexpr int kDots = 6 * kSlots + 6;  // inner products formed per update
+static_assert(kDots <= 64, "one lane per inner product in the Gram update");
 constexpr int kLbBlocks = 1024;
 
 __device__ inline double wave_sum(double v) {
@@ -28,8 +30,7 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-__global__ void k_lb_init(LbState* st, int mem, double hmin, const double* jds) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ inline void lb_init_one(LbState* st, int mem, double hmin, const double* jds) {
     st->count = 0;
     st->free_slot = 0;
     st->mem = mem;
@@ -48,13 +49,17 @@ __global__ void k_lb_init(LbState* st, int mem, double hmin, const double* jds) 
     st->G[kBasisG * kBasis + kBasisG] = jds[4];
 }
 
+__global__ void k_lb_init(LbState* st, int mem, double hmin, const double* jds) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) lb_init_one(st, mem, hmin, jds);
+}
+
 // Direction coefficients by the two-loop recursion over the Gram matrix.
 // Falls back to the scaled steepest-descent step (and drops the memory) when
 // there is no pair or the recursion does not give a descent direction.
 // The current point's J, max |g| and |g|^2 are taken from the state, where
-// k_lb_init and k_lb_gram_update put them.
-__global__ void k_lb_solve(LbState* st) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// k_lb_init and k_lb_gram_update put them.  g^T d also goes to jds[5], which
+// the next evaluation's reduction leaves alone (it writes jds[0..4]).
+__device__ inline void lb_solve_one(LbState* st, double* jds) {
     double* G = st->G;
     G[kBasisG * kBasis + kBasisG] = st->gnorm2;
     double flags = 0.0;
@@ -64,6 +69,7 @@ __global__ void k_lb_solve(LbState* st) {
     if (!(st->gmax > 0.0)) {
         st->flags = 2.0;
         st->gtd = 0.0;
+        jds[5] = 0.0;
         for (int i = 0; i < kBasis; ++i) st->coef[i] = 0.0;
         return;
     }
@@ -109,15 +115,22 @@ __global__ void k_lb_solve(LbState* st) {
     st->gtd = gtd;
     st->flags = flags;
     st->count_d = static_cast<double>(st->count);
+    jds[5] = gtd;  // read by the host with the trial's J in one copy
 }
 
-// d = sum_l coef_l b_l over the active basis; yt = y + d.
-__global__ __launch_bounds__(kThreads) void k_lb_combine(const LbState* st,
+__global__ void k_lb_solve(LbState* st, double* jds) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) lb_solve_one(st, jds);
+}
+
+// d = sum_l coef_l b_l over the active basis; yt = y + d.  Four elements per
+// thread and iteration (16-byte loads), then a scalar tail.
+__device__ __forceinline__ void lb_combine_body(const LbState* st,
                                                          const float* __restrict__ hist,
-                                                         int64_t n, const float* __restrict__ y,
+                                                         int64_t ld, int64_t n,
+                                                         const float* __restrict__ y,
                                                          const float* __restrict__ g,
                                                          float* __restrict__ d,
-                                                         float* __restrict__ yt) {
+                                                         float* __restrict__ yt, int block, int nblocks) {
     __shared__ double cs[kSlots], ct[kSlots];
     __shared__ int sl[kSlots];
     __shared__ double cg;
@@ -134,12 +147,34 @@ __global__ __launch_bounds__(kThreads) void k_lb_combine(const LbState* st,
     }
     __syncthreads();
     const int count = cnt;
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const int64_t n4 = n >> 2;
+    const int64_t stride = static_cast<int64_t>(nblocks) * kThreads;
+    for (int64_t q = block * static_cast<int64_t>(kThreads) + threadIdx.x; q < n4;
+         q += stride) {
+        const float4 gv = reinterpret_cast<const float4*>(g)[q];
+        double v0 = cg * gv.x, v1 = cg * gv.y, v2 = cg * gv.z, v3 = cg * gv.w;
+        for (int k = 0; k < count; ++k) {
+            const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
+            const float4 a = reinterpret_cast<const float4*>(sk)[q];
+            const float4 b = reinterpret_cast<const float4*>(sk + ld)[q];
+            v0 += cs[k] * a.x + ct[k] * b.x;
+            v1 += cs[k] * a.y + ct[k] * b.y;
+            v2 += cs[k] * a.z + ct[k] * b.z;
+            v3 += cs[k] * a.w + ct[k] * b.w;
+        }
+        const float4 yv = reinterpret_cast<const float4*>(y)[q];
+        const float4 dv = make_float4(static_cast<float>(v0), static_cast<float>(v1),
+                                      static_cast<float>(v2), static_cast<float>(v3));
+        reinterpret_cast<float4*>(d)[q] = dv;
+        reinterpret_cast<float4*>(yt)[q] =
+            make_float4(yv.x + dv.x, yv.y + dv.y, yv.z + dv.z, yv.w + dv.w);
+    }
+    for (int64_t i = 4 * n4 + block * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += stride) {
         double v = cg * static_cast<double>(g[i]);
         for (int k = 0; k < count; ++k) {
-            const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * n;
-            v += cs[k] * static_cast<double>(sk[i]) + ct[k] * static_cast<double>(sk[n + i]);
+            const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
+            v += cs[k] * static_cast<double>(sk[i]) + ct[k] * static_cast<double>(sk[ld + i]);
         }
         const float df = static_cast<float>(v);
         d[i] = df;
@@ -147,25 +182,52 @@ __global__ __launch_bounds__(kThreads) void k_lb_combine(const LbState* st,
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_lb_combine(const LbState* st,
+                                                         const float* __restrict__ hist,
+                                                         int64_t ld, int64_t n,
+                                                         const float* __restrict__ y,
+                                                         const float* __restrict__ g,
+                                                         float* __restrict__ d,
+                                                         float* __restrict__ yt) {
+    lb_combine_body(st, hist, ld, n, y, g, d, yt, blockIdx.x, gridDim.x);
+}
+
+__device__ __forceinline__ void lb_axpy_body(const float* __restrict__ y,
+                                                      const float* __restrict__ d, float t,
+                                                      float* __restrict__ yt, int64_t n, int block, int nblocks) {
+    const int64_t n4 = n >> 2;
+    const int64_t stride = static_cast<int64_t>(nblocks) * kThreads;
+    for (int64_t q = block * static_cast<int64_t>(kThreads) + threadIdx.x; q < n4;
+         q += stride) {
+        const float4 a = reinterpret_cast<const float4*>(y)[q];
+        const float4 b = reinterpret_cast<const float4*>(d)[q];
+        reinterpret_cast<float4*>(yt)[q] =
+            make_float4(fmaf(t, b.x, a.x), fmaf(t, b.y, a.y), fmaf(t, b.z, a.z),
+                        fmaf(t, b.w, a.w));
+    }
+    for (int64_t i = 4 * n4 + block * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += stride)
+        yt[i] = fmaf(t, d[i], y[i]);
+}
+
 __global__ __launch_bounds__(kThreads) void k_lb_axpy(const float* __restrict__ y,
                                                       const float* __restrict__ d, float t,
                                                       float* __restrict__ yt, int64_t n) {
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * kThreads)
-        yt[i] = fmaf(t, d[i], y[i]);
+    lb_axpy_body(y, d, t, yt, n, blockIdx.x, gridDim.x);
 }
 
 // Forms the new pair s = yt - y, t = gt - g in the free slot and all inner
 // products of {s, t, gt} with the stored pairs and with each other.
-// Per-block float64 partials: dotpart[block][kDots].
-__global__ __launch_bounds__(kThreads) void k_lb_update_dots(const LbState* st,
+// Per-block float64 partials: dotpart[block][kDots].  Two elements per
+// thread and iteration (8-byte loads), then a scalar tail.
+__device__ __forceinline__ void lb_update_dots_body(const LbState* st,
                                                              float* __restrict__ hist,
-                                                             int64_t n,
+                                                             int64_t ld, int64_t n,
                                                              const float* __restrict__ y,
                                                              const float* __restrict__ yt,
                                                              const float* __restrict__ g,
                                                              const float* __restrict__ gt,
-                                                             double* __restrict__ dotpart) {
+                                                             double* __restrict__ dotpart, int block, int nblocks) {
     __shared__ int sl[kSlots];
     __shared__ int cnt, fs;
     __shared__ double sh[4][kDots];
@@ -179,27 +241,20 @@ __global__ __launch_bounds__(kThreads) void k_lb_update_dots(const LbState* st,
     double acc[kDots];
 #pragma unroll
     for (int j = 0; j < kDots; ++j) acc[j] = 0.0;
-    float* sn = hist + (2 * static_cast<int64_t>(fs)) * n;
-    float* tn = sn + n;
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * kThreads) {
-        const float s = yt[i] - y[i];
-        const float t = gt[i] - g[i];
-        const float gn = gt[i];
-        sn[i] = s;
-        tn[i] = t;
+    float* sn = hist + (2 * static_cast<int64_t>(fs)) * ld;
+    float* tn = sn + ld;
+    auto add = [&](float s, float t, float gn, const float* a, const float* b) {
         const double sd = s, td = t, gd = gn;
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
             if (k < count) {
-                const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * n;
-                const double a = sk[i], b = sk[n + i];
-                acc[6 * k + 0] += sd * a;
-                acc[6 * k + 1] += sd * b;
-                acc[6 * k + 2] += td * a;
-                acc[6 * k + 3] += td * b;
-                acc[6 * k + 4] += gd * a;
-                acc[6 * k + 5] += gd * b;
+                const double av = a[k], bv = b[k];
+                acc[6 * k + 0] += sd * av;
+                acc[6 * k + 1] += sd * bv;
+                acc[6 * k + 2] += td * av;
+                acc[6 * k + 3] += td * bv;
+                acc[6 * k + 4] += gd * av;
+                acc[6 * k + 5] += gd * bv;
             }
         }
         acc[6 * kSlots + 0] += sd * sd;
@@ -208,6 +263,51 @@ __global__ __launch_bounds__(kThreads) void k_lb_update_dots(const LbState* st,
         acc[6 * kSlots + 3] += td * td;
         acc[6 * kSlots + 4] += td * gd;
         acc[6 * kSlots + 5] += gd * gd;
+    };
+    const int64_t n2 = n >> 1;
+    const int64_t stride = static_cast<int64_t>(nblocks) * kThreads;
+    for (int64_t q = block * static_cast<int64_t>(kThreads) + threadIdx.x; q < n2;
+         q += stride) {
+        const float2 yv = reinterpret_cast<const float2*>(y)[q];
+        const float2 ytv = reinterpret_cast<const float2*>(yt)[q];
+        const float2 gv = reinterpret_cast<const float2*>(g)[q];
+        const float2 gtv = reinterpret_cast<const float2*>(gt)[q];
+        const float2 s = make_float2(ytv.x - yv.x, ytv.y - yv.y);
+        const float2 t = make_float2(gtv.x - gv.x, gtv.y - gv.y);
+        reinterpret_cast<float2*>(sn)[q] = s;
+        reinterpret_cast<float2*>(tn)[q] = t;
+        float a0[kSlots], b0[kSlots], a1[kSlots], b1[kSlots];
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            if (k < count) {
+                const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
+                const float2 av = reinterpret_cast<const float2*>(sk)[q];
+                const float2 bv = reinterpret_cast<const float2*>(sk + ld)[q];
+                a0[k] = av.x;
+                a1[k] = av.y;
+                b0[k] = bv.x;
+                b1[k] = bv.y;
+            } else {
+                a0[k] = a1[k] = b0[k] = b1[k] = 0.0f;
+            }
+        }
+        add(s.x, t.x, gtv.x, a0, b0);
+        add(s.y, t.y, gtv.y, a1, b1);
+    }
+    for (int64_t i = 2 * n2 + block * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+         i += stride) {
+        const float s = yt[i] - y[i];
+        const float t = gt[i] - g[i];
+        sn[i] = s;
+        tn[i] = t;
+        float a[kSlots], b[kSlots];
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
+            a[k] = k < count ? sk[i] : 0.0f;
+            b[k] = k < count ? sk[ld + i] : 0.0f;
+        }
+        add(s, t, gt[i], a, b);
     }
     const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -217,19 +317,47 @@ __global__ __launch_bounds__(kThreads) void k_lb_update_dots(const LbState* st,
     }
     __syncthreads();
     for (int j = threadIdx.x; j < kDots; j += kThreads)
-        dotpart[static_cast<int64_t>(blockIdx.x) * kDots + j] =
+        dotpart[static_cast<int64_t>(block) * kDots + j] =
             (sh[0][j] + sh[1][j]) + (sh[2][j] + sh[3][j]);
 }
 
+__global__ __launch_bounds__(kThreads) void k_lb_update_dots(const LbState* st,
+                                                             float* __restrict__ hist,
+                                                             int64_t ld, int64_t n,
+                                                             const float* __restrict__ y,
+                                                             const float* __restrict__ yt,
+                                                             const float* __restrict__ g,
+                                                             const float* __restrict__ gt,
+                                                             double* __restrict__ dotpart) {
+    lb_update_dots_body(st, hist, ld, n, y, yt, g, gt, dotpart, blockIdx.x, gridDim.x);
+}
+
 // Fixed-order sum of the per-block dot partials, curvature test of the new
-// pair, ring update and Gram-matrix update.
-__global__ __launch_bounds__(64) void k_lb_gram_update(LbState* st, const double* dotpart,
-                                                       int nblocks, const double* jds) {
+// pair, ring update and Gram-matrix update.  The partials are summed by 1024
+// threads: thread t adds dot (t mod 64) over the blocks b = t/64, t/64 + 16,
+// ..., and the 16 phase sums of each dot are then added in phase order.
+constexpr int kGramThreads = 1024;
+constexpr int kGramPhases = kGramThreads / 64;
+
+__device__ __forceinline__ void lb_gram_body(LbState* st,
+                                                                 const double* dotpart,
+                                                                 int nblocks,
+                                                                 const double* jds) {
+    __shared__ double ph[kGramPhases][64];
     __shared__ double dots[kDots];
-    for (int j = threadIdx.x; j < kDots; j += 64) {
+    {
+        const int j = threadIdx.x & 63, p = threadIdx.x >> 6;
         double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += dotpart[static_cast<int64_t>(b) * kDots + j];
-        dots[j] = s;
+        if (j < kDots)
+            for (int b = p; b < nblocks; b += kGramPhases)
+                s += dotpart[static_cast<int64_t>(b) * kDots + j];
+        ph[p][j] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDots) {
+        double s = 0.0;
+        for (int p = 0; p < kGramPhases; ++p) s += ph[p][threadIdx.x];
+        dots[threadIdx.x] = s;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -290,6 +418,13 @@ __global__ __launch_bounds__(64) void k_lb_gram_update(LbState* st, const double
     st->gnorm2 = jds[4];
 }
 
+__global__ __launch_bounds__(kGramThreads) void k_lb_gram_update(LbState* st,
+                                                                 const double* dotpart,
+                                                                 int nblocks,
+                                                                 const double* jds) {
+    lb_gram_body(st, dotpart, nblocks, jds);
+}
+
 }  // namespace
 
 int lb_dot_blocks(int64_t n) {
@@ -303,32 +438,32 @@ void launch_lb_init(LbState* st, int mem, double hmin, const double* jds, hipStr
     hipLaunchKernelGGL(k_lb_init, dim3(1), dim3(64), 0, s, st, mem, hmin, jds);
 }
 
-void launch_lb_solve(LbState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_lb_solve, dim3(1), dim3(64), 0, s, st);
+void launch_lb_solve(LbState* st, double* jds, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_solve, dim3(1), dim3(64), 0, s, st, jds);
 }
 
-void launch_lb_combine(LbState* st, const float* hist, int64_t n, const float* y, const float* g,
-                       float* d, float* yt, hipStream_t s) {
-    hipLaunchKernelGGL(k_lb_combine, dim3(lb_dot_blocks(n) * 2), dim3(kThreads), 0, s, st, hist,
+void launch_lb_combine(LbState* st, const float* hist, int64_t ld, int64_t n, const float* y,
+                       const float* g, float* d, float* yt, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_combine, dim3(lb_dot_blocks(n)), dim3(kThreads), 0, s, st, hist, ld,
                        n, y, g, d, yt);
 }
 
 void launch_lb_axpy(const float* y, const float* d, float t, float* yt, int64_t n,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_lb_axpy, dim3(lb_dot_blocks(n) * 2), dim3(kThreads), 0, s, y, d, t, yt,
-                       n);
+    hipLaunchKernelGGL(k_lb_axpy, dim3(lb_dot_blocks(n)), dim3(kThreads), 0, s, y, d, t, yt, n);
 }
 
-void launch_lb_update_dots(LbState* st, float* hist, int64_t n, const float* y, const float* yt,
-                           const float* g, const float* gt, double* dotpart, int nblocks,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_lb_update_dots, dim3(nblocks), dim3(kThreads), 0, s, st, hist, n, y, yt,
-                       g, gt, dotpart);
+void launch_lb_update_dots(LbState* st, float* hist, int64_t ld, int64_t n, const float* y,
+                           const float* yt, const float* g, const float* gt, double* dotpart,
+                           int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_update_dots, dim3(nblocks), dim3(kThreads), 0, s, st, hist, ld, n, y,
+                       yt, g, gt, dotpart);
 }
 
 void launch_lb_gram_update(LbState* st, const double* dotpart, int nblocks, const double* jds,
                            hipStream_t s) {
-    hipLaunchKernelGGL(k_lb_gram_update, dim3(1), dim3(64), 0, s, st, dotpart, nblocks, jds);
+    hipLaunchKernelGGL(k_lb_gram_update, dim3(1), dim3(kGramThreads), 0, s, st, dotpart, nblocks,
+                       jds);
 }
 
 }  // namespace ngf

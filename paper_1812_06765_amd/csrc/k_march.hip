@@ -76,9 +76,23 @@ __device__ inline float w1_of(int i) {
     return static_cast<float>(2 * (i % R) + 1) * (0.5f / R);
 }
 
-template <int TY, int TZ, int R, bool GRAD>
-__global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int CX) {
+// position of face-halo ring entry s (< 2 TZ + 2 TY) in the one-voxel halo box
+template <int TY, int TZ>
+__device__ inline void ring1_pos_t(int s, int& b1y, int& b1z) {
+    if (s < 2 * TZ) {
+        b1y = s < TZ ? 0 : TY + 1;
+        b1z = 1 + (s % TZ);
+    } else {
+        const int q = s - 2 * TZ;
+        b1y = 1 + (q >> 1);
+        b1z = (q & 1) ? TZ + 1 : 0;
+    }
+}
+
+template <int TY, int TZ, int R, bool GRAD, bool POW2>
+__device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int block) {
     using L = March<TY, TZ, R>;
+    auto ring1_pos = [](int s, int& b1y, int& b1z) { ring1_pos_t<TY, TZ>(s, b1y, b1z); };
     extern __shared__ float smem[];
     float* sTy = smem + L::OFF_TY;
     float* sR = smem + L::OFF_R;
@@ -91,9 +105,7 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
     __shared__ double red[4];
 
     // tile decode, spread over the XCDs so that neighbouring tiles share an L2
-    const int ntiles = a.ntx * a.nty * a.ntz;
-    int tile = blockIdx.x;
-    if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+    const int tile = xcd_tile(block, a.ntx * a.nty * a.ntz);
     const int tz = tile % a.ntz;
     const int ty = (tile / a.ntz) % a.nty;
     const int tx = tile / (a.ntz * a.nty);
@@ -105,20 +117,42 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
     const int jx_first = x0 / R;
     const int xend = min(x0 + CX, mx);  // first plane past the chunk (in the domain)
 
-    // x-interpolated node plane for image plane p (clamped), float64, into sQ
-    auto build_q = [&](int p) {
+    // x-interpolated node plane for image plane p (clamped), float64, into sQ.
+    // The node values are loaded into registers one phase ahead of the store
+    // (load_q during the warp phase, store_q after the last read of sG), so
+    // their latency overlaps the warp's gathers.
+    constexpr int KQ = (3 * L::NQ + kThreads - 1) / kThreads;
+    float qv0[KQ], qv1[KQ];
+    auto load_q = [&](int p) {
         const int pc = clampi(p, 0, mx - 1);
         const int jx = node_of<R>(pc);
-        const double w1 = w1_of<R>(pc), w0 = 1.0 - w1;
-        for (int i = threadIdx.x; i < 3 * L::NQ; i += kThreads) {
-            const int c = i / L::NQ;
-            const int r = i - c * L::NQ;
-            const int qz = r % L::NQZ, qy = r / L::NQZ;
-            const int gy = min(qly + qy, a.ny - 1), gz = min(qlz + qz, a.nz - 1);
-            const float* yc = a.y + c * nnod + gy * a.nz + gz;
-            const double v0 = yc[jx * a.ny * a.nz], v1 = yc[(jx + 1) * a.ny * a.nz];
-            sQ[i] = w0 * v0 + w1 * v1;
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) {
+            const int i = threadIdx.x + k * kThreads;
+            if (i < 3 * L::NQ) {
+                const int c = i / L::NQ;
+                const int r = i - c * L::NQ;
+                const int qz = r % L::NQZ, qy = r / L::NQZ;
+                const int gy = min(qly + qy, a.ny - 1), gz = min(qlz + qz, a.nz - 1);
+                const float* yc = a.y + c * nnod + gy * a.nz + gz;
+                qv0[k] = yc[jx * a.ny * a.nz];
+                qv1[k] = yc[(jx + 1) * a.ny * a.nz];
+            }
         }
+    };
+    auto store_q = [&](int p) {
+        const int pc = clampi(p, 0, mx - 1);
+        const double w1 = w1_of<R>(pc), w0 = 1.0 - w1;
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) {
+            const int i = threadIdx.x + k * kThreads;
+            if (i < 3 * L::NQ)
+                sQ[i] = w0 * static_cast<double>(qv0[k]) + w1 * static_cast<double>(qv1[k]);
+        }
+    };
+    auto build_q = [&](int p) {
+        load_q(p);
+        store_q(p);
     };
 
     // warp at in-plane position (gy, gz) (clamped into the domain) of plane p
@@ -145,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
         const int mm[3] = {mx, my, mz};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double xi = a.pow2h ? fma(yh[d], ih[d], -0.5) : yh[d] / hh[d] - 0.5;
+            double xi = POW2 ? fma(yh[d], ih[d], -0.5) : yh[d] / hh[d] - 0.5;
             const double hi = static_cast<double>(mm[d] - 1);
             s[d] = (xi >= 0.0 && xi <= hi) ? 1.0f : 0.0f;
             xi = fmin(fmax(xi, 0.0), hi);
@@ -174,7 +208,9 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
         return fmaf(f[0], c1, qx * c0);
     };
 
-    float dTr[3][L::KP][3];  // dT of the last three warped planes (slot = k mod 3)
+    // dT of the last three warped planes: dTw is written by W, dT2 (two steps
+    // old) is read by E; the registers rotate at the end of every step
+    float dTw[L::KP][3], dT1[L::KP][3], dT2[L::KP][3];
     float acc0[L::KO], acc1[L::KO];
 #pragma unroll
     for (int o = 0; o < L::KO; ++o) acc0[o] = acc1[o] = 0.0f;
@@ -200,8 +236,8 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
     build_q(x0 - 2);
     __syncthreads();
 
-    auto step = [&](const int k, auto Sc) {
-        constexpr int S = decltype(Sc)::value;
+    auto step = [&](const int k) {
+        const int S = k % 3;  // LDS slot of the plane warped in this step
         // ---------------- W: warp plane pw, stage R of plane pw - 1 --------
         const int pw = x0 - 2 + k;
         const int pwc = clampi(pw, 0, mx - 1);
@@ -212,8 +248,7 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
             const int t = threadIdx.x + kk * kThreads;
             const int ly = t / TZ, lz = t % TZ;
             const int gy = min(y0 + ly, my - 1), gz = min(z0 + lz, mz - 1);
-            Ty[(ly + 2) * L::H2Z + (lz + 2)] =
-                warp_at(pwc, gy, gz, wgrad ? dTr[S][kk] : nullptr);
+            Ty[(ly + 2) * L::H2Z + (lz + 2)] = warp_at(pwc, gy, gz, wgrad ? dTw[kk] : nullptr);
         }
         for (int s = threadIdx.x; s < L::NRING2; s += kThreads) {
             int by, bz;
@@ -232,6 +267,28 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
         }
         const int pv = pw - 1;
         const bool vok = pv >= max(x0 - 1, 0) && pv <= min(x0 + CX, mx - 1);
+        // prefetch for the next phases: node values of the next x-interpolated
+        // plane, and the x neighbours of R at this thread's V positions
+        if (k + 1 < CX + 4) load_q(pw + 1);
+        float rxm[L::KP + 1], rxp[L::KP + 1];
+        if (vok) {
+            const float* Rm = a.R + max(pv - 1, 0) * sxT;
+            const float* Rq = a.R + min(pv + 1, mx - 1) * sxT;
+#pragma unroll
+            for (int kk = 0; kk <= L::KP; ++kk) {
+                int b1y, b1z;
+                if (kk < L::KP) {
+                    const int t = threadIdx.x + kk * kThreads;
+                    b1y = t / TZ + 1;
+                    b1z = t % TZ + 1;
+                } else {
+                    ring1_pos(min(static_cast<int>(threadIdx.x), L::NRING1 - 1), b1y, b1z);
+                }
+                const int cy = clampi(y0 - 1 + b1y, 0, my - 1), cz = clampi(z0 - 1 + b1z, 0, mz - 1);
+                rxm[kk] = Rm[cy * mz + cz];
+                rxp[kk] = Rq[cy * mz + cz];
+            }
+        }
         if (vok) {
             const float* Rp = a.R + pv * sxT;
             for (int i = threadIdx.x; i < L::NH2; i += kThreads) {
@@ -247,13 +304,11 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
             const float* Tm = sTy + ((S + 1) % 3) * L::NH2;  // plane pv - 1 (slot of k - 2)
             const float* T0 = sTy + ((S + 2) % 3) * L::NH2;  // plane pv     (slot of k - 1)
             const float* Tp = Ty;                            // plane pv + 1 (slot of k)
-            const float* Rm = a.R + max(pv - 1, 0) * sxT;
-            const float* Rq = a.R + min(pv + 1, mx - 1) * sxT;
             const bool dtile = pv >= x0 && pv < xend;
             float* Vx = sVx + (pv % 3) * L::NI;
             float* Vy = sVy + (pv & 1) * (L::H1Y * TZ);
             float* Vz = sVz + (pv & 1) * (TY * L::H1Z);
-            auto ngf_at = [&](int b1y, int b1z, bool inner) {
+            auto ngf_at = [&](int b1y, int b1z, bool inner, float rm, float rp) {
                 const int gy = y0 - 1 + b1y, gz = z0 - 1 + b1z;
                 const int cy = clampi(gy, 0, my - 1), cz = clampi(gz, 0, mz - 1);
                 const int p = (cy - y0 + 2) * L::H2Z + (cz - z0 + 2);
@@ -261,13 +316,13 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
                 const float gTx = (Tp[p] - Tm[p]) * a.i2hx;
                 const float gTy = (T0[p + L::H2Z] - T0[p - L::H2Z]) * a.i2hy;
                 const float gTz = (T0[p + 1] - T0[p - 1]) * a.i2hz;
-                const float gRx = (Rq[cy * mz + cz] - Rm[cy * mz + cz]) * a.i2hx;
+                const float gRx = (rp - rm) * a.i2hx;
                 const float gRy = (sR[p + L::H2Z] - sR[p - L::H2Z]) * a.i2hy;
                 const float gRz = (sR[p + 1] - sR[p - 1]) * a.i2hz;
                 const float aa = fmaf(gTx, gTx, fmaf(gTy, gTy, fmaf(gTz, gTz, tau * tau)));
                 const float bb = fmaf(gRx, gRx, fmaf(gRy, gRy, fmaf(gRz, gRz, rho * rho)));
                 const float ab = fmaf(gTx, gRx, fmaf(gTy, gRy, fmaf(gTz, gRz, tau * rho)));
-                const float iaa = 1.0f / aa, ibb = 1.0f / bb;
+                const float iaa = __builtin_amdgcn_rcpf(aa), ibb = __builtin_amdgcn_rcpf(bb);
                 if (inner && dtile && gy < my && gz < mz) {
                     float q1, q2, q3, q4, q5, q6;
                     {
@@ -284,11 +339,21 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
                     dsum += static_cast<double>(lag * iaa * ibb);
                 }
                 if (GRAD) {
-                    const float k1 = ab / aa;
-                    const float coef = -a.hbar * ab * iaa * ibb;
-                    float vx = coef * fmaf(-k1, gTx, gRx);
-                    float vy = coef * fmaf(-k1, gTy, gRy);
-                    float vz = coef * fmaf(-k1, gTz, gRz);
+                    // v = -hbar r/(nT nR) (grad R - (c/nT^2) grad T)
+                    //   = -hbar ab/(aa^2 bb) (aa grad R - ab grad T),
+                    // with unfused products so that v is exactly 0 when grad T = grad R
+                    // (then ab = aa bit for bit and both products round alike)
+                    const float coef = -a.hbar * ab * (iaa * iaa) * ibb;
+                    float wx, wy, wz;
+                    {
+#pragma clang fp contract(off)
+                        wx = aa * gRx - ab * gTx;
+                        wy = aa * gRy - ab * gTy;
+                        wz = aa * gRz - ab * gTz;
+                    }
+                    float vx = coef * wx;
+                    float vy = coef * wy;
+                    float vz = coef * wz;
                     if (gy != cy) vy = -vy;  // mirrored ghost of the y adjoint stencil
                     if (gz != cz) vz = -vz;
                     const int hy = (b1y == 0 || b1y == TY + 1), hz = (b1z == 0 || b1z == TZ + 1);
@@ -300,25 +365,17 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
 #pragma unroll
             for (int kk = 0; kk < L::KP; ++kk) {
                 const int t = threadIdx.x + kk * kThreads;
-                ngf_at(t / TZ + 1, t % TZ + 1, true);
+                ngf_at(t / TZ + 1, t % TZ + 1, true, rxm[kk], rxp[kk]);
             }
             if (GRAD && threadIdx.x < L::NRING1) {
-                const int s = threadIdx.x;
                 int b1y, b1z;
-                if (s < 2 * TZ) {
-                    b1y = s < TZ ? 0 : TY + 1;
-                    b1z = 1 + (s % TZ);
-                } else {
-                    const int q = s - 2 * TZ;
-                    b1y = 1 + (q >> 1);
-                    b1z = (q & 1) ? TZ + 1 : 0;
-                }
-                ngf_at(b1y, b1z, false);
+                ring1_pos(threadIdx.x, b1y, b1z);
+                ngf_at(b1y, b1z, false, rxm[L::KP], rxp[L::KP]);
             }
         }
         if (!GRAD) {
             __syncthreads();
-            if (k + 1 < CX + 4) build_q(pw + 1);
+            if (k + 1 < CX + 4) store_q(pw + 1);
             __syncthreads();
             return;
         }
@@ -333,7 +390,6 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
             const float* Vp = pe + 1 <= mx - 1 ? sVx + ((pe + 1) % 3) * L::NI : nullptr;
             const float* Vy = sVy + (pe & 1) * (L::H1Y * TZ);
             const float* Vz = sVz + (pe & 1) * (TY * L::H1Z);
-            const int SE = (S + 1) % 3;  // dT of plane pe was stored at step k - 2
 #pragma unroll
             for (int kk = 0; kk < L::KP; ++kk) {
                 const int t = threadIdx.x + kk * kThreads;
@@ -345,32 +401,30 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
                 const float ez = Vz[ly * L::H1Z + lz] - Vz[ly * L::H1Z + lz + 2];
                 const bool in = (y0 + ly < my) && (z0 + lz < mz);
                 const float e = in ? fmaf(ex, a.i2hx, fmaf(ey, a.i2hy, ez * a.i2hz)) : 0.0f;
-                float dd[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    // static slot selection keeps dTr in registers
-                    dd[c] = SE == 0 ? dTr[0][kk][c] : (SE == 1 ? dTr[1][kk][c] : dTr[2][kk][c]);
-                }
-                sG[t] = e * dd[0];
-                sG[L::NI + t] = e * dd[1];
-                sG[2 * L::NI + t] = e * dd[2];
+                sG[t] = e * dT2[kk][0];  // dT of plane pe, warped two steps ago
+                sG[L::NI + t] = e * dT2[kk][1];
+                sG[2 * L::NI + t] = e * dT2[kk][2];
             }
         }
         __syncthreads();
 
         // ---------------- Z: P^T along z ----------------------------------
+        // node nz of the tile collects voxels R(nz-1) .. R(nz+1)-1 with the
+        // weights (2k+1)/(2R) rising then falling (the two halves of a cell)
         const int jz0 = z0 / R, jy0 = y0 / R;
         if (eok) {
             for (int i = threadIdx.x; i < L::GZ; i += kThreads) {
                 const int nz = i % L::PZ;
-                const int r = i / L::PZ;  // (c, ly)
-                const int lo = max(0, R * (nz - 1)), hi = min(TZ, R * (nz + 1));
-                const float* g = sG + r * TZ;
+                const float* g = sG + (i / L::PZ) * TZ;  // (c, ly) row
                 float acc = 0.0f;
-                for (int lz = lo; lz < hi; ++lz) {
-                    const int iz = z0 + lz;
-                    const float w1 = w1_of<R>(iz);
-                    acc = fmaf(node_of<R>(iz) == jz0 + nz ? 1.0f - w1 : w1, g[lz], acc);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    // voxel R(nz-1)+k: node nz is its upper node (weight w1)
+                    const int lz = R * (nz - 1) + k;
+                    if (lz >= 0) acc = fmaf((2 * k + 1) * (0.5f / R), g[lz], acc);
+                    // voxel R nz + k: node nz is its lower node (weight w0)
+                    const int lz2 = R * nz + k;
+                    if (lz2 < TZ) acc = fmaf(1.0f - (2 * k + 1) * (0.5f / R), g[lz2], acc);
                 }
                 sGz[i] = acc;
             }
@@ -397,28 +451,32 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
                     const int nz = i % L::PZ;
                     const int ny = (i / L::PZ) % L::PY;
                     const int c = i / (L::PZ * L::PY);
-                    const int lo = max(0, R * (ny - 1)), hi = min(TY, R * (ny + 1));
+                    const float* gz = sGz + c * TY * L::PZ + nz;
                     float v = 0.0f;
-                    for (int ly = lo; ly < hi; ++ly) {
-                        const int iy = y0 + ly;
-                        const float w1 = w1_of<R>(iy);
-                        v = fmaf(node_of<R>(iy) == jy0 + ny ? 1.0f - w1 : w1,
-                                 sGz[(c * TY + ly) * L::PZ + nz], v);
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const int ly = R * (ny - 1) + k;
+                        if (ly >= 0) v = fmaf((2 * k + 1) * (0.5f / R), gz[ly * L::PZ], v);
+                        const int ly2 = R * ny + k;
+                        if (ly2 < TY) v = fmaf(1.0f - (2 * k + 1) * (0.5f / R), gz[ly2 * L::PZ], v);
                     }
                     acc0[o] = fmaf(wx0, v, acc0[o]);
                     acc1[o] = fmaf(wx1, v, acc1[o]);
                 }
             }
         }
-        if (k + 1 < CX + 4) build_q(pw + 1);  // sG is no longer read: Q may overwrite it
+        if (k + 1 < CX + 4) store_q(pw + 1);  // sG is no longer read: Q may overwrite it
+#pragma unroll
+        for (int kk = 0; kk < L::KP; ++kk)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                dT2[kk][c] = dT1[kk][c];
+                dT1[kk][c] = dTw[kk][c];
+            }
         __syncthreads();
     };
 
-    for (int k = 0; k < CX + 4; k += 3) {
-        step(k, std::integral_constant<int, 0>());
-        step(k + 1, std::integral_constant<int, 1>());
-        step(k + 2, std::integral_constant<int, 2>());
-    }
+    for (int k = 0; k < CX + 4; ++k) step(k);
     if (GRAD) {
         flush(jA, acc0);
         flush(jA + 1, acc1);
@@ -434,26 +492,52 @@ __global__ __launch_bounds__(kThreads) void k_image_march(ImagePassArgs a, int C
     if (threadIdx.x == 0) a.dpart[tile] = dt;
 }
 
+// The 16 x 32 tile needs 36 KiB of LDS, so up to four workgroups fit a CU;
+// its registers are held to three waves per SIMD.  The 16 x 64 tile is
+// limited to two workgroups per CU by LDS anyway.
+template <int TY, int TZ, int R, bool GRAD, bool POW2>
+__global__ __launch_bounds__(kThreads, TZ == 32 ? 3 : 2) void k_image_march(ImagePassArgs a,
+                                                                            int CX) {
+    march_body<TY, TZ, R, GRAD, POW2>(a, CX, blockIdx.x);
+}
+
 template <int TY, int TZ, int R>
 void launch_march_t(const ImagePassArgs& a, int cx, hipStream_t s) {
     using L = March<TY, TZ, R>;
     const int blocks = a.ntx * a.nty * a.ntz;
     const size_t lds = sizeof(float) * L::LDS_FLOATS;
-    if (a.want_grad)
-        hipLaunchKernelGGL((k_image_march<TY, TZ, R, true>), dim3(blocks), dim3(kThreads), lds, s,
-                           a, cx);
-    else
-        hipLaunchKernelGGL((k_image_march<TY, TZ, R, false>), dim3(blocks), dim3(kThreads), lds,
-                           s, a, cx);
+    // the spacing decides at compile time how the warp index is formed
+    if (a.want_grad) {
+        if (a.pow2h)
+            hipLaunchKernelGGL((k_image_march<TY, TZ, R, true, true>), dim3(blocks),
+                               dim3(kThreads), lds, s, a, cx);
+        else
+            hipLaunchKernelGGL((k_image_march<TY, TZ, R, true, false>), dim3(blocks),
+                               dim3(kThreads), lds, s, a, cx);
+    } else {
+        if (a.pow2h)
+            hipLaunchKernelGGL((k_image_march<TY, TZ, R, false, true>), dim3(blocks),
+                               dim3(kThreads), lds, s, a, cx);
+        else
+            hipLaunchKernelGGL((k_image_march<TY, TZ, R, false, false>), dim3(blocks),
+                               dim3(kThreads), lds, s, a, cx);
+    }
 }
 
 }  // namespace
 
-void launch_image_march(const ImagePassArgs& a, int ratio, int cx, hipStream_t s) {
-    if (ratio == 2)
-        launch_march_t<kMY, kMZ, 2>(a, cx, s);
-    else if (ratio == 4)
-        launch_march_t<kMY, kMZ, 4>(a, cx, s);
+void launch_image_march(const ImagePassArgs& a, int ratio, int tz, int cx, hipStream_t s) {
+    if (tz == 64) {
+        if (ratio == 2)
+            launch_march_t<kMY, 64, 2>(a, cx, s);
+        else if (ratio == 4)
+            launch_march_t<kMY, 64, 4>(a, cx, s);
+    } else {
+        if (ratio == 2)
+            launch_march_t<kMY, 32, 2>(a, cx, s);
+        else if (ratio == 4)
+            launch_march_t<kMY, 32, 4>(a, cx, s);
+    }
 }
 
 }  // namespace ngf

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -35,8 +36,10 @@ struct Level {
     int64_t Ny() const { return static_cast<int64_t>(my[0]) * my[1] * my[2]; }
 };
 
-struct Status {
-    ngf_status code;
+struct LevelStore {
+    int64_t cap_n = 0;               // floats in R and in T
+    int cap_m[3] = {0, 0, 0};        // entries per index-map axis
+    void* p[11] = {};                // R, T, then j0, w0, w1 per axis
 };
 
 constexpr int kProfMax = 4096;
@@ -50,7 +53,9 @@ struct ngf_ctx {
     hipEvent_t join[3] = {nullptr, nullptr, nullptr};
     std::string err;
     std::vector<Level> lv;
-    std::vector<void*> owned;  // every device allocation of the pyramid
+    // device storage of the pyramid, per level, kept across pyramids and
+    // reused whenever it is large enough for the new shape
+    std::vector<LevelStore> store;
 
     // evaluation scratch (sized for level 0 by ngf_build_pyramid / ngf_reserve)
     float* part = nullptr;
@@ -66,6 +71,7 @@ struct ngf_ctx {
 
     // L-BFGS
     size_t lb_cap = 0;  // floats per vector
+    size_t lb_ld = 0;   // row stride of the history (multiple of 64 floats)
     float* ly = nullptr;
     float* lg = nullptr;
     float* lyt = nullptr;
@@ -74,7 +80,6 @@ struct ngf_ctx {
     float* ltmp = nullptr;
     float* hist = nullptr;
     LbState* st = nullptr;
-    LbState* host_st = nullptr;  // pinned
     double* dotpart = nullptr;
     int lb_level = -1;
     double lb_J = 0.0;
@@ -82,7 +87,7 @@ struct ngf_ctx {
     int lb_evals = 0;
 
     // image-pass variant: -1 = autotune, else forced for every level
-    int forced_variant = -1;
+    int forced_variant = -1;  // also kVariantBySize
     bool tune_loaded = false;
     std::vector<std::pair<std::string, int>> tune_cache;  // shape key -> variant
 
@@ -150,14 +155,14 @@ struct Geo {
 };
 Geo geometry(const Level& L, int variant) {
     Geo g{};
-    if (variant == kTile3D) {
-        g.tx = kTX;
+    if (variant == kTile3D || variant == kTile3DSmall) {
+        g.tx = variant == kTile3D ? kTX : kSTX;
         g.ty = kTY;
         g.tz = kTZ;
     } else {
         g.tx = march_cx(variant);
         g.ty = kMY;
-        g.tz = kMZ;
+        g.tz = march_tz(variant);
     }
     g.ntx = tiles(L.m[0], g.tx);
     g.nty = tiles(L.m[1], g.ty);
@@ -174,8 +179,10 @@ bool pow2(double h) {
     int e = 0;
     return std::frexp(h, &e) == 0.5;
 }
+// node-pass workgroups: one per node tile and component
 int64_t node_blocks(const Level& L) {
-    return static_cast<int64_t>(tiles(L.my[0], kNX)) * tiles(L.my[1], kNY) * tiles(L.my[2], kNZ);
+    return 3 * static_cast<int64_t>(tiles(L.my[0], kNX)) * tiles(L.my[1], kNY) *
+           tiles(L.my[2], kNZ);
 }
 
 ngf_status ensure_scratch(ngf_ctx* c, const Level& L) {
@@ -184,6 +191,9 @@ ngf_status ensure_scratch(ngf_ctx* c, const Level& L) {
         pf = std::max(pf, static_cast<size_t>(part_floats(L, c->p.ratio, v)));
         nt = std::max(nt, static_cast<size_t>(geometry(L, v).ntiles()));
     }
+    const size_t nb = static_cast<size_t>(node_blocks(L));
+    if (pf > c->part_cap || nt > c->dpart_cap || nb > c->nblk_cap)
+        HIPCHK(c, hipStreamSynchronize(c->stream));  // queued work may use the old buffers
     if (pf > c->part_cap) {
         dfree(c->part);
         c->part = nullptr;
@@ -198,7 +208,6 @@ ngf_status ensure_scratch(ngf_ctx* c, const Level& L) {
         if (dalloc(c, &c->dpart, nt) != NGF_OK) return NGF_E_OOM;
         c->dpart_cap = nt;
     }
-    const size_t nb = static_cast<size_t>(node_blocks(L));
     if (nb > c->nblk_cap) {
         dfree(c->spart);
         dfree(c->gpart);
@@ -213,6 +222,7 @@ ngf_status ensure_scratch(ngf_ctx* c, const Level& L) {
 
 ngf_status ensure_lbfgs(ngf_ctx* c, size_t n) {
     if (n <= c->lb_cap) return NGF_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // queued work may use the old buffers
     for (float** p : {&c->ly, &c->lg, &c->lyt, &c->lgt, &c->ld, &c->ltmp, &c->hist}) {
         dfree(*p);
         *p = nullptr;
@@ -222,7 +232,9 @@ ngf_status ensure_lbfgs(ngf_ctx* c, size_t n) {
     c->lb_cap = 0;
     for (float** p : {&c->ly, &c->lg, &c->lyt, &c->lgt, &c->ld, &c->ltmp})
         if (dalloc(c, p, n) != NGF_OK) return NGF_E_OOM;
-    if (dalloc(c, &c->hist, static_cast<size_t>(2) * kSlots * n) != NGF_OK) return NGF_E_OOM;
+    c->lb_ld = (n + 63) / 64 * 64;
+    if (dalloc(c, &c->hist, static_cast<size_t>(2) * kSlots * c->lb_ld) != NGF_OK)
+        return NGF_E_OOM;
     if (dalloc(c, &c->dotpart, static_cast<size_t>(lb_dot_blocks(static_cast<int64_t>(n))) *
                                    (6 * kSlots + 6)) != NGF_OK)
         return NGF_E_OOM;
@@ -231,9 +243,61 @@ ngf_status ensure_lbfgs(ngf_ctx* c, size_t n) {
 }
 
 void free_pyramid(ngf_ctx* c) {
-    for (void* p : c->owned) dfree(p);
-    c->owned.clear();
+    for (LevelStore& st : c->store)
+        for (void*& p : st.p) {
+            dfree(p);
+            p = nullptr;
+        }
+    c->store.clear();
     c->lv.clear();
+}
+
+// Point level l at storage of sufficient size, allocating only when the
+// kept storage is too small (then after the context's queued work is done).
+ngf_status bind_level_storage(ngf_ctx* c, int l) {
+    Level& lv = c->lv[l];
+    if (static_cast<int>(c->store.size()) <= l) c->store.resize(l + 1);
+    LevelStore& st = c->store[l];
+    bool fits = st.cap_n >= lv.N();
+    for (int d = 0; d < 3; ++d) fits = fits && st.cap_m[d] >= lv.m[d];
+    if (!fits) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (void*& p : st.p) {
+            dfree(p);
+            p = nullptr;
+        }
+        st.cap_n = 0;
+        for (int d = 0; d < 3; ++d) st.cap_m[d] = 0;
+        const size_t n = static_cast<size_t>(lv.N());
+        // index maps are small: room for the longest axis (at least 1024)
+        // on every axis, so that pairs of other shapes reuse them
+        const int lng = std::max(1024, std::max(lv.m[0], std::max(lv.m[1], lv.m[2])));
+        const int cap_m[3] = {lng, lng, lng};
+        float* f = nullptr;
+        if (dalloc(c, &f, n) != NGF_OK) return NGF_E_OOM;
+        st.p[0] = f;
+        if (dalloc(c, &f, n) != NGF_OK) return NGF_E_OOM;
+        st.p[1] = f;
+        for (int d = 0; d < 3; ++d) {
+            int32_t* j = nullptr;
+            if (dalloc(c, &j, cap_m[d]) != NGF_OK) return NGF_E_OOM;
+            st.p[2 + 3 * d] = j;
+            for (int k = 1; k < 3; ++k) {
+                if (dalloc(c, &f, cap_m[d]) != NGF_OK) return NGF_E_OOM;
+                st.p[2 + 3 * d + k] = f;
+            }
+        }
+        st.cap_n = lv.N();
+        for (int d = 0; d < 3; ++d) st.cap_m[d] = cap_m[d];
+    }
+    lv.R = static_cast<float*>(st.p[0]);
+    lv.T = static_cast<float*>(st.p[1]);
+    for (int d = 0; d < 3; ++d) {
+        lv.j0[d] = static_cast<int32_t*>(st.p[2 + 3 * d]);
+        lv.w0[d] = static_cast<float*>(st.p[3 + 3 * d]);
+        lv.w1[d] = static_cast<float*>(st.p[4 + 3 * d]);
+    }
+    return NGF_OK;
 }
 
 ImagePassArgs image_args(ngf_ctx* c, const Level& L, const float* R, const float* T,
@@ -290,10 +354,11 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
     const bool want = grad != nullptr;
     ImagePassArgs a = image_args(c, L, R, T, y, want);
     auto launch = [&] {
-        if (L.variant == kTile3D)
-            launch_image_pass(a, c->p.ratio, c->stream);
+        if (!is_march(L.variant))
+            launch_image_pass(a, c->p.ratio, c->stream, L.variant == kTile3DSmall);
         else
-            launch_image_march(a, c->p.ratio, march_cx(L.variant), c->stream);
+            launch_image_march(a, c->p.ratio, march_tz(L.variant), march_cx(L.variant),
+                               c->stream);
     };
     if (c->prof && c->nprof < kProfMax) {
         HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof], c->stream));
@@ -393,12 +458,27 @@ void tune_cache_store(const std::string& key, int v) {
     std::fclose(f);
 }
 
+// Image-pass variant from the level size alone, for callers that cannot
+// afford timing runs (or whose timings would be disturbed by concurrent
+// work): the choices the timed selection makes on gfx950 at cubic levels of
+// 256^3, 128^3 and 64^3 and below.
+int variant_by_size(const Level& L) {
+    const int64_t n = L.N();
+    if (n >= (int64_t{8} << 20)) return kMarch64x32;
+    if (n >= (int64_t{1} << 20)) return kMarch32x8;
+    return kTile3DSmall;
+}
+
 // Pick the image-pass variant of every level: forced, cached for this shape,
 // or the fastest of all variants over three timed evaluations at the identity
 // (whole evaluation: image pass, node pass and reduction).
 ngf_status autotune(ngf_ctx* c) {
     if (c->forced_variant >= 0) {
         for (Level& L : c->lv) L.variant = c->forced_variant;
+        return NGF_OK;
+    }
+    if (c->forced_variant == kVariantBySize) {
+        for (Level& L : c->lv) L.variant = variant_by_size(L);
         return NGF_OK;
     }
     if (!c->tune_loaded) {
@@ -486,8 +566,6 @@ ngf_status ngf_create(const ngf_params* p, void* stream, ngf_ctx** out) {
     chk(hipHostMalloc(reinterpret_cast<void**>(&c->host_jds), 8 * sizeof(double),
                       hipHostMallocDefault));
     chk(hipMalloc(reinterpret_cast<void**>(&c->st), sizeof(LbState)));
-    chk(hipHostMalloc(reinterpret_cast<void**>(&c->host_st), sizeof(LbState),
-                      hipHostMallocDefault));
     chk(hipMalloc(reinterpret_cast<void**>(&c->dflag), sizeof(int)));
     if (s != NGF_OK) {
         ngf_destroy(c);
@@ -521,7 +599,6 @@ void ngf_destroy(ngf_ctx* c) {
         dfree(p);
     for (void* p : c->pair_owned) dfree(p);
     if (c->host_jds) (void)hipHostFree(c->host_jds);
-    if (c->host_st) (void)hipHostFree(c->host_st);
     delete c;
 }
 
@@ -555,10 +632,8 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
         N *= g->m[d];
     }
     if (N >= (static_cast<int64_t>(1) << 31)) return fail(c, NGF_E_SHAPE, "image too large");
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    free_pyramid(c);
     c->lb_level = -1;
-    c->lv.resize(L);
+    c->lv.assign(L, Level{});
     for (int l = 0; l < L; ++l) {
         Level& lv = c->lv[l];
         for (int d = 0; d < 3; ++d) {
@@ -567,17 +642,10 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
             lv.my[d] = lv.m[d] / r + 1;
             lv.hy[d] = lv.m[d] * lv.h[d] / (lv.my[d] - 1);
         }
-        const size_t n = static_cast<size_t>(lv.N());
-        if (dalloc(c, &lv.R, n) != NGF_OK || dalloc(c, &lv.T, n) != NGF_OK) return NGF_E_OOM;
-        c->owned.push_back(lv.R);
-        c->owned.push_back(lv.T);
-        for (int d = 0; d < 3; ++d) {
-            if (dalloc(c, &lv.j0[d], lv.m[d]) != NGF_OK || dalloc(c, &lv.w0[d], lv.m[d]) != NGF_OK ||
-                dalloc(c, &lv.w1[d], lv.m[d]) != NGF_OK)
-                return NGF_E_OOM;
-            c->owned.push_back(lv.j0[d]);
-            c->owned.push_back(lv.w0[d]);
-            c->owned.push_back(lv.w1[d]);
+        const ngf_status e = bind_level_storage(c, l);
+        if (e != NGF_OK) {
+            c->lv.clear();
+            return e;
         }
     }
     if (ensure_scratch(c, c->lv[0]) != NGF_OK) return NGF_E_OOM;
@@ -617,7 +685,7 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
     HIPCHK(c, hipMemcpyAsync(&bad, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (bad) {
-        free_pyramid(c);
+        c->lv.clear();
         return fail(c, NGF_E_NONFINITE, "R or T holds NaN or infinity");
     }
     const ngf_status ts = autotune(c);
@@ -628,15 +696,10 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
 
 ngf_status ngf_set_kernel(ngf_ctx* c, int32_t variant) {
     if (!c) return NGF_E_ARG;
-    if (variant < -1 || variant >= kNumVariants) return fail(c, NGF_E_ARG, "unknown variant");
+    if (variant < kVariantBySize || variant >= kNumVariants)
+        return fail(c, NGF_E_ARG, "unknown variant");
     c->forced_variant = variant;
-    if (!c->lv.empty()) {
-        if (variant >= 0) {
-            for (Level& L : c->lv) L.variant = variant;
-        } else {
-            return autotune(c);
-        }
-    }
+    if (!c->lv.empty()) return autotune(c);
     return NGF_OK;
 }
 
@@ -765,8 +828,9 @@ ngf_status ngf_lbfgs_step(ngf_ctx* c, double* J, int32_t* info) {
     } else if (c->lb_gmax == 0.0) {
         inf = NGF_INFO_CONVERGED;
     } else {
-        launch_lb_solve(c->st, c->stream);
-        launch_lb_combine(c->st, c->hist, n, c->ly, c->lg, c->ld, c->lyt, c->stream);
+        launch_lb_solve(c->st, c->jds, c->stream);
+        launch_lb_combine(c->st, c->hist, static_cast<int64_t>(c->lb_ld), n, c->ly, c->lg, c->ld,
+                          c->lyt, c->stream);
         HIPCHK(c, hipGetLastError());
         const double c1 = 1e-4;
         double t = 1.0, gtd = 0.0;
@@ -777,10 +841,8 @@ ngf_status ngf_lbfgs_step(ngf_ctx* c, double* J, int32_t* info) {
             ngf_status e = enqueue_eval(c, L, L.R, L.T, c->lyt, c->lgt);
             if (e != NGF_OK) return e;
             c->lb_evals++;
-            HIPCHK(c, hipMemcpyAsync(c->host_st, c->st, 8 * sizeof(double),
-                                     hipMemcpyDeviceToHost, c->stream));
-            if (read_jds(c) != NGF_OK) return NGF_E_HIP;
-            if (h == 0) gtd = c->host_st->gtd;
+            if (read_jds(c) != NGF_OK) return NGF_E_HIP;  // J of the trial and g^T d
+            if (h == 0) gtd = c->host_jds[5];
             const double Jt = c->host_jds[0];
             if (std::isfinite(Jt) && Jt <= c->lb_J + c1 * t * gtd) {
                 ok = true;
@@ -792,7 +854,8 @@ ngf_status ngf_lbfgs_step(ngf_ctx* c, double* J, int32_t* info) {
             inf = NGF_INFO_LINESEARCH_FAIL;
         } else {
             const int nb = lb_dot_blocks(n);
-            launch_lb_update_dots(c->st, c->hist, n, c->ly, c->lyt, c->lg, c->lgt, c->dotpart,
+            launch_lb_update_dots(c->st, c->hist, static_cast<int64_t>(c->lb_ld), n, c->ly, c->lyt,
+                                  c->lg, c->lgt, c->dotpart,
                                   nb, c->stream);
             launch_lb_gram_update(c->st, c->dotpart, nb, c->jds, c->stream);
             HIPCHK(c, hipGetLastError());
@@ -842,6 +905,7 @@ ngf_status ngf_register_levels(ngf_ctx* c, float* y_out, ngf_report* rep) {
     }
     const int L = static_cast<int>(c->lv.size());
     for (int lev = L - 1; lev >= 0; --lev) {
+        const auto t_level = std::chrono::steady_clock::now();
         const Level& lv = c->lv[lev];
         if (lev == L - 1) {
             launch_identity(c->ltmp, lv.my[0], lv.my[1], lv.my[2], lv.hy[0], lv.hy[1], lv.hy[2],
@@ -872,6 +936,10 @@ ngf_status ngf_register_levels(ngf_ctx* c, float* y_out, ngf_report* rep) {
             }
         }
         if (rep) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            rep->ms[lev] = std::chrono::duration<double, std::milli>(
+                               std::chrono::steady_clock::now() - t_level)
+                               .count();
             rep->iters[lev] = it;
             rep->evals[lev] = c->lb_evals;
             rep->J[lev] = c->lb_J;

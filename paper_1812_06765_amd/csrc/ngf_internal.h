@@ -16,14 +16,35 @@ constexpr int kBasisG = 2 * kSlots;             // basis index of the gradient
 // Image-pass tile (voxels per axis).  Tiles are aligned to the deformation
 // grid: each extent is a multiple of the grid ratio.
 constexpr int kTX = 8, kTY = 8, kTZ = 32;
-// Marching image pass: (y, z) tile; the x chunk is a run-time choice.
-constexpr int kMY = 16, kMZ = 64;
+// Marching image pass: (y, z) tile of kMY x (32 or 64); the x chunk is a
+// run-time choice.
+constexpr int kMY = 16;
 // Node-pass tile (nodes per axis).
 constexpr int kNX = 4, kNY = 8, kNZ = 32;
 
-// Image-pass variants the autotuner chooses from.
-enum Variant { kTile3D = 0, kMarch8 = 1, kMarch20 = 2, kMarch32 = 3, kNumVariants = 4 };
-inline int march_cx(int v) { return v == kMarch8 ? 8 : (v == kMarch20 ? 20 : 32); }
+// Image-pass variants the autotuner chooses from: the 3D-tile kernel, and the
+// marching kernel with in-plane tile 16 x 64 or 16 x 32 and x chunks of 8,
+// 20 or 32 planes.
+enum Variant {
+    kTile3D = 0,
+    kMarch64x8 = 1, kMarch64x20 = 2, kMarch64x32 = 3,
+    kMarch32x8 = 4, kMarch32x20 = 5, kMarch32x32 = 6,
+    kTile3DSmall = 7,  // 3D tile of 4 x 8 x 32 voxels (coarse levels)
+    kNumVariants = 8
+};
+constexpr int kVariantBySize = -2;  // selection rule instead of timed selection
+inline bool is_march(int v) { return v >= kMarch64x8 && v <= kMarch32x32; }
+constexpr int kSTX = 4;  // small 3D tile: kSTX x kTY x kTZ
+inline int march_cx(int v) { return (v - 1) % 3 == 0 ? 8 : ((v - 1) % 3 == 1 ? 20 : 32); }
+inline int march_tz(int v) { return v <= kMarch64x32 ? 64 : 32; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Renumbering block b to (b mod 8) * (n / 8) + b / 8 gives each XCD a
+// contiguous range of tiles, so neighbouring tiles (which share halo data)
+// meet in the same L2.  A bijection when n is a multiple of 8.
+__device__ inline int xcd_tile(int b, int n) {
+    return (n & 7) == 0 ? (b & 7) * (n >> 3) + (b >> 3) : b;
+}
 
 // One pyramid level as the kernels see it.
 struct LevelView {
@@ -115,8 +136,8 @@ void launch_index_map(int32_t* j0, float* w0, float* w1, int m, int my, hipStrea
 void launch_identity(float* y, int nx, int ny, int nz, double hx, double hy, double hz,
                      hipStream_t s);
 void launch_prolongate(const float* yc, float* yf, int cx, int cy, int cz, hipStream_t s);
-void launch_image_pass(const ImagePassArgs& a, int ratio, hipStream_t s);
-void launch_image_march(const ImagePassArgs& a, int ratio, int cx, hipStream_t s);
+void launch_image_pass(const ImagePassArgs& a, int ratio, hipStream_t s, bool small = false);
+void launch_image_march(const ImagePassArgs& a, int ratio, int tz, int cx, hipStream_t s);
 void launch_node_pass(const NodePassArgs& a, hipStream_t s);
 void launch_reduce(const ReduceArgs& a, hipStream_t s);
 void launch_check_finite(const float* v, int64_t n, int* flag, hipStream_t s);
@@ -132,12 +153,12 @@ void launch_apply_PT(const int32_t* const j0[3], const float* const w0[3],
                      float* out, int scheme, hipStream_t s);
 
 // L-BFGS vector kernels
-void launch_lb_solve(LbState* st, hipStream_t s);
-void launch_lb_combine(LbState* st, const float* hist, int64_t n, const float* y,
+void launch_lb_solve(LbState* st, double* jds, hipStream_t s);
+void launch_lb_combine(LbState* st, const float* hist, int64_t ld, int64_t n, const float* y,
                        const float* g, float* d, float* yt, hipStream_t s);
 void launch_lb_axpy(const float* y, const float* d, float t, float* yt, int64_t n,
                     hipStream_t s);
-void launch_lb_update_dots(LbState* st, float* hist, int64_t n, const float* y,
+void launch_lb_update_dots(LbState* st, float* hist, int64_t ld, int64_t n, const float* y,
                            const float* yt, const float* g, const float* gt,
                            double* dotpart, int nblocks, hipStream_t s);
 void launch_lb_gram_update(LbState* st, const double* dotpart, int nblocks,

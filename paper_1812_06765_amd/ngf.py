@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("iters", ctypes.c_int32 * MAX_LEVELS),
                 ("evals", ctypes.c_int32 * MAX_LEVELS), ("info", ctypes.c_int32 * MAX_LEVELS),
-                ("J", ctypes.c_double * MAX_LEVELS)]
+                ("J", ctypes.c_double * MAX_LEVELS), ("ms", ctypes.c_double * MAX_LEVELS)]
 
 
 class NgfError(RuntimeError):
@@ -93,6 +93,13 @@ def load():
         "ngf_kernel_time": ([_P, ctypes.POINTER(i32), ctypes.POINTER(f64),
                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
                             i32),
+        "ngf_batch_create": ([ctypes.POINTER(Params), i32, ctypes.POINTER(_P)], i32),
+        "ngf_batch_destroy": ([_P], None),
+        "ngf_batch_last_error": ([_P], ctypes.c_char_p),
+        "ngf_batch_set_kernel": ([_P, i32], i32),
+        "ngf_batch_register": ([_P, i32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                ctypes.POINTER(Grid), ctypes.POINTER(_P), _P,
+                                ctypes.POINTER(Report)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -268,7 +275,7 @@ class Context:
     @staticmethod
     def _report(rep: Report):
         return [dict(level=lev, iters=rep.iters[lev], evals=rep.evals[lev], J=rep.J[lev],
-                     info=rep.info[lev]) for lev in range(rep.levels)]
+                     info=rep.info[lev], ms=rep.ms[lev]) for lev in range(rep.levels)]
 
     def register(self, R, T, h=(1.0, 1.0, 1.0)):
         """Full registration from R, T (device tensors, or CPU tensors for the
@@ -346,10 +353,12 @@ class Context:
         return out
 
     # -- kernel choice --------------------------------------------------------
-    VARIANTS = {"auto": -1, "tile3d": 0, "march8": 1, "march20": 2, "march32": 3}
+    VARIANTS = {"by_size": -2, "auto": -1, "tile3d": 0, "march64x8": 1, "march64x20": 2, "march64x32": 3,
+                "march32x8": 4, "march32x20": 5, "march32x32": 6, "tile3d_small": 7}
 
     def set_kernel(self, variant):
-        """Image-pass variant: 'auto' (autotune), 'tile3d', 'march8/20/32', or its number."""
+        """Image-pass variant: 'auto' (autotune), 'by_size' (size rule), a name
+        of VARIANTS, or its number."""
         v = self.VARIANTS.get(variant, variant)
         self._chk(self.lib.ngf_set_kernel(self.h, int(v)))
 
@@ -375,3 +384,73 @@ class Context:
 
 def version() -> str:
     return load().ngf_version().decode()
+
+
+class Batch:
+    """An ngf_batch: independent registrations of many image pairs of any
+    shapes on one device, run concurrently by ``workers`` host threads, each
+    with its own context and stream.  Each pair's result equals the
+    single-pair ``Context.register`` result for the same image-pass variant."""
+
+    def __init__(self, alpha=0.1, tau=1.0, rho=1.0, levels=1, ratio=2, max_iter=50,
+                 lbfgs_mem=5, tol_J=1e-6, early_stop=False, workers=4, device="cuda"):
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the ngf library has no CPU path")
+        self.device = torch.device(device)
+        self.p = Params(float(alpha), float(tau), float(rho), int(levels), int(ratio),
+                        int(max_iter), int(lbfgs_mem), float(tol_J), int(bool(early_stop)), 0)
+        h = _P()
+        with torch.cuda.device(self.device):
+            st = self.lib.ngf_batch_create(ctypes.byref(self.p), int(workers), ctypes.byref(h))
+        if st != OK:
+            raise NgfError(st, "ngf_batch_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ngf_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st != OK:
+            raise NgfError(st, self.lib.ngf_batch_last_error(self.h).decode())
+
+    def set_kernel(self, variant):
+        v = Context.VARIANTS.get(variant, variant)
+        self._chk(self.lib.ngf_batch_set_kernel(self.h, int(v)))
+
+    def register(self, Rs, Ts, hs=None, out=None):
+        """Register pairs (Rs[i], Ts[i]) (contiguous float32 device tensors)
+        with spacings hs[i] (default 1).  Returns (list of y, list of
+        per-level reports)."""
+        n = len(Rs)
+        if len(Ts) != n:
+            raise ValueError("as many templates as references are needed")
+        hs = hs if hs is not None else [(1.0, 1.0, 1.0)] * n
+        grids = (Grid * max(n, 1))()
+        ys = []
+        for i in range(n):
+            for name, t in (("R", Rs[i]), ("T", Ts[i])):
+                if not (isinstance(t, torch.Tensor) and t.dtype == torch.float32 and t.is_cuda
+                        and t.is_contiguous() and t.dim() == 3):
+                    raise TypeError(f"{name}[{i}] must be a contiguous 3D float32 GPU tensor")
+            if tuple(Rs[i].shape) != tuple(Ts[i].shape):
+                raise ValueError(f"pair {i}: R and T differ in shape")
+            grids[i] = _grid(Rs[i].shape, hs[i])
+            my = tuple(int(v) // self.p.ratio + 1 for v in Rs[i].shape)
+            y = out[i] if out is not None else torch.empty((3,) + my, dtype=torch.float32,
+                                                           device=self.device)
+            ys.append(y)
+        arr = lambda ts: (_P * max(n, 1))(*[t.data_ptr() for t in ts])
+        reps = (Report * max(n, 1))()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self._chk(self.lib.ngf_batch_register(self.h, n, arr(Rs), arr(Ts), grids, arr(ys),
+                                              ctypes.c_void_p(stream), reps))
+        return ys, [Context._report(reps[i]) for i in range(n)]

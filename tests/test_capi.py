@@ -56,6 +56,16 @@ def test_version_and_argument_checks_without_gpu(lib):
     assert lib.ngf_create(None, None, ctypes.byref(h)) == E_ARG
     p = Params(**good)
     assert lib.ngf_create(ctypes.byref(p), None, None) == E_ARG
+    # batched form: worker count and null arguments are checked first
+    lib.ngf_batch_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_void_p)]
+    lib.ngf_batch_create.restype = ctypes.c_int32
+    for w in (0, -1, 17):
+        assert lib.ngf_batch_create(ctypes.byref(p), w, ctypes.byref(h)) == E_ARG, w
+    assert lib.ngf_batch_create(None, 4, ctypes.byref(h)) == E_ARG
+    assert lib.ngf_batch_create(ctypes.byref(p), 4, None) == E_ARG
+    lib.ngf_batch_register.restype = ctypes.c_int32
+    assert lib.ngf_batch_register(None, 0, None, None, None, None, None, None) == E_ARG
 
 
 def test_build_sources_and_flags():

@@ -45,7 +45,8 @@ def _y(prob, amp, seed, spacing=8.0):
     return (prob.identity() + d).astype(np.float32)
 
 
-VARIANTS = ("tile3d", "march8", "march20", "march32")
+VARIANTS = ("tile3d", "march64x8", "march64x20", "march64x32", "march32x8", "march32x20",
+            "march32x32", "tile3d_small")
 
 
 def _check_eval(ngf, ctx, level, prob, y32, tag, variants=VARIANTS):
@@ -188,12 +189,12 @@ def test_autotuner_choice_is_valid_and_cached(gpu_lib):
     ctx = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=3)
     ctx.build_pyramid(_t(pr.R), _t(pr.T))
     first = [ctx.get_kernel(lev) for lev in range(3)]
-    assert all(v in (0, 1, 2, 3) for v in first)
+    assert all(0 <= v <= 7 for v in first)
     ctx.build_pyramid(_t(pr.R), _t(pr.T))  # same shapes: cached choice
     assert [ctx.get_kernel(lev) for lev in range(3)] == first
     _say(f"[autotune] 128^3 pyramid choices {first}")
-    ctx.set_kernel("march32")
-    assert [ctx.get_kernel(lev) for lev in range(3)] == [3, 3, 3]
+    ctx.set_kernel("march32x20")
+    assert [ctx.get_kernel(lev) for lev in range(3)] == [5, 5, 5]
 
 
 def test_eval_deterministic(gpu_lib):
