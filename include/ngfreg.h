@@ -225,6 +225,18 @@ ngf_status ngf_prolongate(ngf_ctx* ctx, int32_t coarse_level, const float* y_c, 
 ngf_status ngf_register(ngf_ctx* ctx, const float* R, const float* T, const ngf_grid* g,
                         float* y_out, int32_t host_ptrs, ngf_report* rep);
 
+/* Who drives the line search of ngf_register / ngf_register_levels.
+ *   mode 0 (default): the device.  Each L-BFGS round (direction or halved
+ *     step, trial evaluation, Armijo test, history update, stopping tests) is
+ *     a fixed sequence of kernels that read and advance a control block in
+ *     device memory; the host enqueues rounds in batches of up to 16 and
+ *     reads the control block once per batch.
+ *   mode 1: the host, through ngf_lbfgs_step, reading J back after every
+ *     trial evaluation.
+ * Both take the same decisions on the same numbers: results are identical
+ * bit for bit.  Errors: NGF_E_ARG for another mode. */
+ngf_status ngf_set_driver(ngf_ctx* ctx, int32_t mode);
+
 /* As ngf_register, from the pyramid already built by ngf_build_pyramid
  * (device-resident inputs; the pyramid step is not repeated). */
 ngf_status ngf_register_levels(ngf_ctx* ctx, float* y_out, ngf_report* rep);

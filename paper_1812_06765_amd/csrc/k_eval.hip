@@ -445,6 +445,7 @@ __device__ __forceinline__ void image_body(const ImagePassArgs& a, int block) {
 // ------------------------------------------------------------------------
 template <int TX, int TY, int TZ, int RATIO, bool GRAD, bool ATOMIC, bool POW2>
 __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
+    if (a.gate && *a.gate == kOpNone) return;
     image_body<TX, TY, TZ, RATIO, GRAD, ATOMIC, POW2>(a, blockIdx.x);
 }
 
@@ -574,6 +575,7 @@ __device__ __forceinline__ void node_body(const NodePassArgs& a, int block) {
 
 template <int NX, int NY, int NZ>
 __global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
+    if (a.gate && *a.gate == kOpNone) return;
     node_body<NX, NY, NZ>(a, blockIdx.x);
 }
 

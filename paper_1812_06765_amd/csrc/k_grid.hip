@@ -136,6 +136,7 @@ __device__ double block_sum_fixed(const double* a, int n, double* sh) {
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
+    if (a.gate && *a.gate == kOpNone) return;
     __shared__ double sh[kThreads];
     const double d = block_sum_fixed(a.dpart, a.nd, sh);
     const double s = block_sum_fixed(a.spart, a.ns, sh);

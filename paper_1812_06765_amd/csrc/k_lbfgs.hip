@@ -17,6 +17,8 @@
 
 #include <math.h>
 
+#include "../../include/ngfreg.h"
+
 namespace ngf {
 
 namespace {
@@ -30,7 +32,21 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-__device__ inline void lb_init_one(LbState* st, int mem, double hmin, const double* jds) {
+__device__ inline void lb_init_one(LbState* st, int mem, double hmin, const double* jds,
+                                   int max_iter, int early_stop, double tol) {
+    LbCtl& c = st->ctl;
+    c.op = kOpNone;
+    c.phase = kPhNeedDir;
+    c.halvings = 0;
+    c.iters = 0;
+    c.evals = 1;
+    c.info = NGF_INFO_MAX_ITER;
+    c.max_iter = max_iter;
+    c.early_stop = early_stop;
+    c.t = 1.0;
+    c.tol = tol;
+    c.J = jds[0];
+    c.gmax = jds[3];
     st->count = 0;
     st->free_slot = 0;
     st->mem = mem;
@@ -49,8 +65,10 @@ __device__ inline void lb_init_one(LbState* st, int mem, double hmin, const doub
     st->G[kBasisG * kBasis + kBasisG] = jds[4];
 }
 
-__global__ void k_lb_init(LbState* st, int mem, double hmin, const double* jds) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) lb_init_one(st, mem, hmin, jds);
+__global__ void k_lb_init(LbState* st, int mem, double hmin, const double* jds, int max_iter,
+                          int early_stop, double tol) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        lb_init_one(st, mem, hmin, jds, max_iter, early_stop, tol);
 }
 
 // Direction coefficients by the two-loop recursion over the Gram matrix.
@@ -220,14 +238,16 @@ __global__ __launch_bounds__(kThreads) void k_lb_axpy(const float* __restrict__ 
 // products of {s, t, gt} with the stored pairs and with each other.
 // Per-block float64 partials: dotpart[block][kDots].  Two elements per
 // thread and iteration (8-byte loads), then a scalar tail.
+// With ACCEPT, the accepted trial point also replaces the current one
+// (y = yt, g = gt), each element by the thread that has just read it.
+template <bool ACCEPT>
 __device__ __forceinline__ void lb_update_dots_body(const LbState* st,
-                                                             float* __restrict__ hist,
-                                                             int64_t ld, int64_t n,
-                                                             const float* __restrict__ y,
-                                                             const float* __restrict__ yt,
-                                                             const float* __restrict__ g,
-                                                             const float* __restrict__ gt,
-                                                             double* __restrict__ dotpart, int block, int nblocks) {
+                                                    float* __restrict__ hist, int64_t ld,
+                                                    int64_t n, float* y,
+                                                    const float* __restrict__ yt, float* g,
+                                                    const float* __restrict__ gt,
+                                                    double* __restrict__ dotpart, int block,
+                                                    int nblocks) {
     __shared__ int sl[kSlots];
     __shared__ int cnt, fs;
     __shared__ double sh[4][kDots];
@@ -276,6 +296,10 @@ __device__ __forceinline__ void lb_update_dots_body(const LbState* st,
         const float2 t = make_float2(gtv.x - gv.x, gtv.y - gv.y);
         reinterpret_cast<float2*>(sn)[q] = s;
         reinterpret_cast<float2*>(tn)[q] = t;
+        if (ACCEPT) {
+            reinterpret_cast<float2*>(y)[q] = ytv;
+            reinterpret_cast<float2*>(g)[q] = gtv;
+        }
         float a0[kSlots], b0[kSlots], a1[kSlots], b1[kSlots];
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
@@ -296,10 +320,15 @@ __device__ __forceinline__ void lb_update_dots_body(const LbState* st,
     }
     for (int64_t i = 2 * n2 + block * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
          i += stride) {
-        const float s = yt[i] - y[i];
-        const float t = gt[i] - g[i];
+        const float yti = yt[i], gti = gt[i];
+        const float s = yti - y[i];
+        const float t = gti - g[i];
         sn[i] = s;
         tn[i] = t;
+        if (ACCEPT) {
+            y[i] = yti;
+            g[i] = gti;
+        }
         float a[kSlots], b[kSlots];
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
@@ -307,7 +336,7 @@ __device__ __forceinline__ void lb_update_dots_body(const LbState* st,
             a[k] = k < count ? sk[i] : 0.0f;
             b[k] = k < count ? sk[ld + i] : 0.0f;
         }
-        add(s, t, gt[i], a, b);
+        add(s, t, gti, a, b);
     }
     const int w = threadIdx.x >> 6;
 #pragma unroll
@@ -329,7 +358,8 @@ __global__ __launch_bounds__(kThreads) void k_lb_update_dots(const LbState* st,
                                                              const float* __restrict__ g,
                                                              const float* __restrict__ gt,
                                                              double* __restrict__ dotpart) {
-    lb_update_dots_body(st, hist, ld, n, y, yt, g, gt, dotpart, blockIdx.x, gridDim.x);
+    lb_update_dots_body<false>(st, hist, ld, n, const_cast<float*>(y), yt,
+                               const_cast<float*>(g), gt, dotpart, blockIdx.x, gridDim.x);
 }
 
 // Fixed-order sum of the per-block dot partials, curvature test of the new
@@ -425,7 +455,137 @@ __global__ __launch_bounds__(kGramThreads) void k_lb_gram_update(LbState* st,
     lb_gram_body(st, dotpart, nblocks, jds);
 }
 
+// ---------------------------------------------------------------------------
+// One round of the device-driven level.  Every kernel reads the control block
+// first and does nothing when its part of the round does not apply, so a
+// round enqueued after the level has ended is a no-op.
+// ---------------------------------------------------------------------------
+
+__device__ inline void lb_finish(LbCtl& c, int info) {
+    c.phase = kPhDone;
+    c.info = info;
+    c.op = kOpNone;
+}
+
+// Start of a round: a new direction (two-loop recursion) after an accepted
+// step, or the next halving of the step after a rejected trial.  The tests
+// before a new direction are those of one L-BFGS iteration: iteration
+// budget, non-finite gradient, zero gradient.
+__global__ void k_lb_plan(LbState* st, double* jds) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    LbCtl& c = st->ctl;
+    if (c.phase == kPhDone) {
+        c.op = kOpNone;
+    } else if (c.phase == kPhNeedDir) {
+        if (c.iters >= c.max_iter) {
+            lb_finish(c, NGF_INFO_MAX_ITER);
+        } else if (!isfinite(c.gmax)) {
+            lb_finish(c, NGF_INFO_NONFINITE);
+        } else if (c.gmax == 0.0) {
+            lb_finish(c, NGF_INFO_CONVERGED);
+        } else {
+            lb_solve_one(st, jds);
+            c.t = 1.0;
+            c.halvings = 0;
+            c.phase = kPhTrial;
+            c.op = kOpCombine;
+        }
+    } else {
+        c.op = kOpAxpy;  // kPhTrial after a rejection: same d, halved t
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_lb_vec(const LbState* st,
+                                                     const float* __restrict__ hist, int64_t ld,
+                                                     int64_t n, const float* __restrict__ y,
+                                                     const float* __restrict__ g,
+                                                     float* __restrict__ d,
+                                                     float* __restrict__ yt) {
+    const int op = st->ctl.op;
+    if (op == kOpCombine)
+        lb_combine_body(st, hist, ld, n, y, g, d, yt, blockIdx.x, gridDim.x);
+    else if (op == kOpAxpy)
+        lb_axpy_body(y, d, static_cast<float>(st->ctl.t), yt, n, blockIdx.x, gridDim.x);
+}
+
+// Armijo test of the trial just evaluated (c1 = 1e-4, at most 10 halvings).
+// Contraction is off so that the test rounds exactly as the host's.
+__global__ void k_lb_decide(LbState* st, const double* jds) {
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    LbCtl& c = st->ctl;
+    if (c.op == kOpNone) return;
+    c.evals += 1;
+    const double c1 = 1e-4;
+    const double Jt = jds[0];
+    if (isfinite(Jt) && Jt <= c.J + c1 * c.t * st->gtd) {
+        c.phase = kPhAccepted;
+    } else {
+        c.t *= 0.5;
+        c.halvings += 1;
+        if (c.halvings > 10) lb_finish(c, NGF_INFO_LINESEARCH_FAIL);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_lb_accept_dots(const LbState* st,
+                                                             float* __restrict__ hist,
+                                                             int64_t ld, int64_t n, float* y,
+                                                             const float* __restrict__ yt,
+                                                             float* g,
+                                                             const float* __restrict__ gt,
+                                                             double* __restrict__ dotpart) {
+    if (st->ctl.phase != kPhAccepted) return;
+    lb_update_dots_body<true>(st, hist, ld, n, y, yt, g, gt, dotpart, blockIdx.x, gridDim.x);
+}
+
+// Gram update for the accepted step, then the stopping tests of the level:
+// relative decrease (early stop) and the iteration budget.
+__global__ __launch_bounds__(kGramThreads) void k_lb_accept_gram(LbState* st,
+                                                                 const double* dotpart,
+                                                                 int nblocks,
+                                                                 const double* jds) {
+#pragma clang fp contract(off)
+    if (st->ctl.phase != kPhAccepted) return;
+    lb_gram_body(st, dotpart, nblocks, jds);
+    if (threadIdx.x != 0) return;
+    LbCtl& c = st->ctl;
+    const double J_old = c.J, J_new = jds[0];
+    c.J = J_new;
+    c.gmax = jds[3];
+    c.iters += 1;
+    c.op = kOpNone;
+    if (c.early_stop && (J_old - J_new) <= c.tol * (1.0 + fabs(J_old)))
+        lb_finish(c, NGF_INFO_CONVERGED);
+    else if (c.iters >= c.max_iter)
+        lb_finish(c, NGF_INFO_MAX_ITER);
+    else
+        c.phase = kPhNeedDir;
+}
+
 }  // namespace
+
+void launch_lb_plan(LbState* st, double* jds, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_plan, dim3(1), dim3(64), 0, s, st, jds);
+}
+
+void launch_lb_vec(LbState* st, const float* hist, int64_t ld, int64_t n, const float* y,
+                   const float* g, float* d, float* yt, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_vec, dim3(lb_dot_blocks(n)), dim3(kThreads), 0, s, st, hist, ld, n,
+                       y, g, d, yt);
+}
+
+void launch_lb_decide(LbState* st, const double* jds, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_decide, dim3(1), dim3(64), 0, s, st, jds);
+}
+
+void launch_lb_accept(LbState* st, float* hist, int64_t ld, int64_t n, float* y,
+                      const float* yt, float* g, const float* gt, double* dotpart,
+                      int nblocks, const double* jds, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_accept_dots, dim3(nblocks), dim3(kThreads), 0, s, st, hist, ld, n,
+                       y, yt, g, gt, dotpart);
+    hipLaunchKernelGGL(k_lb_accept_gram, dim3(1), dim3(kGramThreads), 0, s, st, dotpart,
+                       nblocks, jds);
+}
 
 int lb_dot_blocks(int64_t n) {
     int64_t b = (n + kThreads - 1) / kThreads;
@@ -434,8 +594,10 @@ int lb_dot_blocks(int64_t n) {
     return static_cast<int>(b);
 }
 
-void launch_lb_init(LbState* st, int mem, double hmin, const double* jds, hipStream_t s) {
-    hipLaunchKernelGGL(k_lb_init, dim3(1), dim3(64), 0, s, st, mem, hmin, jds);
+void launch_lb_init(LbState* st, int mem, double hmin, const double* jds, int max_iter,
+                    int early_stop, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_init, dim3(1), dim3(64), 0, s, st, mem, hmin, jds, max_iter,
+                       early_stop, tol);
 }
 
 void launch_lb_solve(LbState* st, double* jds, hipStream_t s) {

@@ -498,6 +498,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
 template <int TY, int TZ, int R, bool GRAD, bool POW2>
 __global__ __launch_bounds__(kThreads, TZ == 32 ? 3 : 2) void k_image_march(ImagePassArgs a,
                                                                             int CX) {
+    if (a.gate && *a.gate == kOpNone) return;
     march_body<TY, TZ, R, GRAD, POW2>(a, CX, blockIdx.x);
 }
 

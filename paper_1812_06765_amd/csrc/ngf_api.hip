@@ -66,7 +66,7 @@ struct ngf_ctx {
     double* gpart = nullptr;
     size_t nblk_cap = 0;
     double* jds = nullptr;       // device {J, D, S, max|g|, |g|^2, ...}
-    double* host_jds = nullptr;  // pinned
+    double* host_jds = nullptr;  // pinned: 8 doubles, then room for an LbCtl
     int* dflag = nullptr;
 
     // L-BFGS
@@ -85,6 +85,8 @@ struct ngf_ctx {
     double lb_J = 0.0;
     double lb_gmax = 0.0;
     int lb_evals = 0;
+
+    bool host_driven = false;  // register_levels: host-side line search (one sync per trial)
 
     // image-pass variant: -1 = autotune, else forced for every level
     int forced_variant = -1;  // also kVariantBySize
@@ -350,9 +352,10 @@ ImagePassArgs image_args(ngf_ctx* c, const Level& L, const float* R, const float
 // Enqueue one evaluation on the context stream; results land in c->jds and
 // (if grad != nullptr) in grad.
 ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float* T,
-                        const float* y, float* grad) {
+                        const float* y, float* grad, const int* gate = nullptr) {
     const bool want = grad != nullptr;
     ImagePassArgs a = image_args(c, L, R, T, y, want);
+    a.gate = gate;
     auto launch = [&] {
         if (!is_march(L.variant))
             launch_image_pass(a, c->p.ratio, c->stream, L.variant == kTile3DSmall);
@@ -402,6 +405,7 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
     b.want_grad = want ? 1 : 0;
     b.gather = 1;
     b.gscale = nullptr;
+    b.gate = gate;
     launch_node_pass(b, c->stream);
     HIPCHK(c, hipGetLastError());
     ReduceArgs r{};
@@ -415,6 +419,7 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
     r.half_hbary = 0.5 * hbary;
     r.alpha = c->p.alpha;
     r.out = c->jds;
+    r.gate = gate;
     launch_reduce(r, c->stream);
     HIPCHK(c, hipGetLastError());
     return NGF_OK;
@@ -531,6 +536,81 @@ ngf_status autotune(ngf_ctx* c) {
     return st;
 }
 
+bool early_stop_met(double J_old, double J_new, double tol) {
+#pragma clang fp contract(off)
+    return (J_old - J_new) <= tol * (1.0 + std::fabs(J_old));
+}
+
+// Armijo test, rounded exactly as the device's (no contraction).
+bool armijo_ok(double Jt, double J, double c1, double t, double gtd) {
+#pragma clang fp contract(off)
+    return std::isfinite(Jt) && Jt <= J + c1 * t * gtd;
+}
+
+// One round of the device-driven level: plan, vector update, gated
+// evaluation of the trial point, Armijo decision, gated history update.
+// Returns whether the round's image pass was recorded for profiling.
+ngf_status enqueue_round(ngf_ctx* c, const Level& L, bool* recorded) {
+    const int64_t n = 3 * L.Ny();
+    const int* gate = &c->st->ctl.op;
+    launch_lb_plan(c->st, c->jds, c->stream);
+    launch_lb_vec(c->st, c->hist, static_cast<int64_t>(c->lb_ld), n, c->ly, c->lg, c->ld,
+                  c->lyt, c->stream);
+    HIPCHK(c, hipGetLastError());
+    const int before = c->nprof;
+    const ngf_status e = enqueue_eval(c, L, L.R, L.T, c->lyt, c->lgt, gate);
+    if (e != NGF_OK) return e;
+    *recorded = c->nprof > before;
+    launch_lb_decide(c->st, c->jds, c->stream);
+    launch_lb_accept(c->st, c->hist, static_cast<int64_t>(c->lb_ld), n, c->ly, c->lyt, c->lg,
+                     c->lgt, c->dotpart, lb_dot_blocks(n), c->jds, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return NGF_OK;
+}
+
+// Run the L-BFGS iterations of the level set up by ngf_lbfgs_reset on the
+// device: rounds are enqueued in batches and the control block is read back
+// once per batch.  Rounds after the end of the level do nothing; their
+// profiling records (if any) are dropped.  Same arithmetic and decisions as
+// repeated ngf_lbfgs_step calls with the early-stop test between them.
+ngf_status run_level_on_device(ngf_ctx* c, LbCtl* out) {
+    const Level& L = c->lv[c->lb_level];
+    const int64_t cap = static_cast<int64_t>(c->p.max_iter) * 11 + 2;  // rounds that can do work
+    std::vector<char> rec;
+    int64_t rounds = 0;
+    // every round makes at most one step: size a batch by the remaining budget
+    int batch = std::max(1, std::min(kRoundBatch, c->p.max_iter));
+    LbCtl* h = reinterpret_cast<LbCtl*>(c->host_jds + 8);
+    for (;;) {
+        for (int k = 0; k < batch; ++k) {
+            bool r = false;
+            const ngf_status e = enqueue_round(c, L, &r);
+            if (e != NGF_OK) return e;
+            rec.push_back(r ? 1 : 0);
+            ++rounds;
+        }
+        HIPCHK(c, hipMemcpyAsync(h, &c->st->ctl, sizeof(LbCtl), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        if (h->phase == kPhDone) break;
+        if (rounds > cap) return fail(c, NGF_E_STATE, "device line search did not terminate");
+        batch = std::max(1, std::min(kRoundBatch, h->max_iter - h->iters));
+    }
+    // rounds that ran an evaluation come first; drop the records of the rest
+    const int64_t working = h->evals - 1;
+    for (int64_t r = rounds - 1; r >= working && r >= 0; --r)
+        if (rec[r]) {
+            c->nprof--;
+            c->prof_vox -= L.N();
+            c->prof_nodes -= L.Ny();
+        }
+    *out = *h;
+    c->lb_J = h->J;
+    c->lb_gmax = h->gmax;
+    c->lb_evals = h->evals;
+    return NGF_OK;
+}
+
 ngf_status check_level(const ngf_ctx* c, int level) {
     if (c->lv.empty()) return NGF_E_STATE;
     if (level < 0 || level >= static_cast<int>(c->lv.size())) return NGF_E_LEVEL;
@@ -563,8 +643,8 @@ ngf_status ngf_create(const ngf_params* p, void* stream, ngf_ctx** out) {
     chk(hipStreamCreateWithFlags(&c->side[1], hipStreamNonBlocking));
     for (int i = 0; i < 3; ++i) chk(hipEventCreateWithFlags(&c->join[i], hipEventDisableTiming));
     chk(hipMalloc(reinterpret_cast<void**>(&c->jds), 8 * sizeof(double)));
-    chk(hipHostMalloc(reinterpret_cast<void**>(&c->host_jds), 8 * sizeof(double),
-                      hipHostMallocDefault));
+    chk(hipHostMalloc(reinterpret_cast<void**>(&c->host_jds),
+                      8 * sizeof(double) + sizeof(LbCtl), hipHostMallocDefault));
     chk(hipMalloc(reinterpret_cast<void**>(&c->st), sizeof(LbState)));
     chk(hipMalloc(reinterpret_cast<void**>(&c->dflag), sizeof(int)));
     if (s != NGF_OK) {
@@ -703,6 +783,13 @@ ngf_status ngf_set_kernel(ngf_ctx* c, int32_t variant) {
     return NGF_OK;
 }
 
+ngf_status ngf_set_driver(ngf_ctx* c, int32_t mode) {
+    if (!c) return NGF_E_ARG;
+    if (mode != 0 && mode != 1) return fail(c, NGF_E_ARG, "mode must be 0 or 1");
+    c->host_driven = mode == 1;
+    return NGF_OK;
+}
+
 ngf_status ngf_get_kernel(const ngf_ctx* c, int32_t level, int32_t* variant) {
     if (!c || !variant) return NGF_E_ARG;
     const ngf_status s = check_level(c, level);
@@ -805,7 +892,8 @@ ngf_status ngf_lbfgs_reset(ngf_ctx* c, int32_t level, const float* y0) {
     ngf_status e = enqueue_eval(c, L, L.R, L.T, c->ly, c->lg);
     if (e != NGF_OK) return e;
     const double hmin = std::min(L.h[0], std::min(L.h[1], L.h[2]));
-    launch_lb_init(c->st, c->p.lbfgs_mem, hmin, c->jds, c->stream);
+    launch_lb_init(c->st, c->p.lbfgs_mem, hmin, c->jds, c->p.max_iter, c->p.early_stop,
+                   c->p.tol_J, c->stream);
     HIPCHK(c, hipGetLastError());
     if (read_jds(c) != NGF_OK) return NGF_E_HIP;
     c->lb_level = level;
@@ -844,7 +932,7 @@ ngf_status ngf_lbfgs_step(ngf_ctx* c, double* J, int32_t* info) {
             if (read_jds(c) != NGF_OK) return NGF_E_HIP;  // J of the trial and g^T d
             if (h == 0) gtd = c->host_jds[5];
             const double Jt = c->host_jds[0];
-            if (std::isfinite(Jt) && Jt <= c->lb_J + c1 * t * gtd) {
+            if (armijo_ok(Jt, c->lb_J, c1, t, gtd)) {
                 ok = true;
                 break;
             }
@@ -919,21 +1007,29 @@ ngf_status ngf_register_levels(ngf_ctx* c, float* y_out, ngf_report* rep) {
         if (e != NGF_OK) return e;
         int it = 0;
         int32_t info = NGF_INFO_MAX_ITER;
-        while (it < c->p.max_iter) {
-            const double J_old = c->lb_J;
-            int32_t inf = 0;
-            double Jn = 0.0;
-            e = ngf_lbfgs_step(c, &Jn, &inf);
+        if (c->host_driven) {
+            while (it < c->p.max_iter) {
+                const double J_old = c->lb_J;
+                int32_t inf = 0;
+                double Jn = 0.0;
+                e = ngf_lbfgs_step(c, &Jn, &inf);
+                if (e != NGF_OK) return e;
+                if (inf != NGF_INFO_OK) {
+                    info = inf;
+                    break;
+                }
+                ++it;
+                if (c->p.early_stop && early_stop_met(J_old, Jn, c->p.tol_J)) {
+                    info = NGF_INFO_CONVERGED;
+                    break;
+                }
+            }
+        } else {
+            LbCtl ctl{};
+            e = run_level_on_device(c, &ctl);
             if (e != NGF_OK) return e;
-            if (inf != NGF_INFO_OK) {
-                info = inf;
-                break;
-            }
-            ++it;
-            if (c->p.early_stop && (J_old - Jn) <= c->p.tol_J * (1.0 + std::fabs(J_old))) {
-                info = NGF_INFO_CONVERGED;
-                break;
-            }
+            it = ctl.iters;
+            info = ctl.info;
         }
         if (rep) {
             HIPCHK(c, hipStreamSynchronize(c->stream));

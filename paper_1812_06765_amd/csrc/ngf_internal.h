@@ -83,6 +83,7 @@ struct ImagePassArgs {
     float* gy_atomic;      // [3][my], accumulated in place (zeroed beforehand)
     float* gT_atomic;      // [mx][my][mz], accumulated in place (zeroed beforehand)
     const double* gscale;  // device scalar multiplying both (null: 1)
+    const int* gate;       // device flag: the pass does nothing when *gate == kOpNone (null: always run)
 };
 
 struct NodePassArgs {
@@ -102,6 +103,7 @@ struct NodePassArgs {
     int want_grad;
     int gather;            // 1: sum the image-tile partials; 0: grad already holds grad D
     const double* gscale;  // device scalar multiplying alpha grad S when gather == 0
+    const int* gate;       // as in ImagePassArgs
 };
 
 struct ReduceArgs {
@@ -110,12 +112,35 @@ struct ReduceArgs {
     const double* gpart; int ng;   // pairs (max, sumsq); ng == 0: skip
     double half_hbar, half_hbary, alpha;
     double* out;                    // {J, D, S, max|g|, |g|^2}
+    const int* gate;                // as in ImagePassArgs
 };
 
 // L-BFGS device state; lives in device memory, read and written by the
 // vector kernels and the single-thread solver.
+// Device-driven L-BFGS level: the line search as a state machine that the
+// kernels of one round (plan, vector update, evaluation, decision, history
+// update) advance, so that the host can enqueue rounds without reading
+// anything back in between.
+enum LbPhase : int { kPhNeedDir = 0, kPhTrial = 1, kPhAccepted = 2, kPhDone = 3 };
+enum LbOp : int { kOpNone = 0, kOpCombine = 1, kOpAxpy = 2 };
+constexpr int kRoundBatch = 16;  // rounds enqueued between reads of the control block
+struct LbCtl {
+    int op;          // what the current round's vector kernel does (first: the gate)
+    int phase;
+    int halvings;    // rejected trials along the current direction
+    int iters;       // accepted steps on this level
+    int evals;       // evaluations on this level (the start point's included)
+    int info;        // NGF_INFO_* once phase == kPhDone
+    int max_iter;
+    int early_stop;
+    double t;        // trial step length
+    double tol;      // early-stop tolerance
+    double J;        // objective at the current point
+    double gmax;     // max |grad J| at the current point
+};
+
 struct LbState {
-    // read back by the host after every trial evaluation (first 8 doubles):
+    LbCtl ctl;                      // read back by the host between batches of rounds
     double J, D, S, gmax, gnorm2;   // copy of the last evaluation
     double gtd;                     // g^T d of the current direction
     double flags;                   // bit 0: memory reset, bit 1: zero gradient
@@ -154,6 +179,14 @@ void launch_apply_PT(const int32_t* const j0[3], const float* const w0[3],
 
 // L-BFGS vector kernels
 void launch_lb_solve(LbState* st, double* jds, hipStream_t s);
+// one round of the device-driven level (see LbCtl)
+void launch_lb_plan(LbState* st, double* jds, hipStream_t s);
+void launch_lb_vec(LbState* st, const float* hist, int64_t ld, int64_t n, const float* y,
+                   const float* g, float* d, float* yt, hipStream_t s);
+void launch_lb_decide(LbState* st, const double* jds, hipStream_t s);
+void launch_lb_accept(LbState* st, float* hist, int64_t ld, int64_t n, float* y,
+                      const float* yt, float* g, const float* gt, double* dotpart,
+                      int nblocks, const double* jds, hipStream_t s);
 void launch_lb_combine(LbState* st, const float* hist, int64_t ld, int64_t n, const float* y,
                        const float* g, float* d, float* yt, hipStream_t s);
 void launch_lb_axpy(const float* y, const float* d, float t, float* yt, int64_t n,
@@ -163,7 +196,8 @@ void launch_lb_update_dots(LbState* st, float* hist, int64_t ld, int64_t n, cons
                            double* dotpart, int nblocks, hipStream_t s);
 void launch_lb_gram_update(LbState* st, const double* dotpart, int nblocks,
                            const double* jds, hipStream_t s);
-void launch_lb_init(LbState* st, int mem, double hmin, const double* jds, hipStream_t s);
+void launch_lb_init(LbState* st, int mem, double hmin, const double* jds, int max_iter,
+                    int early_stop, double tol, hipStream_t s);
 int lb_dot_blocks(int64_t n);
 
 

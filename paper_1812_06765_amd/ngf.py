@@ -87,6 +87,7 @@ def load():
                            _P, _P, ctypes.POINTER(f64), _P, _P, _P], i32),
         "ngf_set_profiling": ([_P, i32], i32),
         "ngf_set_kernel": ([_P, i32], i32),
+        "ngf_set_driver": ([_P, i32], i32),
         "ngf_apply_P": ([_P, i32, _P, _P], i32),
         "ngf_apply_PT": ([_P, i32, _P, _P, i32], i32),
         "ngf_get_kernel": ([_P, i32, ctypes.POINTER(i32)], i32),
@@ -361,6 +362,10 @@ class Context:
         of VARIANTS, or its number."""
         v = self.VARIANTS.get(variant, variant)
         self._chk(self.lib.ngf_set_kernel(self.h, int(v)))
+
+    def set_driver(self, mode):
+        """Line search of register(): 'device' (default) or 'host'."""
+        self._chk(self.lib.ngf_set_driver(self.h, {"device": 0, "host": 1}[mode]))
 
     def get_kernel(self, level):
         v = ctypes.c_int32()

@@ -272,6 +272,42 @@ def test_register_multilevel_and_host_path(gpu_lib):
     assert [r["J"] for r in rep] == [r["J"] for r in rep2]
 
 
+@pytest.mark.parametrize("case", ["multilevel", "early_stop", "max_iter0", "tiny_budget"])
+def test_device_and_host_line_search_agree_bitwise(gpu_lib, case):
+    """The device-driven level (control block advanced by the kernels of each
+    round) and the host-driven one (ngf_lbfgs_step) take the same decisions
+    on the same numbers: identical y, J, iteration and evaluation counts."""
+    import torch
+    ngf = gpu_lib
+    if case == "multilevel":
+        pr = synth.ct_phantom_pair((64, 64, 64), seed_R=3, seed_u=4)
+        kw = dict(alpha=0.1, tau=10.0, rho=10.0, levels=3, max_iter=25)
+    elif case == "early_stop":
+        pr = synth.blob_phantom_pair((32, 32, 32), seed_R=1, seed_u=2, max_disp=2.0)
+        kw = dict(alpha=0.1, tau=0.1, rho=0.1, levels=2, max_iter=200, early_stop=True,
+                  tol_J=1e-4)
+    elif case == "max_iter0":
+        pr = synth.blob_phantom_pair((32, 32, 32), seed_R=1, seed_u=2, max_disp=2.0)
+        kw = dict(alpha=0.1, tau=0.1, rho=0.1, levels=2, max_iter=0)
+    else:
+        pr = synth.ct_phantom_pair((48, 32, 40), seed_R=5, seed_u=6)
+        kw = dict(alpha=0.1, tau=10.0, rho=10.0, levels=2, max_iter=3)
+    out = []
+    for mode in ("device", "host"):
+        ctx = _ctx(ngf, **kw)
+        ctx.set_driver(mode)
+        y, rep = ctx.register(_t(pr.R), _t(pr.T))
+        out.append((y.clone(), [{k: v for k, v in r.items() if k != "ms"} for r in rep]))
+        ctx.close()
+    _say(f"[driver] {case}: device {out[0][1]} host {out[1][1]}")
+    assert torch.equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+    if case == "early_stop":
+        assert any(r["info"] == ngf.INFO_CONVERGED for r in out[0][1])
+    if case == "max_iter0":
+        assert all(r["iters"] == 0 and r["evals"] == 1 for r in out[0][1])
+
+
 def test_error_paths(gpu_lib):
     ngf = gpu_lib
     import torch
