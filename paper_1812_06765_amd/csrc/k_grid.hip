@@ -123,6 +123,7 @@ __global__ __launch_bounds__(kThreads) void k_fill(float* p, int64_t n, float v)
 // t + 256, ... in order, then a fixed tree over the 256 thread sums.
 __device__ double block_sum_fixed(const double* a, int n, double* sh) {
     double s = 0.0;
+#pragma unroll 4
     for (int i = threadIdx.x; i < n; i += kThreads) s += a[i];
     sh[threadIdx.x] = s;
     __syncthreads();
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
     double gm = 0.0, g2 = 0.0;
     if (a.ng > 0) {
         double m = 0.0, q = 0.0;
+#pragma unroll 4
         for (int i = threadIdx.x; i < a.ng; i += kThreads) {
             m = fmax(m, a.gpart[2 * i]);
             q += a.gpart[2 * i + 1];
@@ -166,11 +168,13 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
     if (threadIdx.x == 0) {
         const double D = a.half_hbar * d;
         const double S = a.half_hbary * s;
-        a.out[0] = D + a.alpha * S;
+        const double J = D + a.alpha * S;
+        a.out[0] = J;
         a.out[1] = D;
         a.out[2] = S;
         a.out[3] = gm;
         a.out[4] = g2;
+        if (a.lb) lb_decide_one(a.lb, J);
     }
 }
 

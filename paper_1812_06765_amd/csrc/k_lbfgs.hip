@@ -77,13 +77,32 @@ __global__ void k_lb_init(LbState* st, int mem, double hmin, const double* jds, 
 // The current point's J, max |g| and |g|^2 are taken from the state, where
 // k_lb_init and k_lb_gram_update put them.  g^T d also goes to jds[5], which
 // the next evaluation's reduction leaves alone (it writes jds[0..4]).
-__device__ inline void lb_solve_one(LbState* st, double* jds) {
-    double* G = st->G;
+// Working set of the recursion, staged in LDS by the calling kernel: the
+// recursion is a chain of dependent reads and small-array updates, far
+// cheaper from LDS than from L2 or from scratch memory.
+struct SolveLds {
+    double G[kBasis * kBasis];
+    double q[kBasis];
+    double al[kSlots];
+    int order[kSlots];
+};
+
+__device__ inline void lb_stage(const LbState* st, SolveLds& w) {
+    for (int i = threadIdx.x; i < kBasis * kBasis; i += blockDim.x) w.G[i] = st->G[i];
+    for (int i = threadIdx.x; i < kSlots; i += blockDim.x) w.order[i] = st->order[i];
+    __syncthreads();
+}
+
+// One lane.  The g^T g entry of G refers to the current gradient: it is set
+// in the staged copy and in the state.
+__device__ inline void lb_solve_one(LbState* st, double* jds, SolveLds& w) {
+    double* G = w.G;
+    double* q = w.q;
     G[kBasisG * kBasis + kBasisG] = st->gnorm2;
+    st->G[kBasisG * kBasis + kBasisG] = st->gnorm2;
     double flags = 0.0;
-    double coef[kBasis];
-    for (int i = 0; i < kBasis; ++i) coef[i] = 0.0;
     double gtd = 0.0;
+    for (int i = 0; i < kBasis; ++i) q[i] = 0.0;
     if (!(st->gmax > 0.0)) {
         st->flags = 2.0;
         st->gtd = 0.0;
@@ -93,28 +112,26 @@ __device__ inline void lb_solve_one(LbState* st, double* jds) {
     }
     int count = st->count;
     if (count > 0) {
-        double q[kBasis], al[kSlots];
-        for (int i = 0; i < kBasis; ++i) q[i] = 0.0;
         q[kBasisG] = 1.0;
         for (int k = count - 1; k >= 0; --k) {
-            const int si = st->order[k], ti = kSlots + st->order[k];
+            const int si = w.order[k], ti = kSlots + w.order[k];
             double sq = 0.0;
             for (int l = 0; l < kBasis; ++l) sq += q[l] * G[si * kBasis + l];
-            al[k] = sq / G[si * kBasis + ti];
-            q[ti] -= al[k];
+            w.al[k] = sq / G[si * kBasis + ti];
+            q[ti] -= w.al[k];
         }
-        const int sn = st->order[count - 1], tn = kSlots + st->order[count - 1];
+        const int sn = w.order[count - 1], tn = kSlots + w.order[count - 1];
         const double gamma = G[sn * kBasis + tn] / G[tn * kBasis + tn];
         for (int i = 0; i < kBasis; ++i) q[i] *= gamma;
         for (int k = 0; k < count; ++k) {
-            const int si = st->order[k], ti = kSlots + st->order[k];
+            const int si = w.order[k], ti = kSlots + w.order[k];
             double tr = 0.0;
             for (int l = 0; l < kBasis; ++l) tr += q[l] * G[ti * kBasis + l];
             const double b = tr / G[si * kBasis + ti];
-            q[si] += al[k] - b;
+            q[si] += w.al[k] - b;
         }
-        for (int i = 0; i < kBasis; ++i) coef[i] = -q[i];
-        for (int l = 0; l < kBasis; ++l) gtd += coef[l] * G[kBasisG * kBasis + l];
+        for (int i = 0; i < kBasis; ++i) q[i] = -q[i];  // the coefficients of d
+        for (int l = 0; l < kBasis; ++l) gtd += q[l] * G[kBasisG * kBasis + l];
         if (!(gtd < 0.0)) {
             count = 0;
             flags = 1.0;
@@ -125,11 +142,11 @@ __device__ inline void lb_solve_one(LbState* st, double* jds) {
         for (int i = 0; i < kSlots; ++i) st->order[i] = -1;
         st->free_slot = 0;
         const double scale = st->hmin / st->gmax;
-        for (int i = 0; i < kBasis; ++i) coef[i] = 0.0;
-        coef[kBasisG] = -scale;
+        for (int i = 0; i < kBasis; ++i) q[i] = 0.0;
+        q[kBasisG] = -scale;
         gtd = -scale * st->gnorm2;
     }
-    for (int i = 0; i < kBasis; ++i) st->coef[i] = coef[i];
+    for (int i = 0; i < kBasis; ++i) st->coef[i] = q[i];
     st->gtd = gtd;
     st->flags = flags;
     st->count_d = static_cast<double>(st->count);
@@ -137,7 +154,9 @@ __device__ inline void lb_solve_one(LbState* st, double* jds) {
 }
 
 __global__ void k_lb_solve(LbState* st, double* jds) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) lb_solve_one(st, jds);
+    __shared__ SolveLds w;
+    lb_stage(st, w);
+    if (threadIdx.x == 0) lb_solve_one(st, jds, w);
 }
 
 // d = sum_l coef_l b_l over the active basis; yt = y + d.  Four elements per
@@ -234,55 +253,41 @@ __global__ __launch_bounds__(kThreads) void k_lb_axpy(const float* __restrict__ 
     lb_axpy_body(y, d, t, yt, n, blockIdx.x, gridDim.x);
 }
 
-// Forms the new pair s = yt - y, t = gt - g in the free slot and all inner
-// products of {s, t, gt} with the stored pairs and with each other.
-// Per-block float64 partials: dotpart[block][kDots].  Two elements per
-// thread and iteration (8-byte loads), then a scalar tail.
-// With ACCEPT, the accepted trial point also replaces the current one
-// (y = yt, g = gt), each element by the thread that has just read it.
-template <bool ACCEPT>
-__device__ __forceinline__ void lb_update_dots_body(const LbState* st,
-                                                    float* __restrict__ hist, int64_t ld,
-                                                    int64_t n, float* y,
-                                                    const float* __restrict__ yt, float* g,
-                                                    const float* __restrict__ gt,
-                                                    double* __restrict__ dotpart, int block,
-                                                    int nblocks) {
-    __shared__ int sl[kSlots];
-    __shared__ int cnt, fs;
-    __shared__ double sh[4][kDots];
-    if (threadIdx.x == 0) {
-        cnt = st->count;
-        fs = st->free_slot;
-        for (int k = 0; k < kSlots; ++k) sl[k] = k < st->count ? st->order[k] : 0;
-    }
-    __syncthreads();
-    const int count = cnt;
-    double acc[kDots];
+// Pass over the elements for C stored pairs (a compile-time count, so that
+// only 6 C + 6 float64 accumulators are live).  With ACCEPT, the accepted
+// trial point also replaces the current one (y = yt, g = gt), each element
+// by the thread that has just read it.
+template <bool ACCEPT, int C>
+__device__ __forceinline__ void lb_dots_pass(const int* sl, int fs, float* __restrict__ hist,
+                                             int64_t ld, int64_t n, float* y,
+                                             const float* __restrict__ yt, float* g,
+                                             const float* __restrict__ gt,
+                                             double* __restrict__ dotpart, int block,
+                                             int nblocks, double (*sh)[kDots]) {
+    constexpr int kA = 6 * C + 6;  // live accumulators; self products last
+    double acc[kA];
 #pragma unroll
-    for (int j = 0; j < kDots; ++j) acc[j] = 0.0;
+    for (int j = 0; j < kA; ++j) acc[j] = 0.0;
     float* sn = hist + (2 * static_cast<int64_t>(fs)) * ld;
     float* tn = sn + ld;
     auto add = [&](float s, float t, float gn, const float* a, const float* b) {
         const double sd = s, td = t, gd = gn;
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
-            if (k < count) {
-                const double av = a[k], bv = b[k];
-                acc[6 * k + 0] += sd * av;
-                acc[6 * k + 1] += sd * bv;
-                acc[6 * k + 2] += td * av;
-                acc[6 * k + 3] += td * bv;
-                acc[6 * k + 4] += gd * av;
-                acc[6 * k + 5] += gd * bv;
-            }
+        for (int k = 0; k < C; ++k) {
+            const double av = a[k], bv = b[k];
+            acc[6 * k + 0] += sd * av;
+            acc[6 * k + 1] += sd * bv;
+            acc[6 * k + 2] += td * av;
+            acc[6 * k + 3] += td * bv;
+            acc[6 * k + 4] += gd * av;
+            acc[6 * k + 5] += gd * bv;
         }
-        acc[6 * kSlots + 0] += sd * sd;
-        acc[6 * kSlots + 1] += sd * td;
-        acc[6 * kSlots + 2] += sd * gd;
-        acc[6 * kSlots + 3] += td * td;
-        acc[6 * kSlots + 4] += td * gd;
-        acc[6 * kSlots + 5] += gd * gd;
+        acc[6 * C + 0] += sd * sd;
+        acc[6 * C + 1] += sd * td;
+        acc[6 * C + 2] += sd * gd;
+        acc[6 * C + 3] += td * td;
+        acc[6 * C + 4] += td * gd;
+        acc[6 * C + 5] += gd * gd;
     };
     const int64_t n2 = n >> 1;
     const int64_t stride = static_cast<int64_t>(nblocks) * kThreads;
@@ -300,20 +305,16 @@ __device__ __forceinline__ void lb_update_dots_body(const LbState* st,
             reinterpret_cast<float2*>(y)[q] = ytv;
             reinterpret_cast<float2*>(g)[q] = gtv;
         }
-        float a0[kSlots], b0[kSlots], a1[kSlots], b1[kSlots];
+        float a0[C > 0 ? C : 1], b0[C > 0 ? C : 1], a1[C > 0 ? C : 1], b1[C > 0 ? C : 1];
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
-            if (k < count) {
-                const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
-                const float2 av = reinterpret_cast<const float2*>(sk)[q];
-                const float2 bv = reinterpret_cast<const float2*>(sk + ld)[q];
-                a0[k] = av.x;
-                a1[k] = av.y;
-                b0[k] = bv.x;
-                b1[k] = bv.y;
-            } else {
-                a0[k] = a1[k] = b0[k] = b1[k] = 0.0f;
-            }
+        for (int k = 0; k < C; ++k) {
+            const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
+            const float2 av = reinterpret_cast<const float2*>(sk)[q];
+            const float2 bv = reinterpret_cast<const float2*>(sk + ld)[q];
+            a0[k] = av.x;
+            a1[k] = av.y;
+            b0[k] = bv.x;
+            b1[k] = bv.y;
         }
         add(s.x, t.x, gtv.x, a0, b0);
         add(s.y, t.y, gtv.y, a1, b1);
@@ -329,27 +330,76 @@ __device__ __forceinline__ void lb_update_dots_body(const LbState* st,
             y[i] = yti;
             g[i] = gti;
         }
-        float a[kSlots], b[kSlots];
+        float a[C > 0 ? C : 1], b[C > 0 ? C : 1];
 #pragma unroll
-        for (int k = 0; k < kSlots; ++k) {
+        for (int k = 0; k < C; ++k) {
             const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
-            a[k] = k < count ? sk[i] : 0.0f;
-            b[k] = k < count ? sk[ld + i] : 0.0f;
+            a[k] = sk[i];
+            b[k] = sk[ld + i];
         }
         add(s, t, gti, a, b);
     }
+    // wave sums, then the four waves in a fixed order; dots of unused slots are 0
     const int w = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < kDots; ++j) {
+    for (int j = 0; j < kA; ++j) {
         const double v = wave_sum(acc[j]);
-        if ((threadIdx.x & 63) == 0) sh[w][j] = v;
+        const int o = j < 6 * C ? j : 6 * kSlots + (j - 6 * C);
+        if ((threadIdx.x & 63) == 0) sh[w][o] = v;
     }
+    for (int o = 6 * C + threadIdx.x; o < 6 * kSlots; o += kThreads)
+        sh[0][o] = sh[1][o] = sh[2][o] = sh[3][o] = 0.0;
     __syncthreads();
     for (int j = threadIdx.x; j < kDots; j += kThreads)
         dotpart[static_cast<int64_t>(block) * kDots + j] =
             (sh[0][j] + sh[1][j]) + (sh[2][j] + sh[3][j]);
 }
 
+// Forms the new pair s = yt - y, t = gt - g in the free slot and all inner
+// products of {s, t, gt} with the stored pairs and with each other.
+// Per-block float64 partials: dotpart[block][kDots].  Two elements per
+// thread and iteration (8-byte loads), then a scalar tail.
+// CMAX: the largest pair count the kernel is built for (the L-BFGS memory
+// rounded up to 5 or 8); registers are allocated for the largest case.
+template <bool ACCEPT, int CMAX>
+__device__ __forceinline__ void lb_update_dots_body(const LbState* st,
+                                                    float* __restrict__ hist, int64_t ld,
+                                                    int64_t n, float* y,
+                                                    const float* __restrict__ yt, float* g,
+                                                    const float* __restrict__ gt,
+                                                    double* __restrict__ dotpart, int block,
+                                                    int nblocks) {
+    __shared__ int sl[kSlots];
+    __shared__ int cnt, fs;
+    __shared__ double sh[4][kDots];
+    if (threadIdx.x == 0) {
+        cnt = st->count;
+        fs = st->free_slot;
+        for (int k = 0; k < kSlots; ++k) sl[k] = k < st->count ? st->order[k] : 0;
+    }
+    __syncthreads();
+    switch (cnt) {
+#define NGF_DOTS_CASE(C)                                                                \
+    case C:                                                                             \
+        lb_dots_pass<ACCEPT, (C <= CMAX ? C : CMAX)>(sl, fs, hist, ld, n, y, yt, g, gt,   \
+                                                     dotpart, block, nblocks, sh);      \
+        break;
+        NGF_DOTS_CASE(0)
+        NGF_DOTS_CASE(1)
+        NGF_DOTS_CASE(2)
+        NGF_DOTS_CASE(3)
+        NGF_DOTS_CASE(4)
+        NGF_DOTS_CASE(5)
+        NGF_DOTS_CASE(6)
+        NGF_DOTS_CASE(7)
+        NGF_DOTS_CASE(8)
+#undef NGF_DOTS_CASE
+        default:
+            break;
+    }
+}
+
+template <int CMAX>
 __global__ __launch_bounds__(kThreads) void k_lb_update_dots(const LbState* st,
                                                              float* __restrict__ hist,
                                                              int64_t ld, int64_t n,
@@ -358,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void k_lb_update_dots(const LbState* st,
                                                              const float* __restrict__ g,
                                                              const float* __restrict__ gt,
                                                              double* __restrict__ dotpart) {
-    lb_update_dots_body<false>(st, hist, ld, n, const_cast<float*>(y), yt,
+    lb_update_dots_body<false, CMAX>(st, hist, ld, n, const_cast<float*>(y), yt,
                                const_cast<float*>(g), gt, dotpart, blockIdx.x, gridDim.x);
 }
 
@@ -378,9 +428,11 @@ __device__ __forceinline__ void lb_gram_body(LbState* st,
     {
         const int j = threadIdx.x & 63, p = threadIdx.x >> 6;
         double s = 0.0;
-        if (j < kDots)
+        if (j < kDots) {
+#pragma unroll 8
             for (int b = p; b < nblocks; b += kGramPhases)
                 s += dotpart[static_cast<int64_t>(b) * kDots + j];
+        }
         ph[p][j] = s;
     }
     __syncthreads();
@@ -461,18 +513,15 @@ __global__ __launch_bounds__(kGramThreads) void k_lb_gram_update(LbState* st,
 // round enqueued after the level has ended is a no-op.
 // ---------------------------------------------------------------------------
 
-__device__ inline void lb_finish(LbCtl& c, int info) {
-    c.phase = kPhDone;
-    c.info = info;
-    c.op = kOpNone;
-}
 
 // Start of a round: a new direction (two-loop recursion) after an accepted
 // step, or the next halving of the step after a rejected trial.  The tests
 // before a new direction are those of one L-BFGS iteration: iteration
 // budget, non-finite gradient, zero gradient.
 __global__ void k_lb_plan(LbState* st, double* jds) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ SolveLds w;
+    lb_stage(st, w);
+    if (threadIdx.x != 0) return;
     LbCtl& c = st->ctl;
     if (c.phase == kPhDone) {
         c.op = kOpNone;
@@ -484,7 +533,7 @@ __global__ void k_lb_plan(LbState* st, double* jds) {
         } else if (c.gmax == 0.0) {
             lb_finish(c, NGF_INFO_CONVERGED);
         } else {
-            lb_solve_one(st, jds);
+            lb_solve_one(st, jds, w);
             c.t = 1.0;
             c.halvings = 0;
             c.phase = kPhTrial;
@@ -508,25 +557,8 @@ __global__ __launch_bounds__(kThreads) void k_lb_vec(const LbState* st,
         lb_axpy_body(y, d, static_cast<float>(st->ctl.t), yt, n, blockIdx.x, gridDim.x);
 }
 
-// Armijo test of the trial just evaluated (c1 = 1e-4, at most 10 halvings).
-// Contraction is off so that the test rounds exactly as the host's.
-__global__ void k_lb_decide(LbState* st, const double* jds) {
-#pragma clang fp contract(off)
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    LbCtl& c = st->ctl;
-    if (c.op == kOpNone) return;
-    c.evals += 1;
-    const double c1 = 1e-4;
-    const double Jt = jds[0];
-    if (isfinite(Jt) && Jt <= c.J + c1 * c.t * st->gtd) {
-        c.phase = kPhAccepted;
-    } else {
-        c.t *= 0.5;
-        c.halvings += 1;
-        if (c.halvings > 10) lb_finish(c, NGF_INFO_LINESEARCH_FAIL);
-    }
-}
 
+template <int CMAX>
 __global__ __launch_bounds__(kThreads) void k_lb_accept_dots(const LbState* st,
                                                              float* __restrict__ hist,
                                                              int64_t ld, int64_t n, float* y,
@@ -535,7 +567,8 @@ __global__ __launch_bounds__(kThreads) void k_lb_accept_dots(const LbState* st,
                                                              const float* __restrict__ gt,
                                                              double* __restrict__ dotpart) {
     if (st->ctl.phase != kPhAccepted) return;
-    lb_update_dots_body<true>(st, hist, ld, n, y, yt, g, gt, dotpart, blockIdx.x, gridDim.x);
+    lb_update_dots_body<true, CMAX>(st, hist, ld, n, y, yt, g, gt, dotpart, blockIdx.x,
+                                    gridDim.x);
 }
 
 // Gram update for the accepted step, then the stopping tests of the level:
@@ -574,15 +607,15 @@ void launch_lb_vec(LbState* st, const float* hist, int64_t ld, int64_t n, const 
                        y, g, d, yt);
 }
 
-void launch_lb_decide(LbState* st, const double* jds, hipStream_t s) {
-    hipLaunchKernelGGL(k_lb_decide, dim3(1), dim3(64), 0, s, st, jds);
-}
-
 void launch_lb_accept(LbState* st, float* hist, int64_t ld, int64_t n, float* y,
                       const float* yt, float* g, const float* gt, double* dotpart,
-                      int nblocks, const double* jds, hipStream_t s) {
-    hipLaunchKernelGGL(k_lb_accept_dots, dim3(nblocks), dim3(kThreads), 0, s, st, hist, ld, n,
-                       y, yt, g, gt, dotpart);
+                      int nblocks, const double* jds, int mem, hipStream_t s) {
+    if (mem <= 5)
+        hipLaunchKernelGGL(k_lb_accept_dots<5>, dim3(nblocks), dim3(kThreads), 0, s, st, hist,
+                           ld, n, y, yt, g, gt, dotpart);
+    else
+        hipLaunchKernelGGL(k_lb_accept_dots<kMaxMem>, dim3(nblocks), dim3(kThreads), 0, s, st,
+                           hist, ld, n, y, yt, g, gt, dotpart);
     hipLaunchKernelGGL(k_lb_accept_gram, dim3(1), dim3(kGramThreads), 0, s, st, dotpart,
                        nblocks, jds);
 }
@@ -617,9 +650,13 @@ void launch_lb_axpy(const float* y, const float* d, float t, float* yt, int64_t 
 
 void launch_lb_update_dots(LbState* st, float* hist, int64_t ld, int64_t n, const float* y,
                            const float* yt, const float* g, const float* gt, double* dotpart,
-                           int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_lb_update_dots, dim3(nblocks), dim3(kThreads), 0, s, st, hist, ld, n, y,
-                       yt, g, gt, dotpart);
+                           int nblocks, int mem, hipStream_t s) {
+    if (mem <= 5)
+        hipLaunchKernelGGL(k_lb_update_dots<5>, dim3(nblocks), dim3(kThreads), 0, s, st, hist,
+                           ld, n, y, yt, g, gt, dotpart);
+    else
+        hipLaunchKernelGGL(k_lb_update_dots<kMaxMem>, dim3(nblocks), dim3(kThreads), 0, s, st,
+                           hist, ld, n, y, yt, g, gt, dotpart);
 }
 
 void launch_lb_gram_update(LbState* st, const double* dotpart, int nblocks, const double* jds,

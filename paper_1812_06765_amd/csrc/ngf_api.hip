@@ -352,7 +352,8 @@ ImagePassArgs image_args(ngf_ctx* c, const Level& L, const float* R, const float
 // Enqueue one evaluation on the context stream; results land in c->jds and
 // (if grad != nullptr) in grad.
 ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float* T,
-                        const float* y, float* grad, const int* gate = nullptr) {
+                        const float* y, float* grad, const int* gate = nullptr,
+                        LbState* decide = nullptr) {
     const bool want = grad != nullptr;
     ImagePassArgs a = image_args(c, L, R, T, y, want);
     a.gate = gate;
@@ -420,6 +421,7 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
     r.alpha = c->p.alpha;
     r.out = c->jds;
     r.gate = gate;
+    r.lb = decide;
     launch_reduce(r, c->stream);
     HIPCHK(c, hipGetLastError());
     return NGF_OK;
@@ -548,7 +550,8 @@ bool armijo_ok(double Jt, double J, double c1, double t, double gtd) {
 }
 
 // One round of the device-driven level: plan, vector update, gated
-// evaluation of the trial point, Armijo decision, gated history update.
+// evaluation of the trial point (its reduction also takes the Armijo
+// decision), gated history update.
 // Returns whether the round's image pass was recorded for profiling.
 ngf_status enqueue_round(ngf_ctx* c, const Level& L, bool* recorded) {
     const int64_t n = 3 * L.Ny();
@@ -558,12 +561,11 @@ ngf_status enqueue_round(ngf_ctx* c, const Level& L, bool* recorded) {
                   c->lyt, c->stream);
     HIPCHK(c, hipGetLastError());
     const int before = c->nprof;
-    const ngf_status e = enqueue_eval(c, L, L.R, L.T, c->lyt, c->lgt, gate);
+    const ngf_status e = enqueue_eval(c, L, L.R, L.T, c->lyt, c->lgt, gate, c->st);
     if (e != NGF_OK) return e;
     *recorded = c->nprof > before;
-    launch_lb_decide(c->st, c->jds, c->stream);
     launch_lb_accept(c->st, c->hist, static_cast<int64_t>(c->lb_ld), n, c->ly, c->lyt, c->lg,
-                     c->lgt, c->dotpart, lb_dot_blocks(n), c->jds, c->stream);
+                     c->lgt, c->dotpart, lb_dot_blocks(n), c->jds, c->p.lbfgs_mem, c->stream);
     HIPCHK(c, hipGetLastError());
     return NGF_OK;
 }
@@ -943,8 +945,7 @@ ngf_status ngf_lbfgs_step(ngf_ctx* c, double* J, int32_t* info) {
         } else {
             const int nb = lb_dot_blocks(n);
             launch_lb_update_dots(c->st, c->hist, static_cast<int64_t>(c->lb_ld), n, c->ly, c->lyt,
-                                  c->lg, c->lgt, c->dotpart,
-                                  nb, c->stream);
+                                  c->lg, c->lgt, c->dotpart, nb, c->p.lbfgs_mem, c->stream);
             launch_lb_gram_update(c->st, c->dotpart, nb, c->jds, c->stream);
             HIPCHK(c, hipGetLastError());
             std::swap(c->ly, c->lyt);

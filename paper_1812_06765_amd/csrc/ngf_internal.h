@@ -3,6 +3,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "../../include/ngfreg.h"
 #include <stdint.h>
 
 namespace ngf {
@@ -39,11 +41,14 @@ inline int march_cx(int v) { return (v - 1) % 3 == 0 ? 8 : ((v - 1) % 3 == 1 ? 2
 inline int march_tz(int v) { return v <= kMarch64x32 ? 64 : 32; }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2.  Renumbering block b to (b mod 8) * (n / 8) + b / 8 gives each XCD a
-// contiguous range of tiles, so neighbouring tiles (which share halo data)
-// meet in the same L2.  A bijection when n is a multiple of 8.
-__device__ inline int xcd_tile(int b, int n) {
-    return (n & 7) == 0 ? (b & 7) * (n >> 3) + (b >> 3) : b;
+// L2.  Renumbering gives each XCD a contiguous range of tiles, so that
+// neighbouring tiles (which share halo data) meet in the same L2: XCD x
+// (= b mod 8) receives blocks x, x + 8, ..., i.e. q + (x < r) of them for
+// n = 8 q + r, and they take the tiles from x q + min(x, r) on.  A bijection
+// of [0, n) for every n.
+__host__ __device__ inline int xcd_tile(int b, int n) {
+    const int x = b & 7, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
 }
 
 // One pyramid level as the kernels see it.
@@ -106,6 +111,8 @@ struct NodePassArgs {
     const int* gate;       // as in ImagePassArgs
 };
 
+struct LbState;
+
 struct ReduceArgs {
     const double* dpart; int nd;
     const double* spart; int ns;
@@ -113,6 +120,7 @@ struct ReduceArgs {
     double half_hbar, half_hbary, alpha;
     double* out;                    // {J, D, S, max|g|, |g|^2}
     const int* gate;                // as in ImagePassArgs
+    LbState* lb;                    // device-driven level: Armijo test of J (null: none)
 };
 
 // L-BFGS device state; lives in device memory, read and written by the
@@ -155,6 +163,30 @@ struct LbState {
     double coef[kBasis];            // direction coefficients over the basis
 };
 
+__device__ inline void lb_finish(LbCtl& c, int info) {
+    c.phase = kPhDone;
+    c.info = info;
+    c.op = kOpNone;
+}
+
+// Armijo test of the trial just evaluated, objective Jt (c1 = 1e-4, at most
+// 10 halvings).  Contraction is off so that the test rounds exactly as the
+// host's.  One lane; no-op when the round had no trial.
+__device__ inline void lb_decide_one(LbState* st, double Jt) {
+#pragma clang fp contract(off)
+    LbCtl& c = st->ctl;
+    if (c.op == kOpNone) return;
+    c.evals += 1;
+    const double c1 = 1e-4;
+    if (isfinite(Jt) && Jt <= c.J + c1 * c.t * st->gtd) {
+        c.phase = kPhAccepted;
+    } else {
+        c.t *= 0.5;
+        c.halvings += 1;
+        if (c.halvings > 10) lb_finish(c, NGF_INFO_LINESEARCH_FAIL);
+    }
+}
+
 // kernels (definitions in the .hip files), launched from the host code
 void launch_downsample(const float* src, float* dst, int mx, int my, int mz, hipStream_t s);
 void launch_index_map(int32_t* j0, float* w0, float* w1, int m, int my, hipStream_t s);
@@ -183,17 +215,16 @@ void launch_lb_solve(LbState* st, double* jds, hipStream_t s);
 void launch_lb_plan(LbState* st, double* jds, hipStream_t s);
 void launch_lb_vec(LbState* st, const float* hist, int64_t ld, int64_t n, const float* y,
                    const float* g, float* d, float* yt, hipStream_t s);
-void launch_lb_decide(LbState* st, const double* jds, hipStream_t s);
 void launch_lb_accept(LbState* st, float* hist, int64_t ld, int64_t n, float* y,
                       const float* yt, float* g, const float* gt, double* dotpart,
-                      int nblocks, const double* jds, hipStream_t s);
+                      int nblocks, const double* jds, int mem, hipStream_t s);
 void launch_lb_combine(LbState* st, const float* hist, int64_t ld, int64_t n, const float* y,
                        const float* g, float* d, float* yt, hipStream_t s);
 void launch_lb_axpy(const float* y, const float* d, float t, float* yt, int64_t n,
                     hipStream_t s);
 void launch_lb_update_dots(LbState* st, float* hist, int64_t ld, int64_t n, const float* y,
                            const float* yt, const float* g, const float* gt,
-                           double* dotpart, int nblocks, hipStream_t s);
+                           double* dotpart, int nblocks, int mem, hipStream_t s);
 void launch_lb_gram_update(LbState* st, const double* dotpart, int nblocks,
                            const double* jds, hipStream_t s);
 void launch_lb_init(LbState* st, int mem, double hmin, const double* jds, int max_iter,
