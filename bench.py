@@ -32,6 +32,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# Vector ALU peak for this build: packed FP32 instructions are disabled, so
+# FP32 and FP64 FMAs issue at one per lane per clock:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# algorithmic flops of the image-grid pass per voxel (P 63, warp coordinate 6,
+# warped value 21, its derivative 22, central differences 12, NGF term and v
+# 36, adjoint stencil and chain rule 11, tile-local P^T 21)
+FLOPS_PER_VOXEL = 192
 METRIC = "J+∇J evals/s and full-registration seconds at 256^3; HBM GB/s vs peak"
 
 
@@ -43,9 +51,9 @@ def _src_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_hash, launches_bytes):
-    """HBM traffic of the image-pass kernel from a committed counter summary,
-    only if it was taken from the current kernel source."""
+def _traffic(kernel_hash):
+    """HBM bytes per launch of the 256^3 image-pass kernel from the committed
+    counter summary, only if it was taken from the current kernel source."""
     path = os.path.join(ROOT, "profiles", "image_pass_256_traffic.json")
     if not os.path.exists(path):
         return None
@@ -53,25 +61,36 @@ def _traffic(kernel_hash, launches_bytes):
         t = json.load(f)
     if t.get("kernel_src_sha256_16") != kernel_hash:
         return None
-    return t.get("hbm_bytes_per_launch_256")
+    return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(R, T, steps_s=None):
-    """One J + grad J evaluation of the FP64 oracle at the 256^3 level."""
+def cpu_baseline(R, T, evals=2):
+    """J + grad J evaluations of the FP64 oracle at the 256^3 level."""
     import numpy as np
 
     import oracle as O
     m = R.shape
     my = tuple(v // 2 + 1 for v in m)
     prob = O.Problem(R, T, (1.0, 1.0, 1.0), my, 0.1, 10.0, 10.0)
-    y = prob.identity().astype(np.float32).astype(np.float64)
-    t0 = time.perf_counter()
-    O.eval_J_grad(prob, y)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+    X = prob.identity()
+    # a smooth displacement of up to 2 voxels per component (separable sines)
+    j = [np.arange(n, dtype=np.float64) / (n - 1) for n in my]
+    wave = (np.sin(2 * np.pi * j[0])[:, None, None] * np.sin(np.pi * j[1])[None, :, None]
+            * np.cos(np.pi * j[2])[None, None, :])
+    ys = [X, X + 2.0 * np.stack([wave, -wave, 0.5 * wave])]
+    dt = 0.0
+    for k in range(evals):
+        y = ys[k % 2].astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        O.eval_J_grad(prob, y)
+        dt += time.perf_counter() - t0
+        print(f"[bench] oracle evaluation {k + 1}/{evals} done", file=sys.stderr, flush=True)
+    return {"value": evals / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
             "seconds": dt,
-            "sample": "one J+grad J evaluation of the float64 numpy oracle at the 256^3 "
-                      "finest level (129^3 nodes, identity deformation), single-threaded"}
+            "sample": f"{evals} J+grad J evaluations of the float64 numpy oracle at the "
+                      f"{m[0]}x{m[1]}x{m[2]} finest level ({my[0]}x{my[1]}x{my[2]} nodes; "
+                      "identity and a smooth displacement of up to 2 voxels), "
+                      "single-threaded numpy"}
 
 
 def bench_batch(args, torch, ngf, synth):
@@ -141,6 +160,8 @@ def main():
                     help="instead: the uneven batch of this many pairs (axes drawn from "
                          "96..256, 3 levels) through the batched form")
     ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--kernel", default="by_size",
+                    help="image-pass selection: by_size (default), auto, or a variant name")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only copy 1 GiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -176,6 +197,9 @@ def main():
     T = torch.from_numpy(pr.T).cuda()
     ctx = ngf.Context(alpha=0.1, tau=10.0, rho=10.0, levels=args.levels, ratio=2,
                       max_iter=args.max_iter, lbfgs_mem=5, tol_J=1e-6, early_stop=True)
+    # image-pass variants by the size rule (the timed selection's choices on
+    # cubic levels), so that no selection runs appear in a profile of this run
+    ctx.set_kernel(args.kernel)
 
     for _ in range(args.warmup):
         ctx.register(R, T)
@@ -193,7 +217,8 @@ def main():
         reports.append(rep)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    launches, kms, vox, nodes = ctx.kernel_time()
+    # the finest level's launches of the image pass, the dominant kernel
+    launches, kms, vox, nodes = ctx.kernel_time(level=0)
     ctx.set_profiling(False)
     print(f"[bench] timed {args.steps} registrations in {dt:.3f}s", file=sys.stderr, flush=True)
 
@@ -211,11 +236,14 @@ def main():
     Ny = li.my[0] * li.my[1] * li.my[2]
     finest_bytes = 8 * N + 24 * Ny
 
-    # roofline of the dominant kernel over the timed region: algorithmic bytes
-    # per launch = 8 N (read R, T) + 12 N^y (read y) + 12 N^y (write grad)
-    alg_bytes = 8 * vox + 24 * nodes
-    achieved = alg_bytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    # roofline of the dominant kernel (the image pass at the finest level)
+    # over the timed region: it is bound by vector-ALU issue, not by HBM
+    # (its traffic is a few hundred MB per launch at well under 1 TB/s)
+    avg_s = kms * 1e-3 / max(launches, 1)
+    flops_launch = FLOPS_PER_VOXEL * vox / max(launches, 1)
+    achieved = flops_launch / avg_s / 1e12 if kms > 0 else 0.0
     khash = _src_hash()
+    traffic = _traffic(khash)
     out = {
         "metric": METRIC,
         "value": evals / dt,
@@ -242,16 +270,19 @@ def main():
                    "compulsory_bytes": finest_bytes,
                    "effective_GBs": finest_bytes * args.finest_evals / tf / 1e9},
         "roofline": {
-            "kernel": "image pass (k_image_pass or k_image_march, as autotuned per level)",
-            "bound": "hbm",
+            "kernel": "image pass at the finest level (k_image_march<16, 64, 2, true, true>)",
+            "bound": "alu",
             "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": _traffic(khash, None),
+            "peak": ALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / ALU_PEAK_TFLOPS,
+            "traffic": traffic,
             "launches": launches,
-            "avg_launch_us": 1e3 * kms / max(launches, 1),
-            "alg_bytes_per_launch": alg_bytes / max(launches, 1),
+            "avg_launch_us": 1e6 * avg_s,
+            "flops_per_launch": flops_launch,
+            "flops_per_voxel": FLOPS_PER_VOXEL,
+            "hbm_GBs": (traffic / avg_s / 1e9) if traffic else None,
+            "hbm_frac": (traffic / avg_s / 1e9 / HBM_PEAK_GBS) if traffic else None,
             "kernel_src": khash,
         },
     }

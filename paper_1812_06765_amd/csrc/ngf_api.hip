@@ -100,9 +100,8 @@ struct ngf_ctx {
     // profiling of the image-pass kernel
     bool prof = false;
     std::vector<hipEvent_t> ev;
-    int nprof = 0;
-    int64_t prof_vox = 0;
-    int64_t prof_nodes = 0;
+    int nprof = 0;                 // records in use (events 2i, 2i + 1)
+    std::vector<int> prof_level;   // pyramid level of each record (-1: explicit pair)
 };
 
 namespace {
@@ -368,9 +367,11 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
         HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof], c->stream));
         launch();
         HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof + 1], c->stream));
+        int li = -1;
+        for (size_t l = 0; l < c->lv.size(); ++l)
+            if (&c->lv[l] == &L) li = static_cast<int>(l);
+        c->prof_level[c->nprof] = li;
         c->nprof++;
-        c->prof_vox += L.N();
-        c->prof_nodes += L.Ny();
     } else {
         launch();
     }
@@ -601,11 +602,7 @@ ngf_status run_level_on_device(ngf_ctx* c, LbCtl* out) {
     // rounds that ran an evaluation come first; drop the records of the rest
     const int64_t working = h->evals - 1;
     for (int64_t r = rounds - 1; r >= working && r >= 0; --r)
-        if (rec[r]) {
-            c->nprof--;
-            c->prof_vox -= L.N();
-            c->prof_nodes -= L.Ny();
-        }
+        if (rec[r]) c->nprof--;
     *out = *h;
     c->lb_J = h->J;
     c->lb_gmax = h->gmax;
@@ -1096,31 +1093,40 @@ ngf_status ngf_set_profiling(ngf_ctx* c, int32_t enable) {
     if (enable && c->ev.empty()) {
         c->ev.resize(2 * kProfMax, nullptr);
         for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
+        c->prof_level.assign(kProfMax, -1);
     }
     c->prof = enable != 0;
     c->nprof = 0;
-    c->prof_vox = 0;
-    c->prof_nodes = 0;
     return NGF_OK;
 }
 
-ngf_status ngf_kernel_time(ngf_ctx* c, int32_t* launches, double* total_ms, int64_t* voxels,
-                           int64_t* nodes) {
+ngf_status ngf_kernel_time(ngf_ctx* c, int32_t level, int32_t* launches, double* total_ms,
+                           int64_t* voxels, int64_t* nodes) {
     if (!c) return NGF_E_ARG;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double tot = 0.0;
+    int n = 0;
+    int64_t vox = 0, nod = 0;
     for (int i = 0; i < c->nprof; ++i) {
+        const int l = c->prof_level[i];
+        if (level >= 0 && l != level) continue;
         float ms = 0.0f;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
         tot += ms;
+        ++n;
+        if (l >= 0 && l < static_cast<int>(c->lv.size())) {
+            vox += c->lv[l].N();
+            nod += c->lv[l].Ny();
+        } else {
+            vox += c->pair.N();
+            nod += c->pair.Ny();
+        }
     }
-    if (launches) *launches = c->nprof;
+    if (launches) *launches = n;
     if (total_ms) *total_ms = tot;
-    if (voxels) *voxels = c->prof_vox;
-    if (nodes) *nodes = c->prof_nodes;
+    if (voxels) *voxels = vox;
+    if (nodes) *nodes = nod;
     c->nprof = 0;
-    c->prof_vox = 0;
-    c->prof_nodes = 0;
     return NGF_OK;
 }
 

@@ -91,7 +91,7 @@ def load():
         "ngf_apply_P": ([_P, i32, _P, _P], i32),
         "ngf_apply_PT": ([_P, i32, _P, _P, i32], i32),
         "ngf_get_kernel": ([_P, i32, ctypes.POINTER(i32)], i32),
-        "ngf_kernel_time": ([_P, ctypes.POINTER(i32), ctypes.POINTER(f64),
+        "ngf_kernel_time": ([_P, i32, ctypes.POINTER(i32), ctypes.POINTER(f64),
                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
                             i32),
         "ngf_batch_create": ([ctypes.POINTER(Params), i32, ctypes.POINTER(_P)], i32),
@@ -376,13 +376,14 @@ class Context:
     def set_profiling(self, enable=True):
         self._chk(self.lib.ngf_set_profiling(self.h, int(bool(enable))))
 
-    def kernel_time(self):
-        """(launches, total ms, voxels, nodes) of the recorded image-pass launches."""
+    def kernel_time(self, level=-1):
+        """(launches, total ms, voxels, nodes) of the recorded image-pass
+        launches on ``level`` (-1: all); clears the record."""
         n = ctypes.c_int32()
         ms = ctypes.c_double()
         vox = ctypes.c_int64()
         nod = ctypes.c_int64()
-        self._chk(self.lib.ngf_kernel_time(self.h, ctypes.byref(n), ctypes.byref(ms),
+        self._chk(self.lib.ngf_kernel_time(self.h, int(level), ctypes.byref(n), ctypes.byref(ms),
                                            ctypes.byref(vox), ctypes.byref(nod)))
         return n.value, ms.value, vox.value, nod.value
 

@@ -153,6 +153,37 @@ def test_eval_parity_ct_pyramid_levels(gpu_lib):
             _check_eval(ngf, ctx, lev, prob, _y(prob, amp, seed), f"ct128 amp={amp}")
 
 
+def _sine_field(my, amp):
+    """Smooth displacement of peak ``amp`` per component (separable sines),
+    cheap to form at any size."""
+    j = [np.arange(n, dtype=np.float64) / (n - 1) for n in my]
+    w = (np.sin(2 * np.pi * j[0])[:, None, None] * np.sin(np.pi * j[1])[None, :, None]
+         * np.cos(np.pi * j[2])[None, None, :])
+    return amp * np.stack([w, -w, 0.5 * w])
+
+
+def test_eval_parity_256_bench_configuration(gpu_lib):
+    """The headline size in the launch configuration the benchmark times:
+    256^3 CT pair, 4-level pyramid, image-pass variants by the size rule
+    (marching 16x64 tiles at 256^3), the full oracle evaluation at level 0
+    and at level 1."""
+    ngf = gpu_lib
+    pr = synth.ct_phantom_pair((256, 256, 256), seed_R=5, seed_u=6)
+    ctx = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=4)
+    ctx.set_kernel("by_size")
+    ctx.build_pyramid(_t(pr.R), _t(pr.T))
+    assert ctx.get_kernel(0) == ngf.Context.VARIANTS["march64x32"]
+    Rs, Ts = O.pyramid(pr.R, pr.T, 2)
+    names = {num: name for name, num in ngf.Context.VARIANTS.items()}
+    for lev, (m, h, my) in enumerate(O.level_shapes(pr.R.shape, (1.0, 1.0, 1.0), 2)):
+        prob = O.Problem(Rs[lev], Ts[lev], h, my, 0.1, 10.0, 10.0)
+        for amp in (0.0, 2.0 * h[0]):
+            ctx.set_kernel("by_size")
+            chosen = names[ctx.get_kernel(lev)]
+            y = (prob.identity() + _sine_field(my, amp)).astype(np.float32)
+            _check_eval(ngf, ctx, lev, prob, y, f"ct256 amp={amp}", variants=(chosen,))
+
+
 @pytest.mark.parametrize("m,h,ratio", [((44, 36, 40), (1.0, 1.5, 0.75), 2),
                                        ((24, 16, 72), (2.0, 1.0, 1.0), 2),
                                        ((36, 20, 132), (1.0, 1.0, 1.0), 2),
