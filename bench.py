@@ -244,6 +244,7 @@ def main():
     achieved = flops_launch / avg_s / 1e12 if kms > 0 else 0.0
     khash = _src_hash()
     traffic = _traffic(khash)
+    kname = {v: k for k, v in ngf.Context.VARIANTS.items()}[ctx.get_kernel(0)]
     out = {
         "metric": METRIC,
         "value": evals / dt,
@@ -270,7 +271,7 @@ def main():
                    "compulsory_bytes": finest_bytes,
                    "effective_GBs": finest_bytes * args.finest_evals / tf / 1e9},
         "roofline": {
-            "kernel": "image pass at the finest level (k_image_march<16, 64, 2, true, true>)",
+            "kernel": f"image pass at the finest level (variant {kname})",
             "bound": "alu",
             "achieved": achieved,
             "peak": ALU_PEAK_TFLOPS,

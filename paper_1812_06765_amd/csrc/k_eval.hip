@@ -579,24 +579,24 @@ __global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
     node_body<NX, NY, NZ>(a, blockIdx.x);
 }
 
-template <int TX, int RATIO>
-void launch_image_ratio(const ImagePassArgs& a, hipStream_t s) {
-    using L = ImageTile<TX, kTY, kTZ, RATIO>;
+template <int TX, int TY, int TZ, int RATIO>
+void launch_image_tile(const ImagePassArgs& a, hipStream_t s) {
+    using L = ImageTile<TX, TY, TZ, RATIO>;
     const int blocks = a.ntx * a.nty * a.ntz;
     const size_t lds = sizeof(float) * L::LDS_FLOATS;
     if (a.want_grad) {
         if (a.pow2h)
-            hipLaunchKernelGGL((k_image_pass<TX, kTY, kTZ, RATIO, true, false, true>),
+            hipLaunchKernelGGL((k_image_pass<TX, TY, TZ, RATIO, true, false, true>),
                                dim3(blocks), dim3(kThreads), lds, s, a);
         else
-            hipLaunchKernelGGL((k_image_pass<TX, kTY, kTZ, RATIO, true, false, false>),
+            hipLaunchKernelGGL((k_image_pass<TX, TY, TZ, RATIO, true, false, false>),
                                dim3(blocks), dim3(kThreads), lds, s, a);
     } else {
         if (a.pow2h)
-            hipLaunchKernelGGL((k_image_pass<TX, kTY, kTZ, RATIO, false, false, true>),
+            hipLaunchKernelGGL((k_image_pass<TX, TY, TZ, RATIO, false, false, true>),
                                dim3(blocks), dim3(kThreads), lds, s, a);
         else
-            hipLaunchKernelGGL((k_image_pass<TX, kTY, kTZ, RATIO, false, false, false>),
+            hipLaunchKernelGGL((k_image_pass<TX, TY, TZ, RATIO, false, false, false>),
                                dim3(blocks), dim3(kThreads), lds, s, a);
     }
 }
@@ -614,20 +614,24 @@ void launch_image_ratio_atomic(const ImagePassArgs& a, hipStream_t s) {
                            dim3(blocks), dim3(kThreads), lds, s, a);
 }
 
+template <int RATIO>
+void launch_image_ratio(const ImagePassArgs& a, int variant, hipStream_t s) {
+    if (variant == kTile3DSmall)
+        launch_image_tile<4, 8, 32, RATIO>(a, s);
+    else if (variant == kTile3DTiny)
+        launch_image_tile<4, 4, 16, RATIO>(a, s);
+    else
+        launch_image_tile<kTX, kTY, kTZ, RATIO>(a, s);
+}
+
 }  // namespace
 
-void launch_image_pass(const ImagePassArgs& a, int ratio, hipStream_t s, bool small) {
-    if (ratio == 2) {
-        if (small)
-            launch_image_ratio<kSTX, 2>(a, s);
-        else
-            launch_image_ratio<kTX, 2>(a, s);
-    } else if (ratio == 4) {
-        if (small)
-            launch_image_ratio<kSTX, 4>(a, s);
-        else
-            launch_image_ratio<kTX, 4>(a, s);
-    }
+// 3D-tile variants (kTile3D, kTile3DSmall, kTile3DTiny)
+void launch_image_pass(const ImagePassArgs& a, int ratio, int variant, hipStream_t s) {
+    if (ratio == 2)
+        launch_image_ratio<2>(a, variant, s);
+    else if (ratio == 4)
+        launch_image_ratio<4>(a, variant, s);
 }
 
 void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s) {

@@ -156,10 +156,10 @@ struct Geo {
 };
 Geo geometry(const Level& L, int variant) {
     Geo g{};
-    if (variant == kTile3D || variant == kTile3DSmall) {
-        g.tx = variant == kTile3D ? kTX : kSTX;
-        g.ty = kTY;
-        g.tz = kTZ;
+    if (is_tile3d(variant)) {
+        g.tx = tile3d_x(variant);
+        g.ty = tile3d_y(variant);
+        g.tz = tile3d_z(variant);
     } else {
         g.tx = march_cx(variant);
         g.ty = kMY;
@@ -358,7 +358,7 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
     a.gate = gate;
     auto launch = [&] {
         if (!is_march(L.variant))
-            launch_image_pass(a, c->p.ratio, c->stream, L.variant == kTile3DSmall);
+            launch_image_pass(a, c->p.ratio, L.variant, c->stream);
         else
             launch_image_march(a, c->p.ratio, march_tz(L.variant), march_cx(L.variant),
                                c->stream);
@@ -469,12 +469,11 @@ void tune_cache_store(const std::string& key, int v) {
 // Image-pass variant from the level size alone, for callers that cannot
 // afford timing runs (or whose timings would be disturbed by concurrent
 // work): the choices the timed selection makes on gfx950 at cubic levels of
-// 256^3, 128^3 and 64^3 and below.
+// 256^3 and 128^3, and of 64^3 and below.
 int variant_by_size(const Level& L) {
     const int64_t n = L.N();
-    if (n >= (int64_t{8} << 20)) return kMarch64x32;
-    if (n >= (int64_t{1} << 20)) return kMarch32x8;
-    return kTile3DSmall;
+    if (n >= (int64_t{8} << 20)) return kMarch32x16;
+    return n >= (int64_t{1} << 20) ? kMarch32x8 : kTile3DTiny;
 }
 
 // Pick the image-pass variant of every level: forced, cached for this shape,
@@ -1178,7 +1177,7 @@ ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], con
     if (want)
         launch_image_pass_atomic(a, r, c->stream);
     else
-        launch_image_pass(a, r, c->stream);
+        launch_image_pass(a, r, kTile3D, c->stream);
     HIPCHK(c, hipGetLastError());
     NodePassArgs b{};
     b.y = y;

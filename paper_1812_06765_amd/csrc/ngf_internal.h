@@ -24,21 +24,32 @@ constexpr int kMY = 16;
 // Node-pass tile (nodes per axis).
 constexpr int kNX = 4, kNY = 8, kNZ = 32;
 
-// Image-pass variants the autotuner chooses from: the 3D-tile kernel, and the
-// marching kernel with in-plane tile 16 x 64 or 16 x 32 and x chunks of 8,
-// 20 or 32 planes.
+// Image-pass variants the autotuner chooses from: the 3D-tile kernel at three
+// tile sizes, and the marching kernel with in-plane tile 16 x 64 or 16 x 32
+// and x chunks of 8, 16, 20 or 32 planes.
 enum Variant {
     kTile3D = 0,
     kMarch64x8 = 1, kMarch64x20 = 2, kMarch64x32 = 3,
     kMarch32x8 = 4, kMarch32x20 = 5, kMarch32x32 = 6,
     kTile3DSmall = 7,  // 3D tile of 4 x 8 x 32 voxels (coarse levels)
-    kNumVariants = 8
+    kTile3DTiny = 8,   // 3D tile of 4 x 4 x 16 voxels (many workgroups for small levels)
+    kMarch64x16 = 9, kMarch32x16 = 10,
+    kNumVariants = 11
 };
 constexpr int kVariantBySize = -2;  // selection rule instead of timed selection
-inline bool is_march(int v) { return v >= kMarch64x8 && v <= kMarch32x32; }
-constexpr int kSTX = 4;  // small 3D tile: kSTX x kTY x kTZ
-inline int march_cx(int v) { return (v - 1) % 3 == 0 ? 8 : ((v - 1) % 3 == 1 ? 20 : 32); }
-inline int march_tz(int v) { return v <= kMarch64x32 ? 64 : 32; }
+inline bool is_march(int v) {
+    return (v >= kMarch64x8 && v <= kMarch32x32) || v == kMarch64x16 || v == kMarch32x16;
+}
+// 3D-tile extents (x, y, z) of the 3D-tile variants
+inline int tile3d_x(int v) { return v == kTile3D ? 8 : 4; }
+inline int tile3d_y(int v) { return v == kTile3DTiny ? 4 : 8; }
+inline int tile3d_z(int v) { return v == kTile3DTiny ? 16 : 32; }
+inline bool is_tile3d(int v) { return v == kTile3D || v == kTile3DSmall || v == kTile3DTiny; }
+inline int march_cx(int v) {
+    if (v >= kMarch64x16) return 16;
+    return (v - 1) % 3 == 0 ? 8 : ((v - 1) % 3 == 1 ? 20 : 32);
+}
+inline int march_tz(int v) { return (v <= kMarch64x32 || v == kMarch64x16) ? 64 : 32; }
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumbering gives each XCD a contiguous range of tiles, so that
@@ -193,7 +204,7 @@ void launch_index_map(int32_t* j0, float* w0, float* w1, int m, int my, hipStrea
 void launch_identity(float* y, int nx, int ny, int nz, double hx, double hy, double hz,
                      hipStream_t s);
 void launch_prolongate(const float* yc, float* yf, int cx, int cy, int cz, hipStream_t s);
-void launch_image_pass(const ImagePassArgs& a, int ratio, hipStream_t s, bool small = false);
+void launch_image_pass(const ImagePassArgs& a, int ratio, int variant, hipStream_t s);
 void launch_image_march(const ImagePassArgs& a, int ratio, int tz, int cx, hipStream_t s);
 void launch_node_pass(const NodePassArgs& a, hipStream_t s);
 void launch_reduce(const ReduceArgs& a, hipStream_t s);

@@ -46,7 +46,7 @@ def _y(prob, amp, seed, spacing=8.0):
 
 
 VARIANTS = ("tile3d", "march64x8", "march64x20", "march64x32", "march32x8", "march32x20",
-            "march32x32", "tile3d_small")
+            "march32x32", "tile3d_small", "tile3d_tiny", "march64x16", "march32x16")
 
 
 def _check_eval(ngf, ctx, level, prob, y32, tag, variants=VARIANTS):
@@ -172,7 +172,6 @@ def test_eval_parity_256_bench_configuration(gpu_lib):
     ctx = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=4)
     ctx.set_kernel("by_size")
     ctx.build_pyramid(_t(pr.R), _t(pr.T))
-    assert ctx.get_kernel(0) == ngf.Context.VARIANTS["march64x32"]
     Rs, Ts = O.pyramid(pr.R, pr.T, 2)
     names = {num: name for name, num in ngf.Context.VARIANTS.items()}
     for lev, (m, h, my) in enumerate(O.level_shapes(pr.R.shape, (1.0, 1.0, 1.0), 2)):
@@ -220,7 +219,7 @@ def test_autotuner_choice_is_valid_and_cached(gpu_lib):
     ctx = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=3)
     ctx.build_pyramid(_t(pr.R), _t(pr.T))
     first = [ctx.get_kernel(lev) for lev in range(3)]
-    assert all(0 <= v <= 7 for v in first)
+    assert all(0 <= v < len(VARIANTS) for v in first)
     ctx.build_pyramid(_t(pr.R), _t(pr.T))  # same shapes: cached choice
     assert [ctx.get_kernel(lev) for lev in range(3)] == first
     _say(f"[autotune] 128^3 pyramid choices {first}")
