@@ -93,6 +93,49 @@ def cpu_baseline(R, T, evals=2):
                       "single-threaded numpy"}
 
 
+def bench_pt(args, torch, ngf):
+    """P and the three ways of applying P^T (Sec. 2.2, "Grid conversion") as
+    standalone operators on the 256^3 image grid / 129^3 deformation grid:
+    gather (Eq. 3), atomic scatter, red-black slices (the scatter schemes
+    include zeroing their output).  Input: seeded normal values."""
+    n = args.size
+    ctx = ngf.Context(levels=1)
+    R = torch.zeros((n, n, n), dtype=torch.float32, device="cuda")
+    ctx.build_pyramid(R, R)
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    li = ctx.level_info(0)
+    z = torch.randn((3,) + li.m, generator=gen, device="cuda")
+    y = torch.randn((3,) + li.my, generator=gen, device="cuda")
+    out = {"mode": "P^T schemes", "grid": list(li.m), "nodes": list(li.my)}
+    reps = 20
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 1e3 * e0.elapsed_time(e1) / reps
+
+    N = li.m[0] * li.m[1] * li.m[2]
+    Ny = li.my[0] * li.my[1] * li.my[2]
+    us = timed(lambda: ctx.apply_P(0, y))
+    out["P_us"] = us
+    out["P_GBs"] = (12 * Ny + 12 * N) / (us * 1e-6) / 1e9
+    for name in ("gather", "atomic", "redblack"):
+        us = timed(lambda: ctx.apply_PT(0, z, name))
+        out[f"PT_{name}_us"] = us
+        out[f"PT_{name}_GBs"] = (12 * N + 12 * Ny) / (us * 1e-6) / 1e9
+    ref = ctx.apply_PT(0, z, "gather").double()
+    for name in ("atomic", "redblack"):
+        d = (ctx.apply_PT(0, z, name).double() - ref).norm() / ref.norm()
+        out[f"PT_{name}_rel_diff_vs_gather"] = float(d)
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args, torch, ngf, synth):
     """Uneven batch: pairs with axes drawn from {96, 128, 160, 192, 256}, the
     CT phantom recipe per pair, 3 levels, through ngf_batch_register."""
@@ -160,6 +203,8 @@ def main():
                     help="instead: the uneven batch of this many pairs (axes drawn from "
                          "96..256, 3 levels) through the batched form")
     ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--pt-ablation", action="store_true",
+                    help="instead: time the three P^T schemes and P at the 256^3 grids")
     ap.add_argument("--kernel", default="by_size",
                     help="image-pass selection: by_size (default), auto, or a variant name")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -187,6 +232,8 @@ def main():
 
     if args.batch:
         return bench_batch(args, torch, ngf, synth)
+    if args.pt_ablation:
+        return bench_pt(args, torch, ngf)
 
     n = args.size
     t_gen = time.perf_counter()

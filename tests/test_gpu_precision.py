@@ -1,0 +1,94 @@
+"""Precision study: the float32 GPU registration against the float64 oracle's
+registration of the same pair (Sec. 3 of the paper compares its float32 GPU
+code with float64 CPU code and finds the results alike).
+
+Workload: the 3-level CT pyramid of 32^3, 64^3, 128^3 voxels (nodes 17^3,
+33^3, 65^3), alpha 0.1, eps 10, 50 L-BFGS iterations per level.  Both runs
+start from the identity and follow the same algorithm; the problem is not
+convex, so their trajectories may part in flat regions.  Compared: final J
+per level, the difference of the two final deformations, and each one's
+distance to the known inverse of the generating displacement (sampled inside
+the body).
+"""
+
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1812_06765_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+M = (128, 128, 128)
+H = (1.0, 1.0, 1.0)
+KW = dict(alpha=0.1, tau=10.0, rho=10.0, max_iter=50)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_float32_gpu_registration_against_float64_oracle(gpu_lib):
+    import torch
+    ngf = gpu_lib
+    pr = synth.ct_phantom_pair(M, seed_R=3, seed_u=4)
+    ctx = ngf.Context(levels=3, lbfgs_mem=5, **KW)
+    y_gpu, rep = ctx.register(torch.from_numpy(pr.R).cuda(), torch.from_numpy(pr.T).cuda())
+    y_gpu = y_gpu.cpu().numpy().astype(np.float64)
+    _say(f"[precision] gpu levels {rep}")
+    t0 = time.perf_counter()
+    y_or, rep_or = O.register(pr.R, pr.T, H, levels=3, mem=5, **KW)
+    _say(f"[precision] oracle levels {rep_or} ({time.perf_counter() - t0:.1f} s)")
+
+    # final J per level (level index, iterations, evaluations, J, info)
+    for r in rep:
+        ro = [x for x in rep_or if x[0] == r["level"]][0]
+        rel = abs(r["J"] - ro[3]) / abs(ro[3])
+        _say(f"[precision] level {r['level']}: J gpu {r['J']:.6e} oracle {ro[3]:.6e} "
+             f"rel diff {rel:.2e}; iterations {r['iters']} / {ro[1]}")
+        assert r["iters"] == ro[1] == 50
+        assert rel <= 1e-2
+
+    # deformations: difference between the runs, in voxels, over all nodes and
+    # over the nodes inside the body (outside it the NGF term is flat and only
+    # the regulariser holds the deformation, so the runs may drift apart)
+    my = y_gpu.shape[1:]
+    X = O.identity(M, H, my)
+    d = np.sqrt(((y_gpu - y_or) ** 2).sum(0))
+    u_or = np.sqrt(((y_or - X) ** 2).sum(0))
+    idx = np.clip(np.rint(X - 0.5).astype(int), 0, M[0] - 1)
+    inside = pr.R[idx[0], idx[1], idx[2]] > -500.0
+    _say(f"[precision] |y_gpu - y_oracle| all nodes: max {d.max():.4f} mean {d.mean():.4f}; "
+         f"body nodes ({int(inside.sum())}): max {d[inside].max():.4f} mean "
+         f"{d[inside].mean():.4f} voxels; oracle displacement mean all {u_or.mean():.4f}, "
+         f"body {u_or[inside].mean():.4f}")
+    assert d[inside].mean() <= 0.5 * u_or[inside].mean()
+
+    # distance to the true correspondence at sampled voxels: inside the body,
+    # and on strong edges (|grad R| > 200 HU per voxel), where the NGF term
+    # determines the deformation; in homogeneous tissue the noise of R and T
+    # (independent, comparable to eps) dominates the term
+    rng = np.random.default_rng(5)
+    g = np.stack(np.gradient(pr.R.astype(np.float64)))
+    gn = np.sqrt((g ** 2).sum(0))
+    res = {}
+    for name, mask in (("body", pr.R > -500.0), ("edges", gn > 200.0)):
+        cand = np.argwhere(mask)
+        pick = cand[rng.choice(len(cand), size=min(4000, len(cand)), replace=False)]
+        zstar = synth.invert_displacement(pr.field, pick.T.astype(np.float64) + 0.5)
+
+        def err(yy, pick=pick, zstar=zstar):
+            yh = O.apply_P(yy, M, my)
+            at = yh[:, pick[:, 0], pick[:, 1], pick[:, 2]]
+            return np.sqrt(((at - zstar) ** 2).sum(0)).mean()
+
+        res[name] = (err(X), err(y_gpu), err(y_or))
+        _say(f"[precision] mean distance to the true correspondence ({name}): identity "
+             f"{res[name][0]:.4f}, gpu float32 {res[name][1]:.4f}, oracle float64 "
+             f"{res[name][2]:.4f} voxels")
+    for name, (e0, eg, eo) in res.items():
+        assert abs(eg - eo) <= 0.1 * e0, name
