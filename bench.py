@@ -138,7 +138,9 @@ def bench_pt(args, torch, ngf):
 
 def bench_batch(args, torch, ngf, synth):
     """Uneven batch: pairs with axes drawn from {96, 128, 160, 192, 256}, the
-    CT phantom recipe per pair, 3 levels, through ngf_batch_register."""
+    CT phantom recipe per pair, 3 levels.  Timed: the batched form in graph
+    mode (the reported value), in threads mode, and the same pairs registered
+    one after another by a single context."""
     shapes = synth.batch_shapes(args.batch)
     Rs, Ts = [], []
     t_gen = time.perf_counter()
@@ -150,19 +152,40 @@ def bench_batch(args, torch, ngf, synth):
             print(f"[bench] {i + 1} pairs generated", file=sys.stderr, flush=True)
     print(f"[bench] inputs generated in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr,
           flush=True)
-    b = ngf.Batch(alpha=0.1, tau=10.0, rho=10.0, levels=3, ratio=2, max_iter=args.max_iter,
-                  lbfgs_mem=5, tol_J=1e-6, early_stop=True, workers=args.workers)
-    for _ in range(args.warmup):
-        b.register(Rs, Ts)
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-    evals = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ys, reps = b.register(Rs, Ts)
-        evals += sum(r["evals"] for rep in reps for r in rep)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    kw = dict(alpha=0.1, tau=10.0, rho=10.0, levels=3, ratio=2, max_iter=args.max_iter,
+              lbfgs_mem=5, tol_J=1e-6, early_stop=True)
+
+    def timed(run):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        evals = 0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            reps = run()
+            evals += sum(r["evals"] for rep in reps for r in rep)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, evals
+
+    res = {}
+    for mode in ("graph", "threads"):
+        b = ngf.Batch(workers=args.workers, mode=mode, **kw)
+        if mode == "threads":
+            b.set_kernel("by_size")
+        dt, ev = timed(lambda: b.register(Rs, Ts)[1])
+        b.close()
+        res[mode] = (dt, ev)
+        print(f"[bench] batch {mode}: {dt / args.steps:.3f} s per batch", file=sys.stderr,
+              flush=True)
+    ctx = ngf.Context(**kw)
+
+    def sequential():
+        return [ctx.register(R, T)[1] for R, T in zip(Rs, Ts)]
+
+    res["sequential"] = timed(sequential)
+    print(f"[bench] sequential: {res['sequential'][0] / args.steps:.3f} s per batch",
+          file=sys.stderr, flush=True)
+    dt, evals = res["graph"]
     vox = sum(m[0] * m[1] * m[2] for m in shapes)
     out = {
         "metric": METRIC,
@@ -180,11 +203,12 @@ def bench_batch(args, torch, ngf, synth):
         "config": {"workload": f"batch of {args.batch} pairs, axes drawn from 96..256, "
                                f"{vox / 1e6:.1f} M voxels at the finest levels, 3 levels, "
                                f"alpha=0.1, eps=10, L-BFGS m=5, <= {args.max_iter} it/level, "
-                               f"early stop 1e-6, {args.workers} workers",
+                               "early stop 1e-6; batched form in graph mode",
                    "global_batch": args.batch, "seq_len": None, "parallelism": "single GPU"},
-        "batch_s": dt / args.steps,
-        "evals_per_batch": evals / args.steps,
-        "pairs_per_s": args.batch * args.steps / dt,
+        "batch_s": {k: v[0] / args.steps for k, v in res.items()},
+        "evals_per_s": {k: v[1] / v[0] for k, v in res.items()},
+        "pairs_per_s": {k: args.batch * args.steps / v[0] for k, v in res.items()},
+        "threads_workers": args.workers,
     }
     print(json.dumps(out), flush=True)
 

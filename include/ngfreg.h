@@ -293,16 +293,21 @@ ngf_status ngf_kernel_time(ngf_ctx* ctx, int32_t level, int32_t* launches, doubl
 
 /* Batched form: many independent registrations (one image pair each, any
  * mix of shapes) on one device, each computed as by ngf_register (Sec. 2:
- * pyramid, multi-level L-BFGS on Eq. 1).  A host scheduler hands pairs,
- * largest voxel count first, to `workers` threads (1..16); each worker owns
- * a context on its own non-blocking stream of the device current at
- * ngf_batch_create, so pairs run concurrently on the device.  Every pair's
- * result equals the single-pair ngf_register result for the same
- * image-pass variant bit for bit.
- *   ngf_batch_create      params as for ngf_create; the image-pass variant
- *                         defaults to -2 (by level size; timed selection
- *                         would be disturbed by the concurrent pairs)
- *   ngf_batch_set_kernel  variant as for ngf_set_kernel, for every worker
+ * pyramid, multi-level L-BFGS on Eq. 1).  Two modes (ngf_batch_set_mode):
+ *   0 (default) graph: the pairs go through the levels together; at each
+ *     level one L-BFGS round of every pair is one fixed sequence of batched
+ *     launches (each covering all pairs through a block table), captured as
+ *     a hipGraph and replayed on the batch's own stream until every pair's
+ *     level has ended.  Image-pass variants by the timed selection, one
+ *     table shared by the pairs (ngf_batch_set_kernel overrides).
+ *   1 threads: a host scheduler hands pairs, largest voxel count first, to
+ *     `workers` threads (1..16), each with a context on its own stream;
+ *     variants by the size rule unless set.
+ * In both, every pair's result equals the single-pair ngf_register result
+ * for the same image-pass variants bit for bit.
+ *   ngf_batch_create      params as for ngf_create; workers as above (used
+ *                         by mode 1); the device is the current one
+ *   ngf_batch_set_kernel  variant as for ngf_set_kernel, for every pair
  *   ngf_batch_register    npairs >= 0; R[i], T[i]: device float32 images of
  *                         grids[i]; y_out[i]: device float32
  *                         [3][m0/ratio+1][m1/ratio+1][m2/ratio+1]; `stream`
@@ -310,16 +315,18 @@ ngf_status ngf_kernel_time(ngf_ctx* ctx, int32_t level, int32_t* launches, doubl
  *                         waits for the work queued there, so the inputs may
  *                         come from it; reports: NULL or npairs entries.
  *                         Synchronous: returns when every pair is done.  On
- *                         failure no further pairs are started, the status
- *                         of the first failed pair (by index) is returned and
- *                         ngf_batch_last_error names it; outputs of the other
- *                         pairs are then unspecified. */
+ *                         failure the status is returned and
+ *                         ngf_batch_last_error names the pair; the outputs
+ *                         are then unspecified.  Mode 0 keeps one context
+ *                         per pair slot between calls (memory grows with
+ *                         the largest batch). */
 #define NGF_BATCH_MAX_WORKERS 16
 typedef struct ngf_batch ngf_batch;
 ngf_status ngf_batch_create(const ngf_params* p, int32_t workers, ngf_batch** out);
 void ngf_batch_destroy(ngf_batch* b);
 const char* ngf_batch_last_error(const ngf_batch* b);
 ngf_status ngf_batch_set_kernel(ngf_batch* b, int32_t variant);
+ngf_status ngf_batch_set_mode(ngf_batch* b, int32_t mode);
 ngf_status ngf_batch_register(ngf_batch* b, int32_t npairs, const float* const* R,
                               const float* const* T, const ngf_grid* grids,
                               float* const* y_out, void* stream, ngf_report* reports);

@@ -579,6 +579,26 @@ __global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
     node_body<NX, NY, NZ>(a, blockIdx.x);
 }
 
+template <int NX, int NY, int NZ>
+__global__ __launch_bounds__(kThreads) void k_node_pass_batch(const NodePassArgs* args,
+                                                              const BlockRef* blk) {
+    const BlockRef e = blk[blockIdx.x];
+    if (e.pair < 0) return;
+    const NodePassArgs& a = args[e.pair];
+    if (a.gate && *a.gate == kOpNone) return;
+    node_body<NX, NY, NZ>(a, e.block);
+}
+
+template <int TX, int TY, int TZ, int RATIO, bool POW2>
+__global__ __launch_bounds__(kThreads) void k_image_pass_batch(const ImagePassArgs* args,
+                                                               const BlockRef* blk) {
+    const BlockRef e = blk[blockIdx.x];
+    if (e.pair < 0) return;
+    const ImagePassArgs& a = args[e.pair];
+    if (a.gate && *a.gate == kOpNone) return;
+    image_body<TX, TY, TZ, RATIO, true, false, POW2>(a, e.block);
+}
+
 template <int TX, int TY, int TZ, int RATIO>
 void launch_image_tile(const ImagePassArgs& a, hipStream_t s) {
     using L = ImageTile<TX, TY, TZ, RATIO>;
@@ -614,6 +634,30 @@ void launch_image_ratio_atomic(const ImagePassArgs& a, hipStream_t s) {
                            dim3(blocks), dim3(kThreads), lds, s, a);
 }
 
+template <int TX, int TY, int TZ, int RATIO>
+void launch_image_tile_batch(const ImagePassArgs* args, const BlockRef* blk, int nblk, bool pow2,
+                             hipStream_t s) {
+    using L = ImageTile<TX, TY, TZ, RATIO>;
+    const size_t lds = sizeof(float) * L::LDS_FLOATS;
+    if (pow2)
+        hipLaunchKernelGGL((k_image_pass_batch<TX, TY, TZ, RATIO, true>), dim3(nblk),
+                           dim3(kThreads), lds, s, args, blk);
+    else
+        hipLaunchKernelGGL((k_image_pass_batch<TX, TY, TZ, RATIO, false>), dim3(nblk),
+                           dim3(kThreads), lds, s, args, blk);
+}
+
+template <int RATIO>
+void launch_image_ratio_batch(const ImagePassArgs* args, const BlockRef* blk, int nblk,
+                              int variant, bool pow2, hipStream_t s) {
+    if (variant == kTile3DSmall)
+        launch_image_tile_batch<4, 8, 32, RATIO>(args, blk, nblk, pow2, s);
+    else if (variant == kTile3DTiny)
+        launch_image_tile_batch<4, 4, 16, RATIO>(args, blk, nblk, pow2, s);
+    else
+        launch_image_tile_batch<kTX, kTY, kTZ, RATIO>(args, blk, nblk, pow2, s);
+}
+
 template <int RATIO>
 void launch_image_ratio(const ImagePassArgs& a, int variant, hipStream_t s) {
     if (variant == kTile3DSmall)
@@ -632,6 +676,23 @@ void launch_image_pass(const ImagePassArgs& a, int ratio, int variant, hipStream
         launch_image_ratio<2>(a, variant, s);
     else if (ratio == 4)
         launch_image_ratio<4>(a, variant, s);
+}
+
+// gradient form only (the batched rounds always want the gradient)
+void launch_image_pass_batch(const ImagePassArgs* args, const BlockRef* blk, int nblk, int ratio,
+                             int variant, bool pow2, hipStream_t s) {
+    if (nblk <= 0) return;
+    if (ratio == 2)
+        launch_image_ratio_batch<2>(args, blk, nblk, variant, pow2, s);
+    else if (ratio == 4)
+        launch_image_ratio_batch<4>(args, blk, nblk, variant, pow2, s);
+}
+
+void launch_node_pass_batch(const NodePassArgs* args, const BlockRef* blk, int nblk,
+                            hipStream_t s) {
+    if (nblk <= 0) return;
+    hipLaunchKernelGGL((k_node_pass_batch<kNX, kNY, kNZ>), dim3(nblk), dim3(kThreads), 0, s, args,
+                       blk);
 }
 
 void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s) {

@@ -136,8 +136,7 @@ __device__ double block_sum_fixed(const double* a, int n, double* sh) {
     return r;
 }
 
-__global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
-    if (a.gate && *a.gate == kOpNone) return;
+__device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
     __shared__ double sh[kThreads];
     const double d = block_sum_fixed(a.dpart, a.nd, sh);
     const double s = block_sum_fixed(a.spart, a.ns, sh);
@@ -178,6 +177,18 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
     }
 }
 
+__global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
+    if (a.gate && *a.gate == kOpNone) return;
+    reduce_body(a);
+}
+
+// one workgroup per pair
+__global__ __launch_bounds__(kThreads) void k_reduce_batch(const ReduceArgs* args) {
+    const ReduceArgs& a = args[blockIdx.x];
+    if (a.gate && *a.gate == kOpNone) return;
+    reduce_body(a);
+}
+
 }  // namespace
 
 void launch_downsample(const float* src, float* dst, int mx, int my, int mz, hipStream_t s) {
@@ -210,6 +221,10 @@ void launch_check_finite(const float* v, int64_t n, int* flag, hipStream_t s) {
 
 void launch_fill(float* p, int64_t n, float v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kThreads, 8192)), dim3(kThreads), 0, s, p, n, v);
+}
+
+void launch_reduce_batch(const ReduceArgs* args, int npairs, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_batch, dim3(npairs), dim3(kThreads), 0, s, args);
 }
 
 void launch_reduce(const ReduceArgs& a, hipStream_t s) {

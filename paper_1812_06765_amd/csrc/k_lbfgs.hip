@@ -518,7 +518,7 @@ __global__ __launch_bounds__(kGramThreads) void k_lb_gram_update(LbState* st,
 // step, or the next halving of the step after a rejected trial.  The tests
 // before a new direction are those of one L-BFGS iteration: iteration
 // budget, non-finite gradient, zero gradient.
-__global__ void k_lb_plan(LbState* st, double* jds) {
+__device__ __forceinline__ void lb_plan_body(LbState* st, double* jds) {
     __shared__ SolveLds w;
     lb_stage(st, w);
     if (threadIdx.x != 0) return;
@@ -544,19 +544,28 @@ __global__ void k_lb_plan(LbState* st, double* jds) {
     }
 }
 
+__global__ void k_lb_plan(LbState* st, double* jds) { lb_plan_body(st, jds); }
+
+__device__ __forceinline__ void lb_vec_body(const LbState* st, const float* __restrict__ hist,
+                                            int64_t ld, int64_t n, const float* __restrict__ y,
+                                            const float* __restrict__ g,
+                                            float* __restrict__ d, float* __restrict__ yt,
+                                            int block, int nblocks) {
+    const int op = st->ctl.op;
+    if (op == kOpCombine)
+        lb_combine_body(st, hist, ld, n, y, g, d, yt, block, nblocks);
+    else if (op == kOpAxpy)
+        lb_axpy_body(y, d, static_cast<float>(st->ctl.t), yt, n, block, nblocks);
+}
+
 __global__ __launch_bounds__(kThreads) void k_lb_vec(const LbState* st,
                                                      const float* __restrict__ hist, int64_t ld,
                                                      int64_t n, const float* __restrict__ y,
                                                      const float* __restrict__ g,
                                                      float* __restrict__ d,
                                                      float* __restrict__ yt) {
-    const int op = st->ctl.op;
-    if (op == kOpCombine)
-        lb_combine_body(st, hist, ld, n, y, g, d, yt, blockIdx.x, gridDim.x);
-    else if (op == kOpAxpy)
-        lb_axpy_body(y, d, static_cast<float>(st->ctl.t), yt, n, blockIdx.x, gridDim.x);
+    lb_vec_body(st, hist, ld, n, y, g, d, yt, blockIdx.x, gridDim.x);
 }
-
 
 template <int CMAX>
 __global__ __launch_bounds__(kThreads) void k_lb_accept_dots(const LbState* st,
@@ -573,12 +582,9 @@ __global__ __launch_bounds__(kThreads) void k_lb_accept_dots(const LbState* st,
 
 // Gram update for the accepted step, then the stopping tests of the level:
 // relative decrease (early stop) and the iteration budget.
-__global__ __launch_bounds__(kGramThreads) void k_lb_accept_gram(LbState* st,
-                                                                 const double* dotpart,
-                                                                 int nblocks,
-                                                                 const double* jds) {
+__device__ __forceinline__ void lb_accept_gram_body(LbState* st, const double* dotpart,
+                                                    int nblocks, const double* jds) {
 #pragma clang fp contract(off)
-    if (st->ctl.phase != kPhAccepted) return;
     lb_gram_body(st, dotpart, nblocks, jds);
     if (threadIdx.x != 0) return;
     LbCtl& c = st->ctl;
@@ -593,6 +599,57 @@ __global__ __launch_bounds__(kGramThreads) void k_lb_accept_gram(LbState* st,
         lb_finish(c, NGF_INFO_MAX_ITER);
     else
         c.phase = kPhNeedDir;
+}
+
+__global__ __launch_bounds__(kGramThreads) void k_lb_accept_gram(LbState* st,
+                                                                 const double* dotpart,
+                                                                 int nblocks,
+                                                                 const double* jds) {
+    if (st->ctl.phase != kPhAccepted) return;
+    lb_accept_gram_body(st, dotpart, nblocks, jds);
+}
+
+// ---- batched forms: one launch over many pairs (see BlockRef) ------------
+
+__global__ void k_lb_init_batch(const LbVecArgs* args) {
+    const LbVecArgs& a = args[blockIdx.x];
+    if (threadIdx.x == 0)
+        lb_init_one(a.st, a.mem, a.hmin, a.jds, a.max_iter, a.early_stop, a.tol);
+}
+
+__global__ void k_lb_plan_batch(const LbVecArgs* args) {
+    const LbVecArgs& a = args[blockIdx.x];
+    lb_plan_body(a.st, a.jds);
+}
+
+__global__ __launch_bounds__(kThreads) void k_lb_vec_batch(const LbVecArgs* args,
+                                                           const BlockRef* blk) {
+    const BlockRef e = blk[blockIdx.x];
+    if (e.pair < 0) return;
+    const LbVecArgs& a = args[e.pair];
+    lb_vec_body(a.st, a.hist, a.ld, a.n, a.y, a.g, a.d, a.yt, e.block, a.nblocks);
+}
+
+template <int CMAX>
+__global__ __launch_bounds__(kThreads) void k_lb_accept_dots_batch(const LbVecArgs* args,
+                                                                   const BlockRef* blk) {
+    const BlockRef e = blk[blockIdx.x];
+    if (e.pair < 0) return;
+    const LbVecArgs& a = args[e.pair];
+    if (a.st->ctl.phase != kPhAccepted) return;
+    lb_update_dots_body<true, CMAX>(a.st, a.hist, a.ld, a.n, a.y, a.yt, a.g, a.gt, a.dotpart,
+                                    e.block, a.nblocks);
+}
+
+__global__ __launch_bounds__(kGramThreads) void k_lb_accept_gram_batch(const LbVecArgs* args) {
+    const LbVecArgs& a = args[blockIdx.x];
+    if (a.st->ctl.phase != kPhAccepted) return;
+    lb_accept_gram_body(a.st, a.dotpart, a.nblocks, a.jds);
+}
+
+__global__ void k_ctl_gather(const LbVecArgs* args, LbCtl* out, int npairs) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < npairs) out[p] = args[p].st->ctl;
 }
 
 }  // namespace
@@ -618,6 +675,36 @@ void launch_lb_accept(LbState* st, float* hist, int64_t ld, int64_t n, float* y,
                            hist, ld, n, y, yt, g, gt, dotpart);
     hipLaunchKernelGGL(k_lb_accept_gram, dim3(1), dim3(kGramThreads), 0, s, st, dotpart,
                        nblocks, jds);
+}
+
+void launch_lb_init_batch(const LbVecArgs* args, int npairs, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_init_batch, dim3(npairs), dim3(64), 0, s, args);
+}
+
+void launch_lb_plan_batch(const LbVecArgs* args, int npairs, hipStream_t s) {
+    hipLaunchKernelGGL(k_lb_plan_batch, dim3(npairs), dim3(64), 0, s, args);
+}
+
+void launch_lb_vec_batch(const LbVecArgs* args, const BlockRef* blk, int nblk, hipStream_t s) {
+    if (nblk > 0)
+        hipLaunchKernelGGL(k_lb_vec_batch, dim3(nblk), dim3(kThreads), 0, s, args, blk);
+}
+
+void launch_lb_accept_batch(const LbVecArgs* args, const BlockRef* blk, int nblk, int npairs,
+                            int mem, hipStream_t s) {
+    if (nblk > 0) {
+        if (mem <= 5)
+            hipLaunchKernelGGL(k_lb_accept_dots_batch<5>, dim3(nblk), dim3(kThreads), 0, s, args,
+                               blk);
+        else
+            hipLaunchKernelGGL(k_lb_accept_dots_batch<kMaxMem>, dim3(nblk), dim3(kThreads), 0, s,
+                               args, blk);
+    }
+    hipLaunchKernelGGL(k_lb_accept_gram_batch, dim3(npairs), dim3(kGramThreads), 0, s, args);
+}
+
+void launch_ctl_gather(const LbVecArgs* args, LbCtl* out, int npairs, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_gather, dim3((npairs + 63) / 64), dim3(64), 0, s, args, out, npairs);
 }
 
 int lb_dot_blocks(int64_t n) {

@@ -502,6 +502,29 @@ __global__ __launch_bounds__(kThreads, TZ == 32 ? 3 : 2) void k_image_march(Imag
     march_body<TY, TZ, R, GRAD, POW2>(a, CX, blockIdx.x);
 }
 
+template <int TY, int TZ, int R, bool POW2>
+__global__ __launch_bounds__(kThreads, TZ == 32 ? 3 : 2) void k_image_march_batch(
+    const ImagePassArgs* args, const BlockRef* blk, int CX) {
+    const BlockRef e = blk[blockIdx.x];
+    if (e.pair < 0) return;
+    const ImagePassArgs& a = args[e.pair];
+    if (a.gate && *a.gate == kOpNone) return;
+    march_body<TY, TZ, R, true, POW2>(a, CX, e.block);
+}
+
+template <int TY, int TZ, int R>
+void launch_march_batch_t(const ImagePassArgs* args, const BlockRef* blk, int nblk, int cx,
+                          bool pow2, hipStream_t s) {
+    using L = March<TY, TZ, R>;
+    const size_t lds = sizeof(float) * L::LDS_FLOATS;
+    if (pow2)
+        hipLaunchKernelGGL((k_image_march_batch<TY, TZ, R, true>), dim3(nblk), dim3(kThreads),
+                           lds, s, args, blk, cx);
+    else
+        hipLaunchKernelGGL((k_image_march_batch<TY, TZ, R, false>), dim3(nblk), dim3(kThreads),
+                           lds, s, args, blk, cx);
+}
+
 template <int TY, int TZ, int R>
 void launch_march_t(const ImagePassArgs& a, int cx, hipStream_t s) {
     using L = March<TY, TZ, R>;
@@ -526,6 +549,24 @@ void launch_march_t(const ImagePassArgs& a, int cx, hipStream_t s) {
 }
 
 }  // namespace
+
+// gradient form only (the batched rounds always want the gradient)
+void launch_image_march_batch(const ImagePassArgs* args, const BlockRef* blk, int nblk,
+                              int ratio, int variant, bool pow2, hipStream_t s) {
+    if (nblk <= 0) return;
+    const int tz = march_tz(variant), cx = march_cx(variant);
+    if (tz == 64) {
+        if (ratio == 2)
+            launch_march_batch_t<kMY, 64, 2>(args, blk, nblk, cx, pow2, s);
+        else if (ratio == 4)
+            launch_march_batch_t<kMY, 64, 4>(args, blk, nblk, cx, pow2, s);
+    } else {
+        if (ratio == 2)
+            launch_march_batch_t<kMY, 32, 2>(args, blk, nblk, cx, pow2, s);
+        else if (ratio == 4)
+            launch_march_batch_t<kMY, 32, 4>(args, blk, nblk, cx, pow2, s);
+    }
+}
 
 void launch_image_march(const ImagePassArgs& a, int ratio, int tz, int cx, hipStream_t s) {
     if (tz == 64) {

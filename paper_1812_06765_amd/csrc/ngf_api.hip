@@ -15,96 +15,13 @@
 #include <vector>
 
 #include "../../include/ngfreg.h"
+#include "ngf_ctx.h"
 #include "ngf_internal.h"
 
 using namespace ngf;
+using namespace ngf_host;
 
-namespace {
-
-struct Level {
-    int m[3] = {0, 0, 0};
-    int my[3] = {0, 0, 0};
-    double h[3] = {0, 0, 0};
-    double hy[3] = {0, 0, 0};
-    float* R = nullptr;
-    float* T = nullptr;
-    int32_t* j0[3] = {nullptr, nullptr, nullptr};
-    float* w0[3] = {nullptr, nullptr, nullptr};
-    float* w1[3] = {nullptr, nullptr, nullptr};
-    int variant = kTile3D;  // image-pass variant (autotuned or forced)
-    int64_t N() const { return static_cast<int64_t>(m[0]) * m[1] * m[2]; }
-    int64_t Ny() const { return static_cast<int64_t>(my[0]) * my[1] * my[2]; }
-};
-
-struct LevelStore {
-    int64_t cap_n = 0;               // floats in R and in T
-    int cap_m[3] = {0, 0, 0};        // entries per index-map axis
-    void* p[11] = {};                // R, T, then j0, w0, w1 per axis
-};
-
-constexpr int kProfMax = 4096;
-
-}  // namespace
-
-struct ngf_ctx {
-    ngf_params p{};
-    hipStream_t stream = nullptr;
-    hipStream_t side[2] = {nullptr, nullptr};
-    hipEvent_t join[3] = {nullptr, nullptr, nullptr};
-    std::string err;
-    std::vector<Level> lv;
-    // device storage of the pyramid, per level, kept across pyramids and
-    // reused whenever it is large enough for the new shape
-    std::vector<LevelStore> store;
-
-    // evaluation scratch (sized for level 0 by ngf_build_pyramid / ngf_reserve)
-    float* part = nullptr;
-    size_t part_cap = 0;  // floats
-    double* dpart = nullptr;
-    size_t dpart_cap = 0;
-    double* spart = nullptr;
-    double* gpart = nullptr;
-    size_t nblk_cap = 0;
-    double* jds = nullptr;       // device {J, D, S, max|g|, |g|^2, ...}
-    double* host_jds = nullptr;  // pinned: 8 doubles, then room for an LbCtl
-    int* dflag = nullptr;
-
-    // L-BFGS
-    size_t lb_cap = 0;  // floats per vector
-    size_t lb_ld = 0;   // row stride of the history (multiple of 64 floats)
-    float* ly = nullptr;
-    float* lg = nullptr;
-    float* lyt = nullptr;
-    float* lgt = nullptr;
-    float* ld = nullptr;
-    float* ltmp = nullptr;
-    float* hist = nullptr;
-    LbState* st = nullptr;
-    double* dotpart = nullptr;
-    int lb_level = -1;
-    double lb_J = 0.0;
-    double lb_gmax = 0.0;
-    int lb_evals = 0;
-
-    bool host_driven = false;  // register_levels: host-side line search (one sync per trial)
-
-    // image-pass variant: -1 = autotune, else forced for every level
-    int forced_variant = -1;  // also kVariantBySize
-    bool tune_loaded = false;
-    std::vector<std::pair<std::string, int>> tune_cache;  // shape key -> variant
-
-    // differentiation form: grid and index maps of the last explicit pair
-    Level pair;
-    std::vector<void*> pair_owned;
-
-    // profiling of the image-pass kernel
-    bool prof = false;
-    std::vector<hipEvent_t> ev;
-    int nprof = 0;                 // records in use (events 2i, 2i + 1)
-    std::vector<int> prof_level;   // pyramid level of each record (-1: explicit pair)
-};
-
-namespace {
+namespace ngf_host {
 
 ngf_status fail(ngf_ctx* c, ngf_status s, const std::string& msg) {
     if (c) c->err = msg;
@@ -148,12 +65,6 @@ bool params_ok(const ngf_params* p, std::string* why) {
 
 int tiles(int m, int t) { return (m + t - 1) / t; }
 
-// Tile geometry of an image-pass variant: image tile extent per axis.
-struct Geo {
-    int tx, ty, tz;
-    int ntx, nty, ntz;
-    int64_t ntiles() const { return static_cast<int64_t>(ntx) * nty * ntz; }
-};
 Geo geometry(const Level& L, int variant) {
     Geo g{};
     if (is_tile3d(variant)) {
@@ -348,35 +259,14 @@ ImagePassArgs image_args(ngf_ctx* c, const Level& L, const float* R, const float
     return a;
 }
 
-// Enqueue one evaluation on the context stream; results land in c->jds and
-// (if grad != nullptr) in grad.
-ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float* T,
-                        const float* y, float* grad, const int* gate = nullptr,
-                        LbState* decide = nullptr) {
+EvalArgs eval_args(ngf_ctx* c, const Level& L, const float* R, const float* T, const float* y,
+                   float* grad, const int* gate, LbState* decide) {
     const bool want = grad != nullptr;
-    ImagePassArgs a = image_args(c, L, R, T, y, want);
+    EvalArgs e{};
+    ImagePassArgs& a = e.a;
+    a = image_args(c, L, R, T, y, want);
     a.gate = gate;
-    auto launch = [&] {
-        if (!is_march(L.variant))
-            launch_image_pass(a, c->p.ratio, L.variant, c->stream);
-        else
-            launch_image_march(a, c->p.ratio, march_tz(L.variant), march_cx(L.variant),
-                               c->stream);
-    };
-    if (c->prof && c->nprof < kProfMax) {
-        HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof], c->stream));
-        launch();
-        HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof + 1], c->stream));
-        int li = -1;
-        for (size_t l = 0; l < c->lv.size(); ++l)
-            if (&c->lv[l] == &L) li = static_cast<int>(l);
-        c->prof_level[c->nprof] = li;
-        c->nprof++;
-    } else {
-        launch();
-    }
-    HIPCHK(c, hipGetLastError());
-    NodePassArgs b{};
+    NodePassArgs& b = e.b;
     b.y = y;
     b.part = c->part;
     b.grad = grad;
@@ -408,9 +298,7 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
     b.gather = 1;
     b.gscale = nullptr;
     b.gate = gate;
-    launch_node_pass(b, c->stream);
-    HIPCHK(c, hipGetLastError());
-    ReduceArgs r{};
+    ReduceArgs& r = e.r;
     r.dpart = c->dpart;
     r.nd = static_cast<int>(g.ntiles());
     r.spart = c->spart;
@@ -423,7 +311,38 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
     r.out = c->jds;
     r.gate = gate;
     r.lb = decide;
-    launch_reduce(r, c->stream);
+    return e;
+}
+
+// Enqueue one evaluation on the context stream; results land in c->jds and
+// (if grad != nullptr) in grad.
+ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float* T,
+                        const float* y, float* grad, const int* gate = nullptr,
+                        LbState* decide = nullptr) {
+    const EvalArgs e = eval_args(c, L, R, T, y, grad, gate, decide);
+    auto launch = [&] {
+        if (!is_march(L.variant))
+            launch_image_pass(e.a, c->p.ratio, L.variant, c->stream);
+        else
+            launch_image_march(e.a, c->p.ratio, march_tz(L.variant), march_cx(L.variant),
+                               c->stream);
+    };
+    if (c->prof && c->nprof < kProfMax) {
+        HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof], c->stream));
+        launch();
+        HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof + 1], c->stream));
+        int li = -1;
+        for (size_t l = 0; l < c->lv.size(); ++l)
+            if (&c->lv[l] == &L) li = static_cast<int>(l);
+        c->prof_level[c->nprof] = li;
+        c->nprof++;
+    } else {
+        launch();
+    }
+    HIPCHK(c, hipGetLastError());
+    launch_node_pass(e.b, c->stream);
+    HIPCHK(c, hipGetLastError());
+    launch_reduce(e.r, c->stream);
     HIPCHK(c, hipGetLastError());
     return NGF_OK;
 }
@@ -615,7 +534,7 @@ ngf_status check_level(const ngf_ctx* c, int level) {
     return NGF_OK;
 }
 
-}  // namespace
+}  // namespace ngf_host
 
 // ---------------------------------------------------------------------------
 // C ABI

@@ -1,0 +1,128 @@
+// Host-side state of a context (internal to the library): the pyramid, the
+// evaluation scratch and the L-BFGS buffers, shared by the single-pair entry
+// points and the batched driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ngfreg.h"
+#include "ngf_internal.h"
+
+namespace ngf_host {
+
+using namespace ngf;
+
+struct Level {
+    int m[3] = {0, 0, 0};
+    int my[3] = {0, 0, 0};
+    double h[3] = {0, 0, 0};
+    double hy[3] = {0, 0, 0};
+    float* R = nullptr;
+    float* T = nullptr;
+    int32_t* j0[3] = {nullptr, nullptr, nullptr};
+    float* w0[3] = {nullptr, nullptr, nullptr};
+    float* w1[3] = {nullptr, nullptr, nullptr};
+    int variant = kTile3D;  // image-pass variant (autotuned or forced)
+    int64_t N() const { return static_cast<int64_t>(m[0]) * m[1] * m[2]; }
+    int64_t Ny() const { return static_cast<int64_t>(my[0]) * my[1] * my[2]; }
+};
+
+struct LevelStore {
+    int64_t cap_n = 0;               // floats in R and in T
+    int cap_m[3] = {0, 0, 0};        // entries per index-map axis
+    void* p[11] = {};                // R, T, then j0, w0, w1 per axis
+};
+
+constexpr int kProfMax = 4096;
+
+}  // namespace ngf_host
+
+struct ngf_ctx {
+    ngf_params p{};
+    hipStream_t stream = nullptr;
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t join[3] = {nullptr, nullptr, nullptr};
+    std::string err;
+    std::vector<ngf_host::Level> lv;
+    // device storage of the pyramid, per level, kept across pyramids and
+    // reused whenever it is large enough for the new shape
+    std::vector<ngf_host::LevelStore> store;
+
+    // evaluation scratch (sized for level 0 by ngf_build_pyramid / ngf_reserve)
+    float* part = nullptr;
+    size_t part_cap = 0;  // floats
+    double* dpart = nullptr;
+    size_t dpart_cap = 0;
+    double* spart = nullptr;
+    double* gpart = nullptr;
+    size_t nblk_cap = 0;
+    double* jds = nullptr;       // device {J, D, S, max|g|, |g|^2, ...}
+    double* host_jds = nullptr;  // pinned: 8 doubles, then room for an LbCtl
+    int* dflag = nullptr;
+
+    // L-BFGS
+    size_t lb_cap = 0;  // floats per vector
+    size_t lb_ld = 0;   // row stride of the history (multiple of 64 floats)
+    float* ly = nullptr;
+    float* lg = nullptr;
+    float* lyt = nullptr;
+    float* lgt = nullptr;
+    float* ld = nullptr;
+    float* ltmp = nullptr;
+    float* hist = nullptr;
+    ngf::LbState* st = nullptr;
+    double* dotpart = nullptr;
+    int lb_level = -1;
+    double lb_J = 0.0;
+    double lb_gmax = 0.0;
+    int lb_evals = 0;
+
+    bool host_driven = false;  // register_levels: host-side line search (one sync per trial)
+
+    // image-pass variant: -1 = autotune, else forced for every level
+    int forced_variant = -1;  // also kVariantBySize
+    bool tune_loaded = false;
+    std::vector<std::pair<std::string, int>> tune_cache;  // shape key -> variant
+
+    // differentiation form: grid and index maps of the last explicit pair
+    ngf_host::Level pair;
+    std::vector<void*> pair_owned;
+
+    // profiling of the image-pass kernel
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    int nprof = 0;                 // records in use (events 2i, 2i + 1)
+    std::vector<int> prof_level;   // pyramid level of each record (-1: explicit pair)
+};
+
+
+namespace ngf_host {
+
+// Tile geometry of an image-pass variant: image tile extent per axis.
+struct Geo {
+    int tx, ty, tz;
+    int ntx, nty, ntz;
+    int64_t ntiles() const { return static_cast<int64_t>(ntx) * nty * ntz; }
+};
+Geo geometry(const Level& L, int variant);
+int tiles(int m, int t);
+int64_t node_blocks(const Level& L);
+ngf_status fail(ngf_ctx* c, ngf_status s, const std::string& msg);
+
+// Arguments of the three kernels of one evaluation at level L of context c:
+// y evaluated, gradient into grad (null: value only), results in c->jds;
+// gate and decide as in ImagePassArgs / ReduceArgs.
+struct EvalArgs {
+    ImagePassArgs a;
+    NodePassArgs b;
+    ReduceArgs r;
+};
+EvalArgs eval_args(ngf_ctx* c, const Level& L, const float* R, const float* T, const float* y,
+                   float* grad, const int* gate, LbState* decide);
+bool pow2(double h);
+
+}  // namespace ngf_host

@@ -198,6 +198,52 @@ __device__ inline void lb_decide_one(LbState* st, double Jt) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batched launches: one launch covers the same stage of many independent
+// pairs.  A block table maps each workgroup to (pair, block index within the
+// pair's own launch); pair < 0 marks padding.  Each pair's range of the table
+// starts at a multiple of 8, so every block lands on the XCD it would have in
+// the pair's own launch.  The bodies are those of the single-pair kernels,
+// so every pair computes exactly what its own launch computes.
+// ---------------------------------------------------------------------------
+struct BlockRef {
+    int pair;
+    int block;
+};
+
+// one pair's L-BFGS buffers for the batched round kernels
+struct LbVecArgs {
+    LbState* st;
+    float* hist;
+    int64_t ld;
+    int64_t n;
+    float* y;
+    float* g;
+    float* d;
+    float* yt;
+    float* gt;
+    double* dotpart;
+    int nblocks;      // blocks of the pair's vector launches (lb_dot_blocks(n))
+    double* jds;
+    // level start
+    int mem, max_iter, early_stop;
+    double hmin, tol;
+};
+
+void launch_image_pass_batch(const ImagePassArgs* args, const BlockRef* blk, int nblk, int ratio,
+                             int variant, bool pow2, hipStream_t s);
+void launch_image_march_batch(const ImagePassArgs* args, const BlockRef* blk, int nblk,
+                              int ratio, int variant, bool pow2, hipStream_t s);
+void launch_node_pass_batch(const NodePassArgs* args, const BlockRef* blk, int nblk,
+                            hipStream_t s);
+void launch_reduce_batch(const ReduceArgs* args, int npairs, hipStream_t s);
+void launch_lb_init_batch(const LbVecArgs* args, int npairs, hipStream_t s);
+void launch_lb_plan_batch(const LbVecArgs* args, int npairs, hipStream_t s);
+void launch_lb_vec_batch(const LbVecArgs* args, const BlockRef* blk, int nblk, hipStream_t s);
+void launch_lb_accept_batch(const LbVecArgs* args, const BlockRef* blk, int nblk, int npairs,
+                            int mem, hipStream_t s);
+void launch_ctl_gather(const LbVecArgs* args, LbCtl* out, int npairs, hipStream_t s);
+
 // kernels (definitions in the .hip files), launched from the host code
 void launch_downsample(const float* src, float* dst, int mx, int my, int mz, hipStream_t s);
 void launch_index_map(int32_t* j0, float* w0, float* w1, int m, int my, hipStream_t s);

@@ -98,6 +98,7 @@ def load():
         "ngf_batch_destroy": ([_P], None),
         "ngf_batch_last_error": ([_P], ctypes.c_char_p),
         "ngf_batch_set_kernel": ([_P, i32], i32),
+        "ngf_batch_set_mode": ([_P, i32], i32),
         "ngf_batch_register": ([_P, i32, ctypes.POINTER(_P), ctypes.POINTER(_P),
                                 ctypes.POINTER(Grid), ctypes.POINTER(_P), _P,
                                 ctypes.POINTER(Report)], i32),
@@ -395,12 +396,15 @@ def version() -> str:
 
 class Batch:
     """An ngf_batch: independent registrations of many image pairs of any
-    shapes on one device, run concurrently by ``workers`` host threads, each
-    with its own context and stream.  Each pair's result equals the
-    single-pair ``Context.register`` result for the same image-pass variant."""
+    shapes on one device, either level by level with one batched launch
+    sequence per L-BFGS round over all pairs (graph mode), or on ``workers``
+    host threads with a context each (threads mode).  Each pair's result
+    equals the single-pair ``Context.register`` result for the same
+    image-pass variants."""
 
     def __init__(self, alpha=0.1, tau=1.0, rho=1.0, levels=1, ratio=2, max_iter=50,
-                 lbfgs_mem=5, tol_J=1e-6, early_stop=False, workers=4, device="cuda"):
+                 lbfgs_mem=5, tol_J=1e-6, early_stop=False, workers=4, mode="graph",
+                 device="cuda"):
         self.lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible: the ngf library has no CPU path")
@@ -413,6 +417,7 @@ class Batch:
         if st != OK:
             raise NgfError(st, "ngf_batch_create failed")
         self.h = h
+        self.set_mode(mode)
 
     def close(self):
         if getattr(self, "h", None):
@@ -432,6 +437,11 @@ class Batch:
     def set_kernel(self, variant):
         v = Context.VARIANTS.get(variant, variant)
         self._chk(self.lib.ngf_batch_set_kernel(self.h, int(v)))
+
+    def set_mode(self, mode):
+        """'graph' (default: batched launches per round, captured as a
+        hipGraph) or 'threads' (worker threads, one context each)."""
+        self._chk(self.lib.ngf_batch_set_mode(self.h, {"graph": 0, "threads": 1}[mode]))
 
     def register(self, Rs, Ts, hs=None, out=None):
         """Register pairs (Rs[i], Ts[i]) (contiguous float32 device tensors)

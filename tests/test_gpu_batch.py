@@ -1,5 +1,7 @@
 """Batched form on the GPU: registrations of many pairs of different shapes,
-run concurrently by worker threads (each with its own context and stream).
+in graph mode (all pairs level by level, one batched launch sequence per
+L-BFGS round, captured as a hipGraph and replayed) and in threads mode
+(worker threads, each with its own context and stream).
 
 Every pair's deformation and per-level report must equal, bit for bit, the
 single-pair registration with the same image-pass variant (the single-pair
@@ -68,27 +70,29 @@ def test_batch_equals_single_pair_bitwise(gpu_lib):
     pairs = _pairs(SMALL, 100)
     _say(f"[batch] {len(pairs)} pairs, shapes {SMALL}")
     ys1, reps1 = _single(ngf, pairs, levels=2, max_iter=15)
-    for workers in (1, 3, 8):
-        b = ngf.Batch(levels=2, max_iter=15, workers=workers, **PARAMS)
+    for mode, workers in (("graph", 1), ("threads", 1), ("threads", 3), ("threads", 8)):
+        b = ngf.Batch(levels=2, max_iter=15, workers=workers, mode=mode, **PARAMS)
+        b.set_kernel("by_size")
         ys, reps = b.register([p[0] for p in pairs], [p[1] for p in pairs])
         b.close()
         for i in range(len(pairs)):
-            assert _same(ys[i], ys1[i]), (workers, i)
-            assert _strip(reps[i]) == _strip(reps1[i]), (workers, i)
-        _say(f"[batch] workers={workers}: all pairs bitwise equal to single-pair runs")
+            assert _same(ys[i], ys1[i]), (mode, workers, i)
+            assert _strip(reps[i]) == _strip(reps1[i]), (mode, workers, i)
+        _say(f"[batch] {mode} workers={workers}: all pairs bitwise equal to single-pair runs")
     # the registrations did something: J fell at the finest level
     for rep in reps1:
         assert rep[0]["iters"] >= 1 and np.isfinite(rep[0]["J"])
 
 
-def test_batch_forced_variant_and_reuse(gpu_lib):
+@pytest.mark.parametrize("MODE", ["graph", "threads"])
+def test_batch_forced_variant_and_reuse(gpu_lib, MODE):
     """A forced variant applies to every worker; a second batch on the same
     object (storage kept from the first) gives the same results."""
     import torch
     ngf = gpu_lib
     pairs = _pairs(SMALL[:5], 200)
     ys1, _ = _single(ngf, pairs, levels=2, max_iter=8, variant="march32x8")
-    b = ngf.Batch(levels=2, max_iter=8, workers=4, **PARAMS)
+    b = ngf.Batch(levels=2, max_iter=8, workers=4, mode=MODE, **PARAMS)
     b.set_kernel("march32x8")
     for rnd in range(2):
         ys, _ = b.register([p[0] for p in pairs], [p[1] for p in pairs])
@@ -111,8 +115,8 @@ def test_batch_uneven_shapes_at_full_size(gpu_lib):
     pairs = _pairs(shapes, 300, max_disp=6.0)
     _say(f"[batch] uneven shapes {shapes}")
     b = ngf.Batch(levels=3, max_iter=50, workers=4, **PARAMS)
+    b.set_kernel("by_size")
     ys, reps = b.register([p[0] for p in pairs], [p[1] for p in pairs])
-    b.close()
     pick = [0, 5]
     ys1, reps1 = _single(ngf, [pairs[i] for i in pick], levels=3, max_iter=50)
     for k, i in enumerate(pick):
@@ -125,14 +129,26 @@ def test_batch_uneven_shapes_at_full_size(gpu_lib):
         for r in rep:
             assert r["info"] in (ngf.INFO_CONVERGED, ngf.INFO_MAX_ITER), (i, r)
             assert r["evals"] >= r["iters"] + 1
+    # the timed selection (the graph mode's default), shared by the pairs:
+    # valid results and the same per-level outcome classes
+    b.set_kernel("auto")
+    ys2, reps2 = b.register([p[0] for p in pairs], [p[1] for p in pairs])
+    b.close()
+    for i, (y, rep) in enumerate(zip(ys2, reps2)):
+        assert bool(torch.isfinite(y).all()), i
+        for r, r0 in zip(rep, reps[i]):
+            assert (r["iters"] == r0["iters"]
+                    or ngf.INFO_CONVERGED in (r["info"], r0["info"])), (i, r, r0)
+            assert abs(r["J"] - r0["J"]) <= 5e-2 * abs(r0["J"]), (i, r, r0)
 
 
-def test_batch_error_names_the_pair(gpu_lib):
+@pytest.mark.parametrize("MODE", ["graph", "threads"])
+def test_batch_error_names_the_pair(gpu_lib, MODE):
     ngf = gpu_lib
     import torch
     good = _pairs([(32, 32, 32)], 400)[0]
     bad = (torch.zeros((30, 32, 32), device="cuda"), torch.zeros((30, 32, 32), device="cuda"))
-    b = ngf.Batch(levels=2, max_iter=3, workers=2, **PARAMS)
+    b = ngf.Batch(levels=2, max_iter=3, workers=2, mode=MODE, **PARAMS)
     with pytest.raises(ngf.NgfError) as e:
         b.register([good[0], bad[0]], [good[1], bad[1]])
     assert e.value.status == ngf.E_SHAPE and "pair 1" in str(e.value)
