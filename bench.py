@@ -219,6 +219,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--shape", type=int, nargs=3, default=None,
+                    help="image shape (x y z) instead of size^3, e.g. 512 512 1536")
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--max-iter", type=int, default=50)
     ap.add_argument("--finest-evals", type=int, default=200)
@@ -259,11 +261,18 @@ def main():
     if args.pt_ablation:
         return bench_pt(args, torch, ngf)
 
-    n = args.size
+    shape = tuple(args.shape) if args.shape else (args.size,) * 3
+    sname = "x".join(str(v) for v in shape)
     t_gen = time.perf_counter()
-    pr = synth.ct_phantom_pair((n, n, n), seed_R=5, seed_u=6)
+    if shape[0] * shape[1] * shape[2] > (1 << 26):  # large volumes: in slabs
+        def progress(done, total):
+            if done % 128 == 0 or done == total:
+                print(f"[bench] inputs: {done}/{total} planes", file=sys.stderr, flush=True)
+        pr = synth.ct_phantom_pair_slabs(shape, seed_R=5, seed_u=6, progress=progress)
+    else:
+        pr = synth.ct_phantom_pair(shape, seed_R=5, seed_u=6)
     t_gen = time.perf_counter() - t_gen
-    print(f"[bench] inputs {n}^3 generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
+    print(f"[bench] inputs {sname} generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
     R = torch.from_numpy(pr.R).cuda()
     T = torch.from_numpy(pr.T).cuda()
     ctx = ngf.Context(alpha=0.1, tau=10.0, rho=10.0, levels=args.levels, ratio=2,
@@ -329,8 +338,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (f64 coordinates and reductions)",
         "data": "synthetic: seeded CT-like phantom pair, B-spline warp (max 6 voxels)",
-        "config": {"workload": f"single pair {n}^3 CT phantom, {args.levels}-level pyramid, "
-                               f"deformation grid {li.my[0]}^3 at the finest level, "
+        "config": {"workload": f"single pair {sname} CT phantom, {args.levels}-level pyramid, "
+                               f"deformation grid {'x'.join(str(v) for v in li.my)} at the "
+                               "finest level, "
                                f"alpha=0.1, eps=10, L-BFGS m=5, <= {args.max_iter} it/level, "
                                "early stop 1e-6",
                    "global_batch": 1, "seq_len": None, "parallelism": "single GPU"},

@@ -31,6 +31,7 @@ __all__ = [
     "BSplineField",
     "blob_phantom_pair",
     "ct_phantom_pair",
+    "ct_phantom_pair_slabs",
     "ct_phantom_value",
     "invert_displacement",
     "smooth_node_perturbation",
@@ -115,19 +116,23 @@ class BSplineField:
         self.ncp = [int(np.ceil(n / self.spacing)) + 4 for n in self.m]
         self.coef = rng.standard_normal(size=(3,) + tuple(self.ncp))
         self.scale = 1.0
-        raw = self.on_grid()
-        self.scale = max_amp / float(np.sqrt((raw**2).sum(0)).max())
+        peak, step = 0.0, max(1, (1 << 24) // (self.m[1] * self.m[2]))
+        for x0 in range(0, self.m[0], step):  # in slabs: bounded memory
+            raw = self.on_grid(x0, min(self.m[0], x0 + step))
+            peak = max(peak, float(np.sqrt((raw**2).sum(0)).max()))
+        self.scale = max_amp / peak
 
     def _basis(self, d: int, p: np.ndarray) -> np.ndarray:
         # control point k sits at (k - 1) * spacing
         k = np.arange(self.ncp[d], dtype=np.float64)
         return _cubic_bspline(p[..., None] / self.spacing - (k - 1.0))
 
-    def on_grid(self) -> np.ndarray:
-        """Field at the voxel centres of the grid, (3, mx, my, mz)."""
-        bx, by, bz = (
-            self._basis(d, np.arange(self.m[d], dtype=np.float64) + 0.5) for d in range(3)
-        )
+    def on_grid(self, x0: int = 0, x1: int | None = None) -> np.ndarray:
+        """Field at the voxel centres of the grid, (3, mx, my, mz), or of the
+        x-slab [x0, x1) of it."""
+        x1 = self.m[0] if x1 is None else x1
+        bx = self._basis(0, np.arange(x0, x1, dtype=np.float64) + 0.5)
+        by, bz = (self._basis(d, np.arange(self.m[d], dtype=np.float64) + 0.5) for d in (1, 2))
         out = np.einsum("cijk,xi,yj,zk->cxyz", self.coef, bx, by, bz, optimize=True)
         return np.ascontiguousarray(self.scale * out)
 
@@ -243,6 +248,33 @@ def ct_phantom_value(p: np.ndarray, m) -> np.ndarray:
     spine = _soft(rad - np.sqrt((p[0] - 0.5 * m[0]) ** 2 + (p[1] - 0.72 * m[1]) ** 2))
     val = val + (700.0 - 40.0) * spine * body
     return val
+
+
+def ct_phantom_pair_slabs(m, seed_R=5, seed_u=6, max_disp=6.0, cp_spacing=16.0, noise=20.0,
+                          slab=32, progress=None):
+    """The CT pair recipe of ``ct_phantom_pair`` generated in x-slabs of
+    ``slab`` planes, for volumes too large to form in one piece (bounded
+    memory, a progress callback per slab).  The noise of slab k is drawn
+    from PCG64 seeded with (seed_R, k) for R and (seed_R, k, 1) for T, so the
+    values differ from ``ct_phantom_pair`` of the same seeds; the recipe is
+    the same."""
+    m = tuple(int(v) for v in m)
+    field = BSplineField(m, cp_spacing, max_disp, seed_u)
+    R = np.empty(m, dtype=np.float32)
+    T = np.empty(m, dtype=np.float32)
+    ax = [np.arange(n, dtype=np.float64) + 0.5 for n in m]
+    for k, x0 in enumerate(range(0, m[0], slab)):
+        x1 = min(m[0], x0 + slab)
+        x = np.stack(np.meshgrid(ax[0][x0:x1], ax[1], ax[2], indexing="ij"))
+        shp = (x1 - x0, m[1], m[2])
+        rng_r = np.random.Generator(np.random.PCG64([seed_R, k]))
+        rng_t = np.random.Generator(np.random.PCG64([seed_R, k, 1]))
+        R[x0:x1] = ct_phantom_value(x, m) + rng_r.normal(0.0, noise, size=shp)
+        T[x0:x1] = ct_phantom_value(x + field.on_grid(x0, x1), m) + rng_t.normal(0.0, noise,
+                                                                                  size=shp)
+        if progress is not None:
+            progress(x1, m[0])
+    return Pair(R, T, field, m, (1.0, 1.0, 1.0), (seed_R, seed_u))
 
 
 def ct_phantom_pair(m=(128, 128, 128), h=(1.0, 1.0, 1.0), seed_R=3, seed_u=4,
