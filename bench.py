@@ -268,7 +268,8 @@ def main():
         def progress(done, total):
             if done % 128 == 0 or done == total:
                 print(f"[bench] inputs: {done}/{total} planes", file=sys.stderr, flush=True)
-        pr = synth.ct_phantom_pair_slabs(shape, seed_R=5, seed_u=6, progress=progress)
+        pr = synth.ct_phantom_pair_slabs(shape, seed_R=5, seed_u=6, progress=progress,
+                                         workers=min(16, os.cpu_count() or 1))
     else:
         pr = synth.ct_phantom_pair(shape, seed_R=5, seed_u=6)
     t_gen = time.perf_counter() - t_gen

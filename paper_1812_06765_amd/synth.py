@@ -251,7 +251,7 @@ def ct_phantom_value(p: np.ndarray, m) -> np.ndarray:
 
 
 def ct_phantom_pair_slabs(m, seed_R=5, seed_u=6, max_disp=6.0, cp_spacing=16.0, noise=20.0,
-                          slab=32, progress=None):
+                          slab=32, progress=None, workers=8):
     """The CT pair recipe of ``ct_phantom_pair`` generated in x-slabs of
     ``slab`` planes, for volumes too large to form in one piece (bounded
     memory, a progress callback per slab).  The noise of slab k is drawn
@@ -263,7 +263,9 @@ def ct_phantom_pair_slabs(m, seed_R=5, seed_u=6, max_disp=6.0, cp_spacing=16.0, 
     R = np.empty(m, dtype=np.float32)
     T = np.empty(m, dtype=np.float32)
     ax = [np.arange(n, dtype=np.float64) + 0.5 for n in m]
-    for k, x0 in enumerate(range(0, m[0], slab)):
+
+    def one(k):
+        x0 = k * slab
         x1 = min(m[0], x0 + slab)
         x = np.stack(np.meshgrid(ax[0][x0:x1], ax[1], ax[2], indexing="ij"))
         shp = (x1 - x0, m[1], m[2])
@@ -272,8 +274,16 @@ def ct_phantom_pair_slabs(m, seed_R=5, seed_u=6, max_disp=6.0, cp_spacing=16.0, 
         R[x0:x1] = ct_phantom_value(x, m) + rng_r.normal(0.0, noise, size=shp)
         T[x0:x1] = ct_phantom_value(x + field.on_grid(x0, x1), m) + rng_t.normal(0.0, noise,
                                                                                   size=shp)
-        if progress is not None:
-            progress(x1, m[0])
+        return x1
+
+    from concurrent.futures import ThreadPoolExecutor
+    nslab = (m[0] + slab - 1) // slab
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        done = 0
+        for _ in ex.map(one, range(nslab)):
+            done += 1
+            if progress is not None:
+                progress(min(m[0], done * slab), m[0])
     return Pair(R, T, field, m, (1.0, 1.0, 1.0), (seed_R, seed_u))
 
 
