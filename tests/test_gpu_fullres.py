@@ -1,0 +1,117 @@
+"""Full-resolution single pair: 512 x 512 x 1536 voxels (403 M, the scanner
+resolution of the paper's data, Sec. 3, which did not fit its GPU) with the
+5-level pyramid the benchmark registers, deformation grid 257 x 257 x 769.
+
+At this size the oracle cannot evaluate the finest level in a test's time, so:
+index maps bit-exact on every level; pyramid levels bit-exact on sampled
+blocks (the oracle's box means over the blocks' level-0 regions); the full
+oracle evaluation at the 128 x 128 x 384 level (J, grad J); at the finest
+level the properties that hold at any size (finite J and gradient, 0 <= D <=
+hbar N / 2, S = 0 and grad S = 0 at the identity); and a full registration
+whose per-level outcome is valid.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1812_06765_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+M = (512, 512, 1536)
+LEVELS = 5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fullres(gpu_lib):
+    import torch
+    ngf = gpu_lib
+    pr = synth.ct_phantom_pair_slabs(M, seed_R=5, seed_u=6, workers=16)
+    _say("[fullres] inputs generated")
+    R, T = torch.from_numpy(pr.R).cuda(), torch.from_numpy(pr.T).cuda()
+    ctx = ngf.Context(alpha=0.1, tau=10.0, rho=10.0, levels=LEVELS, max_iter=50,
+                      early_stop=True)
+    ctx.set_kernel("by_size")
+    ctx.build_pyramid(R, T)
+    return ngf, ctx, pr, R, T
+
+
+def test_fullres_index_maps_and_sampled_pyramid_bit_exact(fullres):
+    ngf, ctx, pr, _, _ = fullres
+    for lev in range(LEVELS):
+        li = ctx.level_info(lev)
+        for d in range(3):
+            j0, w0, w1 = (t.cpu().numpy() for t in ctx.index_map(lev, d))
+            oj, ow0, ow1 = O.index_map_f32(li.m[d], li.my[d])
+            assert np.array_equal(j0, oj) and np.array_equal(w0, ow0)
+            assert np.array_equal(w1, ow1)
+    rng = np.random.default_rng(3)
+    for lev in range(1, LEVELS):
+        Rg, Tg = (t.cpu().numpy() for t in ctx.level_images(lev))
+        li = ctx.level_info(lev)
+        for _ in range(3):
+            # a 4^3 block of level lev and its level-0 region
+            b = [int(rng.integers(0, li.m[d] // 4)) * 4 for d in range(3)]
+            s = 1 << lev
+            sl0 = tuple(slice(b[d] * s, (b[d] + 4) * s) for d in range(3))
+            r, t = pr.R[sl0], pr.T[sl0]
+            for _ in range(lev):
+                r, t = O.downsample(r), O.downsample(t)
+            sl = tuple(slice(b[d], b[d] + 4) for d in range(3))
+            assert np.array_equal(Rg[sl], r), (lev, b)
+            assert np.array_equal(Tg[sl], t), (lev, b)
+    _say("[fullres] index maps and sampled pyramid blocks bit-exact")
+
+
+def test_fullres_eval_parity_at_128x128x384(fullres):
+    ngf, ctx, pr, _, _ = fullres
+    import torch
+    lev = 2
+    Rs, Ts = O.pyramid(pr.R, pr.T, lev + 1)
+    m, h, my = O.level_shapes(M, (1.0, 1.0, 1.0), lev + 1)[lev]
+    prob = O.Problem(Rs[lev], Ts[lev], h, my, 0.1, 10.0, 10.0)
+    j = [np.arange(n, dtype=np.float64) / (n - 1) for n in my]
+    w = (np.sin(2 * np.pi * j[0])[:, None, None] * np.sin(np.pi * j[1])[None, :, None]
+         * np.cos(np.pi * j[2])[None, None, :])
+    for amp in (0.0, 2.0 * h[0]):
+        y32 = (prob.identity() + amp * np.stack([w, -w, 0.5 * w])).astype(np.float32)
+        Jo, go, _ = O.eval_J_grad(prob, y32.astype(np.float64))
+        J, g, _ = ctx.eval_J_grad(lev, torch.from_numpy(y32).cuda())
+        g = g.cpu().numpy().astype(np.float64)
+        err = np.linalg.norm(g - go) / np.linalg.norm(go)
+        _say(f"[fullres] level {lev} {m} amp={amp}: J {J} oracle {Jo} grad rel-L2 {err:.2e}")
+        assert abs(J - Jo) <= 1e-5 * abs(Jo)
+        assert err <= 1e-4
+
+
+def test_fullres_finest_level_properties_and_registration(fullres):
+    ngf, ctx, pr, R, T = fullres
+    import torch
+    li = ctx.level_info(0)
+    y = ctx.identity(0)
+    J, g, (D, S) = ctx.eval_J_grad(0, y)
+    N = li.m[0] * li.m[1] * li.m[2]
+    _say(f"[fullres] level 0 at the identity: J {J} D {D} S {S}")
+    assert np.isfinite(J) and 0.0 <= D <= 0.5 * N
+    assert S == 0.0
+    assert bool(torch.isfinite(g).all())
+    # at the identity grad S = 0, so grad J is grad D alone: alpha does not matter
+    ctx.set_params(alpha=1.0)
+    J2, g2, _ = ctx.eval_J_grad(0, y)
+    ctx.set_params(alpha=0.1)
+    assert J2 == J and bool(torch.equal(g, g2))
+    yr, rep = ctx.register(R, T)
+    _say(f"[fullres] registration {rep}")
+    assert bool(torch.isfinite(yr).all())
+    for r in rep:
+        assert r["info"] in (ngf.INFO_CONVERGED, ngf.INFO_MAX_ITER)
+        assert r["iters"] >= 1 and r["evals"] >= r["iters"] + 1
+    assert rep[0]["J"] < J
