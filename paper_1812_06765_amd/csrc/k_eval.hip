@@ -449,8 +449,173 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
     image_body<TX, TY, TZ, RATIO, GRAD, ATOMIC, POW2>(a, blockIdx.x);
 }
 
+// Node pass, marching form: one workgroup per (component, NY x NZ node tile
+// in (y, z), chunk of NX node planes along x); thread t owns the in-plane node
+// (t / NZ, t % NZ) of every plane of the chunk.  u = y - X is kept in three
+// rolling LDS planes with a two-node in-plane halo, A u in three rolling
+// planes with a one-node halo.  Ghost nodes replicate the boundary node
+// (for u and for A u): in-plane through clamped loads and zero offsets, across
+// planes by reading the boundary plane's slot.  Step k loads u of plane
+// x0 - 2 + k, forms A u of plane x0 - 3 + k and A(A u) of plane x0 - 4 + k.
 template <int NX, int NY, int NZ>
-__device__ __forceinline__ void node_body(const NodePassArgs& a, int block) {
+__device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block) {
+    static_assert(NY * NZ == kThreads, "one node per thread and plane");
+    constexpr int UY = NY + 4, UZ = NZ + 4, NU = UY * UZ;  // u plane, halo 2
+    constexpr int AY = NY + 2, AZ = NZ + 2, NA = AY * AZ;  // A u plane, halo 1
+    constexpr int KU = (NU + kThreads - 1) / kThreads, KA = (NA + kThreads - 1) / kThreads;
+    __shared__ float su[3][NU];
+    __shared__ float sAu[3][NA];
+    __shared__ double red[4];
+
+    const int ntile = a.nbx * a.nby * a.nbz;
+    const int bid = xcd_tile(block, 3 * ntile);
+    const int c = bid / ntile;
+    const int blk = bid - c * ntile;
+    const int bz = blk % a.nbz;
+    const int byy = (blk / a.nbz) % a.nby;
+    const int bx = blk / (a.nbz * a.nby);
+    const int x0 = bx * NX, y0 = byy * NY, z0 = bz * NZ;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nn = nx * ny * nz;
+    const int xend = min(x0 + NX, nx);
+    const int PX = a.bx + 1, PY = a.by + 1, PZ = a.bz + 1;
+    const int NP = PX * PY * PZ;
+    const float sc = (!a.gather && a.gscale != nullptr) ? static_cast<float>(*a.gscale) : 1.0f;
+    const float* yc = a.y + c * nn;
+    const double hyc = c == 0 ? a.hyx : (c == 1 ? a.hyy : a.hyz);
+
+    // this thread's node (y, z) and its fixed in-plane data
+    const int ly = threadIdx.x / NZ, lz = threadIdx.x % NZ;
+    const int gy = y0 + ly, gz = z0 + lz;
+    const bool own = gy < ny && gz < nz;
+    const int q = (ly + 1) * AZ + (lz + 1);
+    const int dyp = gy + 1 < ny ? AZ : 0, dym = gy > 0 ? AZ : 0;
+    const int dzp = gz + 1 < nz ? 1 : 0, dzm = gz > 0 ? 1 : 0;
+    // u halo entries of this thread: clamped in-plane offset and coordinate
+    int uoff[KU], ugc[KU];
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        const int iy = i / UZ, iz = i - (i / UZ) * UZ;
+        const int cy = clampi(y0 - 2 + iy, 0, ny - 1), cz = clampi(z0 - 2 + iz, 0, nz - 1);
+        uoff[k] = cy * nz + cz;
+        ugc[k] = c == 1 ? cy : cz;
+    }
+    // A u halo entries of this thread: their (clamped) node's place in the u plane
+    int apos[KA];
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+        const int i = threadIdx.x + k * kThreads;
+        const int iy = i / AZ, iz = i - (i / AZ) * AZ;
+        const int cy = clampi(y0 - 1 + iy, 0, ny - 1), cz = clampi(z0 - 1 + iz, 0, nz - 1);
+        apos[k] = (cy - y0 + 2) * UZ + (cz - z0 + 2);
+    }
+    // gather of the image-tile partials: the (y, z) part is fixed
+    const float ibx = 1.0f / a.bx, iby = 1.0f / a.by, ibz = 1.0f / a.bz;
+    const int tyh = div_small(gy, a.by, iby), tzh = div_small(gz, a.bz, ibz);
+    const int ry = gy - tyh * a.by, rz = gz - tzh * a.bz;
+    const int noy = (ry == 0 && tyh > 0) ? 2 : 1, noz = (rz == 0 && tzh > 0) ? 2 : 1;
+
+    double ssum = 0.0, gmax = 0.0, g2 = 0.0;
+    for (int k = 0; k < NX + 4; ++k) {
+        // u of plane pu (planes outside the grid are never read)
+        const int pu = x0 - 2 + k;
+        if (pu >= 0 && pu < nx) {
+            float* U = su[k % 3];
+            const float* ycp = yc + pu * ny * nz;
+#pragma unroll
+            for (int kk = 0; kk < KU; ++kk) {
+                const int i = threadIdx.x + kk * kThreads;
+                if (i < NU) {
+                    const int gc = c == 0 ? pu : ugc[kk];
+                    U[i] = static_cast<float>(static_cast<double>(ycp[uoff[kk]]) -
+                                              static_cast<double>(gc) * hyc);
+                }
+            }
+        }
+        __syncthreads();
+        // A u of plane pa, from u planes pa - 1, pa, pa + 1 (replicated ghosts)
+        const int pa = pu - 1;
+        if (pa >= 0 && pa < nx) {
+            const float* U0 = su[(k + 2) % 3];                      // plane pa
+            const float* Um = pa > 0 ? su[(k + 1) % 3] : U0;          // plane pa - 1
+            const float* Up = pa + 1 < nx ? su[k % 3] : U0;           // plane pa + 1
+            float* A = sAu[k % 3];
+#pragma unroll
+            for (int kk = 0; kk < KA; ++kk) {
+                const int i = threadIdx.x + kk * kThreads;
+                if (i < NA) {
+                    const int p = apos[kk];
+                    const float u0 = U0[p];
+                    const float lx = Up[p] - 2.0f * u0 + Um[p];
+                    const float lyv = U0[p + UZ] - 2.0f * u0 + U0[p - UZ];
+                    const float lzv = U0[p + 1] - 2.0f * u0 + U0[p - 1];
+                    A[i] = fmaf(lx, a.ihy2x, fmaf(lyv, a.ihy2y, lzv * a.ihy2z));
+                }
+            }
+        }
+        __syncthreads();
+        // A(A u) and the gradient at plane po
+        const int po = pu - 2;
+        if (po >= x0 && po < xend && own) {
+            const float* A0 = sAu[(k + 2) % 3];                     // plane po
+            const float* Am = po > 0 ? sAu[(k + 1) % 3] : A0;         // plane po - 1
+            const float* Ap = po + 1 < nx ? sAu[k % 3] : A0;          // plane po + 1
+            const float au = A0[q];
+            ssum += static_cast<double>(au) * static_cast<double>(au);
+            if (a.want_grad) {
+                float gd = 0.0f;
+                if (!a.gather) {
+                    gd = a.grad[c * nn + (po * ny + gy) * nz + gz];
+                } else {
+                    // Eq. 3 completed: the (at most 8) image-tile partials of the node
+                    const int txh = div_small(po, a.bx, ibx);
+                    const int rx = po - txh * a.bx;
+                    const int nox = (rx == 0 && txh > 0) ? 2 : 1;
+                    for (int ox = 0; ox < nox; ++ox) {
+                        const int ttx = txh - ox, llx = rx + ox * a.bx;
+                        if (ttx >= a.ntx) continue;
+                        for (int oy = 0; oy < noy; ++oy) {
+                            const int tty = tyh - oy, lly = ry + oy * a.by;
+                            if (tty >= a.nty) continue;
+                            for (int oz = 0; oz < noz; ++oz) {
+                                const int ttz = tzh - oz, llz = rz + oz * a.bz;
+                                if (ttz >= a.ntz) continue;
+                                const int tile = (ttx * a.nty + tty) * a.ntz + ttz;
+                                gd += a.part[(static_cast<int64_t>(tile) * 3 + c) * NP +
+                                             (llx * PY + lly) * PZ + llz];
+                            }
+                        }
+                    }
+                }
+                const float lxx = Ap[q] - 2.0f * au + Am[q];
+                const float lyy = A0[q + dyp] - 2.0f * au + A0[q - dym];
+                const float lzz = A0[q + dzp] - 2.0f * au + A0[q - dzm];
+                const float aau = fmaf(lxx, a.ihy2x, fmaf(lyy, a.ihy2y, lzz * a.ihy2z));
+                const float g = fmaf(a.alpha_hbary * sc, aau, gd);
+                a.grad[c * nn + (po * ny + gy) * nz + gz] = g;
+                gmax = fmax(gmax, static_cast<double>(fabsf(g)));
+                g2 += static_cast<double>(g) * static_cast<double>(g);
+            }
+        }
+    }
+    const double st = block_sum(ssum, red);
+    if (threadIdx.x == 0) a.spart[bid] = st;
+    if (a.want_grad) {
+        const double gm = block_max(gmax, red);
+        const double gq = block_sum(g2, red);
+        if (threadIdx.x == 0) {
+            a.gpart[2 * bid] = gm;
+            a.gpart[2 * bid + 1] = gq;
+        }
+    }
+}
+
+// Node pass, 3D-tile form (small grids, where the marching form has too few
+// workgroups): one workgroup per (node tile, component) with the u box of a
+// two-node halo and the A u box of a one-node halo in LDS.
+template <int NX, int NY, int NZ>
+__device__ __forceinline__ void node_tile_body(const NodePassArgs& a, int block) {
     // one workgroup per (node tile, component)
     constexpr int B2X = NX + 4, B2Y = NY + 4, B2Z = NZ + 4, NB2 = B2X * B2Y * B2Z;
     constexpr int B1X = NX + 2, B1Y = NY + 2, B1Z = NZ + 2, NB1 = B1X * B1Y * B1Z;
@@ -573,20 +738,28 @@ __device__ __forceinline__ void node_body(const NodePassArgs& a, int block) {
     }
 }
 
-template <int NX, int NY, int NZ>
-__global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
-    if (a.gate && *a.gate == kOpNone) return;
-    node_body<NX, NY, NZ>(a, blockIdx.x);
+template <bool MARCH>
+__device__ __forceinline__ void node_body(const NodePassArgs& a, int block) {
+    if (MARCH)
+        node_march_body<kNMX, kNMY, kNMZ>(a, block);
+    else
+        node_tile_body<kNTX, kNTY, kNTZ>(a, block);
 }
 
-template <int NX, int NY, int NZ>
+template <bool MARCH>
+__global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
+    if (a.gate && *a.gate == kOpNone) return;
+    node_body<MARCH>(a, blockIdx.x);
+}
+
+template <bool MARCH>
 __global__ __launch_bounds__(kThreads) void k_node_pass_batch(const NodePassArgs* args,
                                                               const BlockRef* blk) {
     const BlockRef e = blk[blockIdx.x];
     if (e.pair < 0) return;
     const NodePassArgs& a = args[e.pair];
     if (a.gate && *a.gate == kOpNone) return;
-    node_body<NX, NY, NZ>(a, e.block);
+    node_body<MARCH>(a, e.block);
 }
 
 template <int TX, int TY, int TZ, int RATIO, bool POW2>
@@ -689,10 +862,14 @@ void launch_image_pass_batch(const ImagePassArgs* args, const BlockRef* blk, int
 }
 
 void launch_node_pass_batch(const NodePassArgs* args, const BlockRef* blk, int nblk,
-                            hipStream_t s) {
+                            bool march, hipStream_t s) {
     if (nblk <= 0) return;
-    hipLaunchKernelGGL((k_node_pass_batch<kNX, kNY, kNZ>), dim3(nblk), dim3(kThreads), 0, s, args,
-                       blk);
+    if (march)
+        hipLaunchKernelGGL((k_node_pass_batch<true>), dim3(nblk), dim3(kThreads), 0, s, args,
+                           blk);
+    else
+        hipLaunchKernelGGL((k_node_pass_batch<false>), dim3(nblk), dim3(kThreads), 0, s, args,
+                           blk);
 }
 
 void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s) {
@@ -702,9 +879,12 @@ void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s) 
         launch_image_ratio_atomic<4>(a, s);
 }
 
-void launch_node_pass(const NodePassArgs& a, hipStream_t s) {
+void launch_node_pass(const NodePassArgs& a, bool march, hipStream_t s) {
     const int blocks = 3 * a.nbx * a.nby * a.nbz;
-    hipLaunchKernelGGL((k_node_pass<kNX, kNY, kNZ>), dim3(blocks), dim3(kThreads), 0, s, a);
+    if (march)
+        hipLaunchKernelGGL((k_node_pass<true>), dim3(blocks), dim3(kThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_node_pass<false>), dim3(blocks), dim3(kThreads), 0, s, a);
 }
 
 }  // namespace ngf

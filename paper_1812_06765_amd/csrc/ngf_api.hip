@@ -92,9 +92,18 @@ bool pow2(double h) {
     return std::frexp(h, &e) == 0.5;
 }
 // node-pass workgroups: one per node tile and component
+bool node_march(const Level& L) { return L.Ny() >= kNodeMarchMin; }
+// node-pass workgroups per axis of the form the level uses
+void node_grid(const Level& L, int nb[3]) {
+    const bool m = node_march(L);
+    nb[0] = tiles(L.my[0], m ? kNMX : kNTX);
+    nb[1] = tiles(L.my[1], m ? kNMY : kNTY);
+    nb[2] = tiles(L.my[2], m ? kNMZ : kNTZ);
+}
 int64_t node_blocks(const Level& L) {
-    return 3 * static_cast<int64_t>(tiles(L.my[0], kNX)) * tiles(L.my[1], kNY) *
-           tiles(L.my[2], kNZ);
+    int nb[3];
+    node_grid(L, nb);
+    return 3 * static_cast<int64_t>(nb[0]) * nb[1] * nb[2];
 }
 
 ngf_status ensure_scratch(ngf_ctx* c, const Level& L) {
@@ -282,9 +291,11 @@ EvalArgs eval_args(ngf_ctx* c, const Level& L, const float* R, const float* T, c
     b.bx = g.tx / c->p.ratio;
     b.by = g.ty / c->p.ratio;
     b.bz = g.tz / c->p.ratio;
-    b.nbx = tiles(L.my[0], kNX);
-    b.nby = tiles(L.my[1], kNY);
-    b.nbz = tiles(L.my[2], kNZ);
+    int nb[3];
+    node_grid(L, nb);
+    b.nbx = nb[0];
+    b.nby = nb[1];
+    b.nbz = nb[2];
     b.hyx = L.hy[0];
     b.hyy = L.hy[1];
     b.hyz = L.hy[2];
@@ -340,7 +351,7 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
         launch();
     }
     HIPCHK(c, hipGetLastError());
-    launch_node_pass(e.b, c->stream);
+    launch_node_pass(e.b, node_march(L), c->stream);
     HIPCHK(c, hipGetLastError());
     launch_reduce(e.r, c->stream);
     HIPCHK(c, hipGetLastError());
@@ -1107,9 +1118,11 @@ ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], con
     b.nx = P.my[0];
     b.ny = P.my[1];
     b.nz = P.my[2];
-    b.nbx = tiles(P.my[0], kNX);
-    b.nby = tiles(P.my[1], kNY);
-    b.nbz = tiles(P.my[2], kNZ);
+    int nb[3];
+    node_grid(P, nb);
+    b.nbx = nb[0];
+    b.nby = nb[1];
+    b.nbz = nb[2];
     b.hyx = P.hy[0];
     b.hyy = P.hy[1];
     b.hyz = P.hy[2];
@@ -1122,7 +1135,7 @@ ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], con
     b.want_grad = grad_y ? 1 : 0;
     b.gather = 0;
     b.gscale = gscale;
-    launch_node_pass(b, c->stream);
+    launch_node_pass(b, node_march(P), c->stream);
     HIPCHK(c, hipGetLastError());
     ReduceArgs rd{};
     rd.dpart = c->dpart;

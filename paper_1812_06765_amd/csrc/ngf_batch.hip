@@ -96,7 +96,7 @@ struct LevelTables {
         size_t off = 0;
     };
     std::vector<Group> groups;
-    std::vector<BlockRef> node_blk, vec_blk;
+    std::vector<BlockRef> node_blk[2], vec_blk;  // node pass: 3D-tile form, marching form
 };
 
 template <class T>
@@ -203,7 +203,7 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
                 g = &t.groups.back();
             }
             add_blocks(g->blk, i, geometry(lv, lv.variant).ntiles());
-            add_blocks(t.node_blk, i, node_blocks(lv));
+            add_blocks(t.node_blk[node_march(lv) ? 1 : 0], i, node_blocks(lv));
             add_blocks(t.vec_blk, i, v.nblocks);
         }
         // upload the tables (one device buffer, grown outside the rounds)
@@ -213,7 +213,8 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
         const size_t o_red0 = put(host, t.red0), o_red1 = put(host, t.red1);
         const size_t o_vec = put(host, t.vec);
         for (auto& g : t.groups) g.off = put(host, g.blk);
-        const size_t o_nblk = put(host, t.node_blk), o_vblk = put(host, t.vec_blk);
+        const size_t o_nblk[2] = {put(host, t.node_blk[0]), put(host, t.node_blk[1])};
+        const size_t o_vblk = put(host, t.vec_blk);
         const size_t o_ctl = align_up(host.size(), 256);
         host.resize(o_ctl + np * sizeof(LbCtl));
         if (host.size() > b->dtab_cap) {
@@ -245,11 +246,16 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
             }
         };
         const auto* vec = static_cast<const LbVecArgs*>(P(o_vec));
-        const int nnb = static_cast<int>(t.node_blk.size()), nvb = static_cast<int>(t.vec_blk.size());
+        const int nvb = static_cast<int>(t.vec_blk.size());
+        auto node_stage = [&](size_t o_args) {
+            for (int f = 0; f < 2; ++f)
+                launch_node_pass_batch(static_cast<const NodePassArgs*>(P(o_args)),
+                                       static_cast<const BlockRef*>(P(o_nblk[f])),
+                                       static_cast<int>(t.node_blk[f].size()), f == 1, s);
+        };
         // level start: evaluation at the start point, state reset
         image_stage(o_img0);
-        launch_node_pass_batch(static_cast<const NodePassArgs*>(P(o_node0)),
-                               static_cast<const BlockRef*>(P(o_nblk)), nnb, s);
+        node_stage(o_node0);
         launch_reduce_batch(static_cast<const ReduceArgs*>(P(o_red0)), np, s);
         launch_lb_init_batch(vec, np, s);
         if (hipGetLastError() != hipSuccess) return bfail(b, NGF_E_HIP, "level start launch");
@@ -261,8 +267,7 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
         launch_lb_plan_batch(vec, np, s);
         launch_lb_vec_batch(vec, static_cast<const BlockRef*>(P(o_vblk)), nvb, s);
         image_stage(o_img1);
-        launch_node_pass_batch(static_cast<const NodePassArgs*>(P(o_node1)),
-                               static_cast<const BlockRef*>(P(o_nblk)), nnb, s);
+        node_stage(o_node1);
         launch_reduce_batch(static_cast<const ReduceArgs*>(P(o_red1)), np, s);
         launch_lb_accept_batch(vec, static_cast<const BlockRef*>(P(o_vblk)), nvb, np,
                                b->p.lbfgs_mem, s);

@@ -149,3 +149,28 @@ def _check_fd(name, fd, an, gmax, excluded, total):
          f"({excluded} of {total} entries excluded as kink crossings)")
     assert rel <= 2e-2, rel
     assert worst <= 1.0, worst
+
+
+def test_pair_form_on_a_grid_of_a_million_nodes(gpu_lib):
+    """The differentiation form on a 256 x 256 x 128 image (129 x 129 x 65 =
+    1.08 M nodes, where the node pass runs in its marching form): J and the
+    gradients with respect to y and T against the oracle."""
+    ngf = gpu_lib
+    m = (256, 256, 128)
+    my = (129, 129, 65)
+    pr = synth.ct_phantom_pair(m, seed_R=13, seed_u=14)
+    prob = O.Problem(pr.R, pr.T, H, my, 0.1, 10.0, 10.0)
+    ctx = ngf.Context(alpha=0.1, tau=10.0, rho=10.0, levels=1)
+    j = [np.arange(n, dtype=np.float64) / (n - 1) for n in my]
+    w = (np.sin(2 * np.pi * j[0])[:, None, None] * np.sin(np.pi * j[1])[None, :, None]
+         * np.cos(np.pi * j[2])[None, None, :])
+    y32 = (prob.identity() + 2.0 * np.stack([w, -w, 0.5 * w])).astype(np.float32)
+    J, gy, gT = ctx.eval_pair(_t(pr.R), _t(pr.T), _t(y32), H)
+    Jo, go, gTo, _ = O.eval_J_grad_T(prob, y32.astype(np.float64))
+    gy = gy.cpu().numpy().astype(np.float64)
+    gT = gT.cpu().numpy().astype(np.float64)
+    ey = np.linalg.norm(gy - go) / np.linalg.norm(go)
+    eT = np.linalg.norm(gT - gTo) / np.linalg.norm(gTo)
+    _say(f"[pair 1M] J {J} oracle {Jo}; grad y rel-L2 {ey:.2e}, grad T rel-L2 {eT:.2e}")
+    assert abs(J - Jo) <= 1e-5 * abs(Jo)
+    assert ey <= 1e-4 and eT <= 1e-4
