@@ -287,7 +287,7 @@ def main():
     torch.cuda.synchronize()
     print("[bench] warmup done", file=sys.stderr, flush=True)
 
-    ctx.set_profiling(True)
+    ctx.set_profiling(True, level=0)  # events only where the roofline is taken
     evals = 0
     reports = []
     torch.cuda.synchronize()

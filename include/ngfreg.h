@@ -280,14 +280,16 @@ ngf_status ngf_apply_PT(ngf_ctx* ctx, int32_t level, const float* z, float* out,
 
 /* Profiling aid: when enabled, the library records HIP events around every
  * launch of the fused image-grid kernel (the dominant kernel of an
- * evaluation) on the context's stream.  ngf_kernel_time returns, for the
+ * evaluation) on the context's stream, on pyramid level `level` only (-1:
+ * every launch; each record adds two event markers to the stream, a few
+ * microseconds of device time).  ngf_kernel_time returns, for the
  * recorded launches on pyramid level `level` (-1: all launches), their
  * number, their summed duration in milliseconds, and the image voxels and
  * deformation nodes they covered; it then clears the whole record and
  * synchronises.  At most 4096 launches are recorded (later ones are not);
  * evaluation rounds enqueued after a device-driven level has ended are not
  * counted.  Any output pointer may be NULL. */
-ngf_status ngf_set_profiling(ngf_ctx* ctx, int32_t enable);
+ngf_status ngf_set_profiling(ngf_ctx* ctx, int32_t enable, int32_t level);
 ngf_status ngf_kernel_time(ngf_ctx* ctx, int32_t level, int32_t* launches, double* total_ms,
                            int64_t* voxels, int64_t* nodes);
 

@@ -338,13 +338,14 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
             launch_image_march(e.a, c->p.ratio, march_tz(L.variant), march_cx(L.variant),
                                c->stream);
     };
-    if (c->prof && c->nprof < kProfMax) {
+    int li = -1;
+    if (c->prof)
+        for (size_t l = 0; l < c->lv.size(); ++l)
+            if (&c->lv[l] == &L) li = static_cast<int>(l);
+    if (c->prof && c->nprof < kProfMax && (c->prof_only < 0 || li == c->prof_only)) {
         HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof], c->stream));
         launch();
         HIPCHK(c, hipEventRecord(c->ev[2 * c->nprof + 1], c->stream));
-        int li = -1;
-        for (size_t l = 0; l < c->lv.size(); ++l)
-            if (&c->lv[l] == &L) li = static_cast<int>(l);
         c->prof_level[c->nprof] = li;
         c->nprof++;
     } else {
@@ -1017,8 +1018,9 @@ ngf_status ngf_apply_PT(ngf_ctx* c, int32_t level, const float* z, float* out, i
     return NGF_OK;
 }
 
-ngf_status ngf_set_profiling(ngf_ctx* c, int32_t enable) {
+ngf_status ngf_set_profiling(ngf_ctx* c, int32_t enable, int32_t level) {
     if (!c) return NGF_E_ARG;
+    c->prof_only = level < 0 ? -1 : level;
     if (enable && c->ev.empty()) {
         c->ev.resize(2 * kProfMax, nullptr);
         for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));

@@ -97,6 +97,7 @@ struct ngf_ctx {
     std::vector<hipEvent_t> ev;
     int nprof = 0;                 // records in use (events 2i, 2i + 1)
     std::vector<int> prof_level;   // pyramid level of each record (-1: explicit pair)
+    int prof_only = -1;            // record this pyramid level only (-1: every launch)
 };
 
 

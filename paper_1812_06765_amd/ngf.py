@@ -85,7 +85,7 @@ def load():
         "ngf_register_levels": ([_P, _P, ctypes.POINTER(Report)], i32),
         "ngf_eval_pair": ([_P, ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_int32 * 3), _P, _P,
                            _P, _P, ctypes.POINTER(f64), _P, _P, _P], i32),
-        "ngf_set_profiling": ([_P, i32], i32),
+        "ngf_set_profiling": ([_P, i32, i32], i32),
         "ngf_set_kernel": ([_P, i32], i32),
         "ngf_set_driver": ([_P, i32], i32),
         "ngf_apply_P": ([_P, i32, _P, _P], i32),
@@ -375,8 +375,9 @@ class Context:
         return v.value
 
     # -- profiling -----------------------------------------------------------
-    def set_profiling(self, enable=True):
-        self._chk(self.lib.ngf_set_profiling(self.h, int(bool(enable))))
+    def set_profiling(self, enable=True, level=-1):
+        """HIP-event timing of the image-pass launches on ``level`` (-1: all)."""
+        self._chk(self.lib.ngf_set_profiling(self.h, int(bool(enable)), int(level)))
 
     def kernel_time(self, level=-1):
         """(launches, total ms, voxels, nodes) of the recorded image-pass
