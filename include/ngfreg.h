@@ -145,7 +145,7 @@ ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
                              const ngf_grid* g, int32_t host_ptrs);
 
 /* Image-grid kernel of the evaluation.  `variant`: -2 = by level size (no
- * timing runs: at least 8 Mi voxels -> 10, at least 1 Mi -> 4, else 8);
+ * timing runs: at least 1 Mi voxels -> 11, else 8);
  * -1 = autotune (default:
  * at ngf_build_pyramid every level times each variant over three evaluations
  * at the identity and keeps the fastest; choices are cached per image shape
@@ -153,9 +153,14 @@ ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
  * file, appended to and read from that file); 0 = 3D tiles of 8x8x32 voxels
  * with a two-voxel halo; 1, 2, 3 = x-marching over 16x64 (y, z) tiles in
  * chunks of 8, 20 or 32 planes; 4, 5, 6 = the same over 16x32 tiles; 7 = 3D
- * tiles of 4x8x32 voxels; 8 = 3D tiles of 4x4x16 voxels.  All variants compute the same quantities;
- * only the summation order of the P^T partial sums differs.  Applies at once
- * to a built pyramid.  ngf_get_kernel reports a level's choice. */
+ * tiles of 4x8x32 voxels; 8 = 3D tiles of 4x4x16 voxels; 9, 10 = x-marching
+ * over 16x64 or 16x32 tiles in chunks of 16 planes; 11, 12 = x-marching over
+ * 16x32 or 16x64 tiles in chunks whose length is fitted to the level's shape
+ * and to the number of workgroups the device holds at once (so that the
+ * launch fills the device in as few full rounds as possible).  All variants
+ * compute the same quantities; only the summation order of the P^T partial
+ * sums differs.  Applies at once to a built pyramid.  ngf_get_kernel reports
+ * a level's choice. */
 ngf_status ngf_set_kernel(ngf_ctx* ctx, int32_t variant);
 ngf_status ngf_get_kernel(const ngf_ctx* ctx, int32_t level, int32_t* variant);
 

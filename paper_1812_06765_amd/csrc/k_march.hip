@@ -24,6 +24,7 @@
 
 #include <math.h>
 
+#include <atomic>
 #include <type_traits>
 
 namespace ngf {
@@ -116,6 +117,9 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
     const int qly = max(y0 - 2, 0) / R, qlz = max(z0 - 2, 0) / R;
     const int jx_first = x0 / R;
     const int xend = min(x0 + CX, mx);  // first plane past the chunk (in the domain)
+    // steps: the chunk's planes plus two lead-in and two lead-out planes; a
+    // chunk cut short by the domain stops after its last plane
+    const int nstep = xend - x0 + 4;
 
     // x-interpolated node plane for image plane p (clamped), float64, into sQ.
     // The node values are loaded into registers one phase ahead of the store
@@ -269,7 +273,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         const bool vok = pv >= max(x0 - 1, 0) && pv <= min(x0 + CX, mx - 1);
         // prefetch for the next phases: node values of the next x-interpolated
         // plane, and the x neighbours of R at this thread's V positions
-        if (k + 1 < CX + 4) load_q(pw + 1);
+        if (k + 1 < nstep) load_q(pw + 1);
         float rxm[L::KP + 1], rxp[L::KP + 1];
         if (vok) {
             const float* Rm = a.R + max(pv - 1, 0) * sxT;
@@ -375,7 +379,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         }
         if (!GRAD) {
             __syncthreads();
-            if (k + 1 < CX + 4) store_q(pw + 1);
+            if (k + 1 < nstep) store_q(pw + 1);
             __syncthreads();
             return;
         }
@@ -465,7 +469,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
                 }
             }
         }
-        if (k + 1 < CX + 4) store_q(pw + 1);  // sG is no longer read: Q may overwrite it
+        if (k + 1 < nstep) store_q(pw + 1);  // sG is no longer read: Q may overwrite it
 #pragma unroll
         for (int kk = 0; kk < L::KP; ++kk)
 #pragma unroll
@@ -476,7 +480,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         __syncthreads();
     };
 
-    for (int k = 0; k < CX + 4; ++k) step(k);
+    for (int k = 0; k < nstep; ++k) step(k);
     if (GRAD) {
         flush(jA, acc0);
         flush(jA + 1, acc1);
@@ -502,27 +506,28 @@ __global__ __launch_bounds__(kThreads, TZ == 32 ? 3 : 2) void k_image_march(Imag
     march_body<TY, TZ, R, GRAD, POW2>(a, CX, blockIdx.x);
 }
 
+// each pair's chunk length is its own (a.cx)
 template <int TY, int TZ, int R, bool POW2>
 __global__ __launch_bounds__(kThreads, TZ == 32 ? 3 : 2) void k_image_march_batch(
-    const ImagePassArgs* args, const BlockRef* blk, int CX) {
+    const ImagePassArgs* args, const BlockRef* blk) {
     const BlockRef e = blk[blockIdx.x];
     if (e.pair < 0) return;
     const ImagePassArgs& a = args[e.pair];
     if (a.gate && *a.gate == kOpNone) return;
-    march_body<TY, TZ, R, true, POW2>(a, CX, e.block);
+    march_body<TY, TZ, R, true, POW2>(a, a.cx, e.block);
 }
 
 template <int TY, int TZ, int R>
-void launch_march_batch_t(const ImagePassArgs* args, const BlockRef* blk, int nblk, int cx,
-                          bool pow2, hipStream_t s) {
+void launch_march_batch_t(const ImagePassArgs* args, const BlockRef* blk, int nblk, bool pow2,
+                          hipStream_t s) {
     using L = March<TY, TZ, R>;
     const size_t lds = sizeof(float) * L::LDS_FLOATS;
     if (pow2)
         hipLaunchKernelGGL((k_image_march_batch<TY, TZ, R, true>), dim3(nblk), dim3(kThreads),
-                           lds, s, args, blk, cx);
+                           lds, s, args, blk);
     else
         hipLaunchKernelGGL((k_image_march_batch<TY, TZ, R, false>), dim3(nblk), dim3(kThreads),
-                           lds, s, args, blk, cx);
+                           lds, s, args, blk);
 }
 
 template <int TY, int TZ, int R>
@@ -554,18 +559,46 @@ void launch_march_t(const ImagePassArgs& a, int cx, hipStream_t s) {
 void launch_image_march_batch(const ImagePassArgs* args, const BlockRef* blk, int nblk,
                               int ratio, int variant, bool pow2, hipStream_t s) {
     if (nblk <= 0) return;
-    const int tz = march_tz(variant), cx = march_cx(variant);
-    if (tz == 64) {
+    if (march_tz(variant) == 64) {
         if (ratio == 2)
-            launch_march_batch_t<kMY, 64, 2>(args, blk, nblk, cx, pow2, s);
+            launch_march_batch_t<kMY, 64, 2>(args, blk, nblk, pow2, s);
         else if (ratio == 4)
-            launch_march_batch_t<kMY, 64, 4>(args, blk, nblk, cx, pow2, s);
+            launch_march_batch_t<kMY, 64, 4>(args, blk, nblk, pow2, s);
     } else {
         if (ratio == 2)
-            launch_march_batch_t<kMY, 32, 2>(args, blk, nblk, cx, pow2, s);
+            launch_march_batch_t<kMY, 32, 2>(args, blk, nblk, pow2, s);
         else if (ratio == 4)
-            launch_march_batch_t<kMY, 32, 4>(args, blk, nblk, cx, pow2, s);
+            launch_march_batch_t<kMY, 32, 4>(args, blk, nblk, pow2, s);
     }
+}
+
+int image_march_slots(int tz) {
+    // occupancy per CU, queried once per device and tile (the ratio-2
+    // instance stands for both ratios: same launch bounds, same LDS)
+    static std::atomic<int> cache[16][2];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+    std::atomic<int>& slot = cache[dev & 15][tz == 64 ? 1 : 0];
+    int v = slot.load();
+    if (v > 0) return v;
+    int per_cu = 0, cus = 0;
+    hipError_t e;
+    if (tz == 64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, k_image_march<kMY, 64, 2, true, true>, kThreads,
+            sizeof(float) * March<kMY, 64, 2>::LDS_FLOATS);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, k_image_march<kMY, 32, 2, true, true>, kThreads,
+            sizeof(float) * March<kMY, 32, 2>::LDS_FLOATS);
+    if (e != hipSuccess || per_cu < 1) per_cu = tz == 64 ? 2 : 3;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    (void)hipGetLastError();
+    v = per_cu * cus;
+    slot.store(v);
+    return v;
 }
 
 void launch_image_march(const ImagePassArgs& a, int ratio, int tz, int cx, hipStream_t s) {

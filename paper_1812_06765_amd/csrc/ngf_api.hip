@@ -72,9 +72,10 @@ Geo geometry(const Level& L, int variant) {
         g.ty = tile3d_y(variant);
         g.tz = tile3d_z(variant);
     } else {
-        g.tx = march_cx(variant);
         g.ty = kMY;
         g.tz = march_tz(variant);
+        g.tx = march_cx(variant);
+        if (g.tx == 0) g.tx = fit_chunk(L.m, g.tz, image_march_slots(g.tz));
     }
     g.ntx = tiles(L.m[0], g.tx);
     g.nty = tiles(L.m[1], g.ty);
@@ -248,6 +249,7 @@ ImagePassArgs image_args(ngf_ctx* c, const Level& L, const float* R, const float
     a.ntx = g.ntx;
     a.nty = g.nty;
     a.ntz = g.ntz;
+    a.cx = g.tx;
     a.hx = L.h[0];
     a.hy = L.h[1];
     a.hz = L.h[2];
@@ -335,8 +337,7 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
         if (!is_march(L.variant))
             launch_image_pass(e.a, c->p.ratio, L.variant, c->stream);
         else
-            launch_image_march(e.a, c->p.ratio, march_tz(L.variant), march_cx(L.variant),
-                               c->stream);
+            launch_image_march(e.a, c->p.ratio, march_tz(L.variant), e.a.cx, c->stream);
     };
     int li = -1;
     if (c->prof)
@@ -402,9 +403,7 @@ void tune_cache_store(const std::string& key, int v) {
 // work): the choices the timed selection makes on gfx950 at cubic levels of
 // 256^3 and 128^3, and of 64^3 and below.
 int variant_by_size(const Level& L) {
-    const int64_t n = L.N();
-    if (n >= (int64_t{8} << 20)) return kMarch32x16;
-    return n >= (int64_t{1} << 20) ? kMarch32x8 : kTile3DTiny;
+    return L.N() >= (int64_t{1} << 20) ? kMarch32Fit : kTile3DTiny;
 }
 
 // Pick the image-pass variant of every level: forced, cached for this shape,

@@ -30,7 +30,8 @@ constexpr int64_t kNodeMarchMin = int64_t{1} << 20;
 
 // Image-pass variants the autotuner chooses from: the 3D-tile kernel at three
 // tile sizes, and the marching kernel with in-plane tile 16 x 64 or 16 x 32
-// and x chunks of 8, 16, 20 or 32 planes.
+// and x chunks of 8, 16, 20 or 32 planes, or of a length fitted to the level
+// and the device (the "fit" variants: see fit_chunk).
 enum Variant {
     kTile3D = 0,
     kMarch64x8 = 1, kMarch64x20 = 2, kMarch64x32 = 3,
@@ -38,22 +39,48 @@ enum Variant {
     kTile3DSmall = 7,  // 3D tile of 4 x 8 x 32 voxels (coarse levels)
     kTile3DTiny = 8,   // 3D tile of 4 x 4 x 16 voxels (many workgroups for small levels)
     kMarch64x16 = 9, kMarch32x16 = 10,
-    kNumVariants = 11
+    kMarch32Fit = 11, kMarch64Fit = 12,
+    kNumVariants = 13
 };
 constexpr int kVariantBySize = -2;  // selection rule instead of timed selection
 inline bool is_march(int v) {
-    return (v >= kMarch64x8 && v <= kMarch32x32) || v == kMarch64x16 || v == kMarch32x16;
+    return (v >= kMarch64x8 && v <= kMarch32x32) || (v >= kMarch64x16 && v <= kMarch64Fit);
 }
 // 3D-tile extents (x, y, z) of the 3D-tile variants
 inline int tile3d_x(int v) { return v == kTile3D ? 8 : 4; }
 inline int tile3d_y(int v) { return v == kTile3DTiny ? 4 : 8; }
 inline int tile3d_z(int v) { return v == kTile3DTiny ? 16 : 32; }
 inline bool is_tile3d(int v) { return v == kTile3D || v == kTile3DSmall || v == kTile3DTiny; }
+// fixed x chunk of a marching variant; 0 for the fit variants
 inline int march_cx(int v) {
+    if (v >= kMarch32Fit) return 0;
     if (v >= kMarch64x16) return 16;
     return (v - 1) % 3 == 0 ? 8 : ((v - 1) % 3 == 1 ? 20 : 32);
 }
-inline int march_tz(int v) { return (v <= kMarch64x32 || v == kMarch64x16) ? 64 : 32; }
+inline int march_tz(int v) {
+    return (v <= kMarch64x32 || v == kMarch64x16 || v == kMarch64Fit) ? 64 : 32;
+}
+// Workgroups of the marching kernel with (y, z) tile kMY x tz that the
+// current device holds at once (occupancy per CU times the CU count).
+int image_march_slots(int tz);
+// x chunk of a fit variant for an image of m cells: the multiple of 4 (so of
+// either ratio) that minimises the launch's predicted duration, taken as the
+// number of full rounds of workgroups over the resident slots times the
+// planes a workgroup walks (its chunk plus the four lead-in and lead-out
+// steps).  A chunk that fills the slots once beats a shorter one that needs
+// a partly empty last round.
+inline int fit_chunk(const int m[3], int tz, int slots) {
+    const int64_t nyz = static_cast<int64_t>((m[1] + kMY - 1) / kMY) * ((m[2] + tz - 1) / tz);
+    const int top = ((m[0] + 3) / 4) * 4;
+    int best = 8;
+    int64_t best_cost = -1;
+    for (int cx = 8; cx <= (top > 8 ? top : 8); cx += 4) {
+        const int64_t n = nyz * ((m[0] + cx - 1) / cx);
+        const int64_t cost = ((n + slots - 1) / slots) * (cx + 4);
+        if (best_cost < 0 || cost < best_cost) best = cx, best_cost = cost;
+    }
+    return best;
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumbering gives each XCD a contiguous range of tiles, so that
@@ -91,6 +118,7 @@ struct ImagePassArgs {
     int mx, my, mz;        // image cells
     int nx, ny, nz;        // deformation nodes
     int ntx, nty, ntz;     // tiles per axis
+    int cx;                // x chunk of the marching form (image planes)
     double hx, hy, hz;     // spacing (float64: continuous index of the warp)
     double ihx, ihy, ihz;  // 1 / h, used only when every h is a power of two
     int pow2h;             // 1: every spacing is a power of two (exact reciprocal)
