@@ -22,6 +22,8 @@
 // * reduce: fixed-order float64 sums of the block partials of D and S.
 #include "ngf_internal.h"
 
+#include <atomic>
+
 #include <math.h>
 
 namespace ngf {
@@ -450,14 +452,14 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
 }
 
 // Node pass, marching form: one workgroup per (component, NY x NZ node tile
-// in (y, z), chunk of NX node planes along x); thread t owns the in-plane node
+// in (y, z), chunk of a.cxn node planes along x); thread t owns the in-plane node
 // (t / NZ, t % NZ) of every plane of the chunk.  u = y - X is kept in three
 // rolling LDS planes with a two-node in-plane halo, A u in three rolling
 // planes with a one-node halo.  Ghost nodes replicate the boundary node
 // (for u and for A u): in-plane through clamped loads and zero offsets, across
 // planes by reading the boundary plane's slot.  Step k loads u of plane
 // x0 - 2 + k, forms A u of plane x0 - 3 + k and A(A u) of plane x0 - 4 + k.
-template <int NX, int NY, int NZ>
+template <int NY, int NZ>
 __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block) {
     static_assert(NY * NZ == kThreads, "one node per thread and plane");
     constexpr int UY = NY + 4, UZ = NZ + 4, NU = UY * UZ;  // u plane, halo 2
@@ -474,10 +476,11 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
     const int bz = blk % a.nbz;
     const int byy = (blk / a.nbz) % a.nby;
     const int bx = blk / (a.nbz * a.nby);
-    const int x0 = bx * NX, y0 = byy * NY, z0 = bz * NZ;
+    const int x0 = bx * a.cxn, y0 = byy * NY, z0 = bz * NZ;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int nn = nx * ny * nz;
-    const int xend = min(x0 + NX, nx);
+    const int xend = min(x0 + a.cxn, nx);
+    const int nstep = xend - x0 + 4;  // a chunk cut short by the grid stops after its last plane
     const int PX = a.bx + 1, PY = a.by + 1, PZ = a.bz + 1;
     const int NP = PX * PY * PZ;
     const float sc = (!a.gather && a.gscale != nullptr) ? static_cast<float>(*a.gscale) : 1.0f;
@@ -517,7 +520,7 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
     const int noy = (ry == 0 && tyh > 0) ? 2 : 1, noz = (rz == 0 && tzh > 0) ? 2 : 1;
 
     double ssum = 0.0, gmax = 0.0, g2 = 0.0;
-    for (int k = 0; k < NX + 4; ++k) {
+    for (int k = 0; k < nstep; ++k) {
         // u of plane pu (planes outside the grid are never read)
         const int pu = x0 - 2 + k;
         if (pu >= 0 && pu < nx) {
@@ -741,7 +744,7 @@ __device__ __forceinline__ void node_tile_body(const NodePassArgs& a, int block)
 template <bool MARCH>
 __device__ __forceinline__ void node_body(const NodePassArgs& a, int block) {
     if (MARCH)
-        node_march_body<kNMX, kNMY, kNMZ>(a, block);
+        node_march_body<kNMY, kNMZ>(a, block);
     else
         node_tile_body<kNTX, kNTY, kNTZ>(a, block);
 }
@@ -877,6 +880,27 @@ void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s) 
         launch_image_ratio_atomic<2>(a, s);
     else if (ratio == 4)
         launch_image_ratio_atomic<4>(a, s);
+}
+
+int node_march_slots() {
+    static std::atomic<int> cache[16];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+    std::atomic<int>& slot = cache[dev & 15];
+    int v = slot.load();
+    if (v > 0) return v;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_node_pass<true>, kThreads, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 8;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    (void)hipGetLastError();
+    v = per_cu * cus;
+    slot.store(v);
+    return v;
 }
 
 void launch_node_pass(const NodePassArgs& a, bool march, hipStream_t s) {

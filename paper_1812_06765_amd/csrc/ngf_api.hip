@@ -75,7 +75,9 @@ Geo geometry(const Level& L, int variant) {
         g.ty = kMY;
         g.tz = march_tz(variant);
         g.tx = march_cx(variant);
-        if (g.tx == 0) g.tx = fit_chunk(L.m, g.tz, image_march_slots(g.tz));
+        if (g.tx == 0)
+            g.tx = fit_chunk(L.m[0], int64_t{tiles(L.m[1], g.ty)} * tiles(L.m[2], g.tz), 4, 8,
+                             image_march_slots(g.tz));
     }
     g.ntx = tiles(L.m[0], g.tx);
     g.nty = tiles(L.m[1], g.ty);
@@ -95,9 +97,13 @@ bool pow2(double h) {
 // node-pass workgroups: one per node tile and component
 bool node_march(const Level& L) { return L.Ny() >= kNodeMarchMin; }
 // node-pass workgroups per axis of the form the level uses
+int node_chunk(const Level& L) {
+    return fit_chunk(L.my[0], 3 * int64_t{tiles(L.my[1], kNMY)} * tiles(L.my[2], kNMZ), 1, 4,
+                     node_march_slots());
+}
 void node_grid(const Level& L, int nb[3]) {
     const bool m = node_march(L);
-    nb[0] = tiles(L.my[0], m ? kNMX : kNTX);
+    nb[0] = tiles(L.my[0], m ? node_chunk(L) : kNTX);
     nb[1] = tiles(L.my[1], m ? kNMY : kNTY);
     nb[2] = tiles(L.my[2], m ? kNMZ : kNTZ);
 }
@@ -298,6 +304,7 @@ EvalArgs eval_args(ngf_ctx* c, const Level& L, const float* R, const float* T, c
     b.nbx = nb[0];
     b.nby = nb[1];
     b.nbz = nb[2];
+    b.cxn = node_march(L) ? node_chunk(L) : kNTX;
     b.hyx = L.hy[0];
     b.hyy = L.hy[1];
     b.hyz = L.hy[2];
@@ -1124,6 +1131,7 @@ ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], con
     b.nbx = nb[0];
     b.nby = nb[1];
     b.nbz = nb[2];
+    b.cxn = node_march(P) ? node_chunk(P) : kNTX;
     b.hyx = P.hy[0];
     b.hyy = P.hy[1];
     b.hyz = P.hy[2];

@@ -21,10 +21,10 @@ constexpr int kTX = 8, kTY = 8, kTZ = 32;
 // Marching image pass: (y, z) tile of kMY x (32 or 64); the x chunk is a
 // run-time choice.
 constexpr int kMY = 16;
-// Node pass: marching form (x chunk of kNMX node planes, (y, z) tile of
-// kNMY x kNMZ nodes) from kNodeMarchMin nodes on, 3D-tile form (kNTX x kNTY x
-// kNTZ nodes) below.
-constexpr int kNMX = 16, kNMY = 8, kNMZ = 32;
+// Node pass: marching form ((y, z) tile of kNMY x kNMZ nodes, x chunk fitted
+// to the grid and the device) from kNodeMarchMin nodes on, 3D-tile form
+// (kNTX x kNTY x kNTZ nodes) below.
+constexpr int kNMY = 8, kNMZ = 32;
 constexpr int kNTX = 4, kNTY = 8, kNTZ = 32;
 constexpr int64_t kNodeMarchMin = int64_t{1} << 20;
 
@@ -63,24 +63,26 @@ inline int march_tz(int v) {
 // Workgroups of the marching kernel with (y, z) tile kMY x tz that the
 // current device holds at once (occupancy per CU times the CU count).
 int image_march_slots(int tz);
-// x chunk of a fit variant for an image of m cells: the multiple of 4 (so of
-// either ratio) that minimises the launch's predicted duration, taken as the
-// number of full rounds of workgroups over the resident slots times the
-// planes a workgroup walks (its chunk plus the four lead-in and lead-out
-// steps).  A chunk that fills the slots once beats a shorter one that needs
-// a partly empty last round.
-inline int fit_chunk(const int m[3], int tz, int slots) {
-    const int64_t nyz = static_cast<int64_t>((m[1] + kMY - 1) / kMY) * ((m[2] + tz - 1) / tz);
-    const int top = ((m[0] + 3) / 4) * 4;
-    int best = 8;
+// Chunk length along x for a launch of `across` x-columns of workgroups over
+// an axis of `len` planes: the multiple of `step` (at least `lo`) that
+// minimises the launch's predicted duration, taken as the number of full
+// rounds of workgroups over the `slots` the device holds at once times the
+// planes a workgroup walks (its chunk plus four lead-in and lead-out steps).
+// A chunk that fills the slots once beats a shorter one that needs a partly
+// empty last round.
+inline int fit_chunk(int len, int64_t across, int step, int lo, int slots) {
+    const int top = ((len + step - 1) / step) * step;
+    int best = lo;
     int64_t best_cost = -1;
-    for (int cx = 8; cx <= (top > 8 ? top : 8); cx += 4) {
-        const int64_t n = nyz * ((m[0] + cx - 1) / cx);
+    for (int cx = lo; cx <= (top > lo ? top : lo); cx += step) {
+        const int64_t n = across * ((len + cx - 1) / cx);
         const int64_t cost = ((n + slots - 1) / slots) * (cx + 4);
         if (best_cost < 0 || cost < best_cost) best = cx, best_cost = cost;
     }
     return best;
 }
+// Workgroups of the marching node pass the current device holds at once.
+int node_march_slots();
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumbering gives each XCD a contiguous range of tiles, so that
@@ -144,6 +146,7 @@ struct NodePassArgs {
     int ntx, nty, ntz;     // image-pass tiles per axis
     int bx, by, bz;        // node cells per image tile per axis
     int nbx, nby, nbz;     // node-pass blocks per axis
+    int cxn;               // x chunk of the marching form (node planes)
     double hyx, hyy, hyz;  // node spacing (float64, for X = j h^y)
     float ihy2x, ihy2y, ihy2z;  // 1 / (h^y)^2
     float alpha_hbary;     // alpha * hbar^y
