@@ -518,6 +518,20 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
     const int tyh = div_small(gy, a.by, iby), tzh = div_small(gz, a.bz, ibz);
     const int ry = gy - tyh * a.by, rz = gz - tzh * a.bz;
     const int noy = (ry == 0 && tyh > 0) ? 2 : 1, noz = (rz == 0 && tzh > 0) ? 2 : 1;
+    // the (y, z) part of the node's place in each image tile that holds it
+    // (j = 2 oy + oz, the tile oy rows and oz columns back), fixed over the
+    // chunk; the x part is the same for the whole workgroup.  The part array
+    // of one x-slab of tiles is below 2^31 floats (checked by the host).
+    int yzoff[4];
+    bool yzok[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int oy = j >> 1, oz = j & 1;
+        const int tty = tyh - oy, ttz = tzh - oz;
+        yzok[j] = own && oy < noy && oz < noz && tty < a.nty && ttz < a.ntz;
+        yzoff[j] = ((tty * a.ntz + ttz) * 3 + c) * NP + (ry + oy * a.by) * PZ + (rz + oz * a.bz);
+    }
+    const int64_t xslab = static_cast<int64_t>(a.nty) * a.ntz * 3 * NP;
 
     double ssum = 0.0, gmax = 0.0, g2 = 0.0;
     for (int k = 0; k < nstep; ++k) {
@@ -571,24 +585,18 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
                 if (!a.gather) {
                     gd = a.grad[c * nn + (po * ny + gy) * nz + gz];
                 } else {
-                    // Eq. 3 completed: the (at most 8) image-tile partials of the node
+                    // Eq. 3 completed: the (at most 8) image-tile partials of the
+                    // node, in the order (ox, oy, oz)
                     const int txh = div_small(po, a.bx, ibx);
                     const int rx = po - txh * a.bx;
                     const int nox = (rx == 0 && txh > 0) ? 2 : 1;
                     for (int ox = 0; ox < nox; ++ox) {
-                        const int ttx = txh - ox, llx = rx + ox * a.bx;
+                        const int ttx = txh - ox;
                         if (ttx >= a.ntx) continue;
-                        for (int oy = 0; oy < noy; ++oy) {
-                            const int tty = tyh - oy, lly = ry + oy * a.by;
-                            if (tty >= a.nty) continue;
-                            for (int oz = 0; oz < noz; ++oz) {
-                                const int ttz = tzh - oz, llz = rz + oz * a.bz;
-                                if (ttz >= a.ntz) continue;
-                                const int tile = (ttx * a.nty + tty) * a.ntz + ttz;
-                                gd += a.part[(static_cast<int64_t>(tile) * 3 + c) * NP +
-                                             (llx * PY + lly) * PZ + llz];
-                            }
-                        }
+                        const float* px = a.part + ttx * xslab + (rx + ox * a.bx) * (PY * PZ);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (yzok[j]) gd += px[yzoff[j]];
                     }
                 }
                 const float lxx = Ap[q] - 2.0f * au + Am[q];

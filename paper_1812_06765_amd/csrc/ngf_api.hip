@@ -117,7 +117,13 @@ ngf_status ensure_scratch(ngf_ctx* c, const Level& L) {
     size_t pf = 0, nt = 0;
     for (int v = 0; v < kNumVariants; ++v) {
         pf = std::max(pf, static_cast<size_t>(part_floats(L, c->p.ratio, v)));
-        nt = std::max(nt, static_cast<size_t>(geometry(L, v).ntiles()));
+        const Geo g = geometry(L, v);
+        nt = std::max(nt, static_cast<size_t>(g.ntiles()));
+        // the node pass addresses one x-slab of tile partials with 32-bit offsets
+        const int64_t slab = int64_t{g.nty} * g.ntz * 3 * (g.tx / c->p.ratio + 1) *
+                             (g.ty / c->p.ratio + 1) * (g.tz / c->p.ratio + 1);
+        if (slab >= (int64_t{1} << 31))
+            return fail(c, NGF_E_SHAPE, "image too large in y and z for the tile layout");
     }
     const size_t nb = static_cast<size_t>(node_blocks(L));
     if (pf > c->part_cap || nt > c->dpart_cap || nb > c->nblk_cap)
@@ -663,7 +669,7 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
             return e;
         }
     }
-    if (ensure_scratch(c, c->lv[0]) != NGF_OK) return NGF_E_OOM;
+    if (const ngf_status st = ensure_scratch(c, c->lv[0]); st != NGF_OK) return st;
     if (ensure_lbfgs(c, static_cast<size_t>(3 * c->lv[0].Ny())) != NGF_OK) return NGF_E_OOM;
 
     // R on side stream 0, T on side stream 1, each: copy level 0, then the
@@ -1104,7 +1110,7 @@ ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], con
         HIPCHK(c, hipGetLastError());
     }
     P.variant = kTile3D;  // the scatter form lives in the 3D-tile kernel
-    if (ensure_scratch(c, P) != NGF_OK) return NGF_E_OOM;
+    if (const ngf_status st = ensure_scratch(c, P); st != NGF_OK) return st;
     const bool want = grad_y != nullptr || grad_T != nullptr;
     if (grad_y) launch_fill(grad_y, 3 * P.Ny(), 0.0f, c->stream);
     if (grad_T) launch_fill(grad_T, P.N(), 0.0f, c->stream);
