@@ -91,12 +91,10 @@ __global__ __launch_bounds__(kThreads) void k_lb_accept_dots(const LbState* st,
                                     gridDim.x);
 }
 
-__global__ __launch_bounds__(kGramThreads) void k_lb_accept_gram(LbState* st,
-                                                                 const double* dotpart,
-                                                                 int nblocks,
-                                                                 const double* jds) {
-    if (st->ctl.phase != kPhAccepted) return;
-    lb_accept_gram_body(st, dotpart, nblocks, jds);
+__global__ __launch_bounds__(kGramThreads) void k_lb_gram_plan(LbState* st,
+                                                               const double* dotpart,
+                                                               int nblocks, double* jds) {
+    lb_gram_plan_body(st, dotpart, nblocks, jds);
 }
 
 // ---- batched forms: one launch over many pairs (see BlockRef) ------------
@@ -131,10 +129,9 @@ __global__ __launch_bounds__(kThreads) void k_lb_accept_dots_batch(const LbVecAr
                                     e.block, a.nblocks);
 }
 
-__global__ __launch_bounds__(kGramThreads) void k_lb_accept_gram_batch(const LbVecArgs* args) {
+__global__ __launch_bounds__(kGramThreads) void k_lb_gram_plan_batch(const LbVecArgs* args) {
     const LbVecArgs& a = args[blockIdx.x];
-    if (a.st->ctl.phase != kPhAccepted) return;
-    lb_accept_gram_body(a.st, a.dotpart, a.nblocks, a.jds);
+    lb_gram_plan_body(a.st, a.dotpart, a.nblocks, a.jds);
 }
 
 __global__ void k_ctl_gather(const LbVecArgs* args, LbCtl* out, int npairs) {
@@ -156,14 +153,14 @@ void launch_lb_vec(LbState* st, const float* hist, int64_t ld, int64_t n, const 
 
 void launch_lb_accept(LbState* st, float* hist, int64_t ld, int64_t n, float* y,
                       const float* yt, float* g, const float* gt, double* dotpart,
-                      int nblocks, const double* jds, int mem, hipStream_t s) {
+                      int nblocks, double* jds, int mem, hipStream_t s) {
     if (mem <= 5)
         hipLaunchKernelGGL(k_lb_accept_dots<5>, dim3(nblocks), dim3(kThreads), 0, s, st, hist,
                            ld, n, y, yt, g, gt, dotpart);
     else
         hipLaunchKernelGGL(k_lb_accept_dots<kMaxMem>, dim3(nblocks), dim3(kThreads), 0, s, st,
                            hist, ld, n, y, yt, g, gt, dotpart);
-    hipLaunchKernelGGL(k_lb_accept_gram, dim3(1), dim3(kGramThreads), 0, s, st, dotpart,
+    hipLaunchKernelGGL(k_lb_gram_plan, dim3(1), dim3(kGramThreads), 0, s, st, dotpart,
                        nblocks, jds);
 }
 
@@ -190,7 +187,7 @@ void launch_lb_accept_batch(const LbVecArgs* args, const BlockRef* blk, int nblk
             hipLaunchKernelGGL(k_lb_accept_dots_batch<kMaxMem>, dim3(nblk), dim3(kThreads), 0, s,
                                args, blk);
     }
-    hipLaunchKernelGGL(k_lb_accept_gram_batch, dim3(npairs), dim3(kGramThreads), 0, s, args);
+    hipLaunchKernelGGL(k_lb_gram_plan_batch, dim3(npairs), dim3(kGramThreads), 0, s, args);
 }
 
 void launch_ctl_gather(const LbVecArgs* args, LbCtl* out, int npairs, hipStream_t s) {

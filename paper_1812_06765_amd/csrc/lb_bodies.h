@@ -371,6 +371,8 @@ constexpr int kGramThreads = 1024;
 
 constexpr int kGramPhases = kGramThreads / 64;
 
+__device__ __forceinline__ void lb_gram_one(LbState* st, const double* dots, const double* jds);
+
 __device__ __forceinline__ void lb_gram_body(LbState* st,
                                                                  const double* dotpart,
                                                                  int nblocks,
@@ -396,7 +398,12 @@ __device__ __forceinline__ void lb_gram_body(LbState* st,
         dots[threadIdx.x] = s;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x == 0) lb_gram_one(st, dots, jds);
+}
+
+// The Gram update itself (one lane): curvature test of the new pair, ring
+// update, new entries of G.
+__device__ __forceinline__ void lb_gram_one(LbState* st, const double* dots, const double* jds) {
     double* G = st->G;
     const int count = st->count;
     const int fs = st->free_slot;
@@ -509,19 +516,35 @@ __device__ __forceinline__ void lb_accept_gram_body(LbState* st, const double* d
                                                     int nblocks, const double* jds) {
 #pragma clang fp contract(off)
     lb_gram_body(st, dotpart, nblocks, jds);
-    if (threadIdx.x != 0) return;
-    LbCtl& c = st->ctl;
-    const double J_old = c.J, J_new = jds[0];
-    c.J = J_new;
-    c.gmax = jds[3];
-    c.iters += 1;
-    c.op = kOpNone;
-    if (c.early_stop && (J_old - J_new) <= c.tol * (1.0 + fabs(J_old)))
-        lb_finish(c, NGF_INFO_CONVERGED);
-    else if (c.iters >= c.max_iter)
-        lb_finish(c, NGF_INFO_MAX_ITER);
-    else
-        c.phase = kPhNeedDir;
+    if (threadIdx.x == 0) {
+        LbCtl& c = st->ctl;
+        const double J_old = c.J, J_new = jds[0];
+        c.J = J_new;
+        c.gmax = jds[3];
+        c.iters += 1;
+        c.op = kOpNone;
+        if (c.early_stop && (J_old - J_new) <= c.tol * (1.0 + fabs(J_old)))
+            lb_finish(c, NGF_INFO_CONVERGED);
+        else if (c.iters >= c.max_iter)
+            lb_finish(c, NGF_INFO_MAX_ITER);
+        else
+            c.phase = kPhNeedDir;
+    }
+}
+
+// End of a round and start of the next in one launch: the Gram update and
+// stopping tests after an accepted step, then the plan of the next round
+// (new direction or next halving).  The same steps, in the same order, as
+// the accept and plan kernels launched one after the other; the block's
+// barrier makes lane 0's writes to the state visible to the staging of G.
+__device__ __forceinline__ void lb_gram_plan_body(LbState* st, const double* dotpart,
+                                                  int nblocks, double* jds) {
+    __shared__ int accepted;
+    if (threadIdx.x == 0) accepted = st->ctl.phase == kPhAccepted;
+    __syncthreads();
+    if (accepted) lb_accept_gram_body(st, dotpart, nblocks, jds);
+    __syncthreads();
+    lb_plan_body(st, jds);
 }
 
 }  // namespace

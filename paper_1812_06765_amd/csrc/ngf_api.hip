@@ -499,7 +499,6 @@ bool armijo_ok(double Jt, double J, double c1, double t, double gtd) {
 ngf_status enqueue_round(ngf_ctx* c, const Level& L, bool* recorded) {
     const int64_t n = 3 * L.Ny();
     const int* gate = &c->st->ctl.op;
-    launch_lb_plan(c->st, c->jds, c->stream);
     launch_lb_vec(c->st, c->hist, static_cast<int64_t>(c->lb_ld), n, c->ly, c->lg, c->ld,
                   c->lyt, c->stream);
     HIPCHK(c, hipGetLastError());
@@ -526,6 +525,8 @@ ngf_status run_level_on_device(ngf_ctx* c, LbCtl* out) {
     // every round makes at most one step: size a batch by the remaining budget
     int batch = std::max(1, std::min(kRoundBatch, c->p.max_iter));
     LbCtl* h = reinterpret_cast<LbCtl*>(c->host_jds + 8);
+    launch_lb_plan(c->st, c->jds, c->stream);  // later plans end the rounds before them
+    HIPCHK(c, hipGetLastError());
     for (;;) {
         for (int k = 0; k < batch; ++k) {
             bool r = false;

@@ -4,9 +4,10 @@
 // Graph mode (default).  Every pair has a context (pyramid, scratch, L-BFGS
 // buffers) on the batch's stream.  The pairs go through the levels together:
 // at each level one L-BFGS round of every pair is one fixed sequence of
-// batched launches (plan, vector update, image pass per variant group, node
-// pass, reduction with the Armijo test, history update, control-block
-// gather), each covering all pairs through a block table.  The sequence is
+// batched launches (vector update, image pass per variant group, node pass,
+// reduction with the Armijo test, history update ending with the next
+// round's plan, control-block gather), each covering all pairs through a
+// block table.  The sequence is
 // captured once per level as a hipGraph and replayed; the host reads the
 // gathered control blocks between batches of replays and stops when every
 // pair's level has ended.  The kernels run the single-pair bodies with each
@@ -258,13 +259,13 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
         node_stage(o_node0);
         launch_reduce_batch(static_cast<const ReduceArgs*>(P(o_red0)), np, s);
         launch_lb_init_batch(vec, np, s);
+        launch_lb_plan_batch(vec, np, s);  // later plans end the rounds before them
         if (hipGetLastError() != hipSuccess) return bfail(b, NGF_E_HIP, "level start launch");
         // one round of every pair, captured once
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess)
             return bfail(b, NGF_E_HIP, "hipStreamBeginCapture failed");
-        launch_lb_plan_batch(vec, np, s);
         launch_lb_vec_batch(vec, static_cast<const BlockRef*>(P(o_vblk)), nvb, s);
         image_stage(o_img1);
         node_stage(o_node1);

@@ -303,13 +303,15 @@ void launch_apply_PT(const int32_t* const j0[3], const float* const w0[3],
 
 // L-BFGS vector kernels
 void launch_lb_solve(LbState* st, double* jds, hipStream_t s);
-// one round of the device-driven level (see LbCtl)
+// one round of the device-driven level (see LbCtl): the plan of the first
+// round, then per round vec, evaluation, accept; accept ends with the plan of
+// the next round
 void launch_lb_plan(LbState* st, double* jds, hipStream_t s);
 void launch_lb_vec(LbState* st, const float* hist, int64_t ld, int64_t n, const float* y,
                    const float* g, float* d, float* yt, hipStream_t s);
 void launch_lb_accept(LbState* st, float* hist, int64_t ld, int64_t n, float* y,
                       const float* yt, float* g, const float* gt, double* dotpart,
-                      int nblocks, const double* jds, int mem, hipStream_t s);
+                      int nblocks, double* jds, int mem, hipStream_t s);
 void launch_lb_combine(LbState* st, const float* hist, int64_t ld, int64_t n, const float* y,
                        const float* g, float* d, float* yt, hipStream_t s);
 void launch_lb_axpy(const float* y, const float* d, float t, float* yt, int64_t n,
