@@ -385,7 +385,7 @@ __device__ __forceinline__ void lb_gram_body(LbState* st,
         const int j = threadIdx.x & 63;
         double s = 0.0;
         if (j < kDots) {
-#pragma unroll 8
+#pragma unroll 16
             for (int b = p; b < nblocks; b += kGramPhases)
                 s += dotpart[static_cast<int64_t>(b) * kDots + j];
         }
@@ -537,14 +537,28 @@ __device__ __forceinline__ void lb_accept_gram_body(LbState* st, const double* d
 // (new direction or next halving).  The same steps, in the same order, as
 // the accept and plan kernels launched one after the other; the block's
 // barrier makes lane 0's writes to the state visible to the staging of G.
+// The state is staged in LDS for the single-lane parts (many dependent
+// reads and writes of small fields) and written back once.
 __device__ __forceinline__ void lb_gram_plan_body(LbState* st, const double* dotpart,
                                                   int nblocks, double* jds) {
-    __shared__ int accepted;
-    if (threadIdx.x == 0) accepted = st->ctl.phase == kPhAccepted;
+    static_assert(sizeof(LbState) % 8 == 0, "state copied in 8-byte words");
+    constexpr int kWords = sizeof(LbState) / 8;
+    __shared__ LbState ls;
+    {
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(st);
+        uint64_t* dst = reinterpret_cast<uint64_t*>(&ls);
+        for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = src[i];
+    }
     __syncthreads();
-    if (accepted) lb_accept_gram_body(st, dotpart, nblocks, jds);
+    if (ls.ctl.phase == kPhAccepted) lb_accept_gram_body(&ls, dotpart, nblocks, jds);
     __syncthreads();
-    lb_plan_body(st, jds);
+    lb_plan_body(&ls, jds);
+    __syncthreads();
+    {
+        const uint64_t* src = reinterpret_cast<const uint64_t*>(&ls);
+        uint64_t* dst = reinterpret_cast<uint64_t*>(st);
+        for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = src[i];
+    }
 }
 
 }  // namespace
