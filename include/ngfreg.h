@@ -138,9 +138,10 @@ ngf_status ngf_set_params(ngf_ctx* ctx, const ngf_params* p);
  *   R, T       input images on `g` ([m_x][m_y][m_z] float32)
  *   host_ptrs  0: R and T are device pointers; 1: host pointers (copied
  *              host-to-device on the two streams)
- * Shape rule: every m_d divisible by ratio * 2^(levels-1), and the coarsest
- * level at least 4 cells and 2 deformation cells per axis; otherwise
- * NGF_E_SHAPE.  Synchronises before returning. */
+ * Shape rule: every m_d divisible by ratio * 2^(levels-1), the coarsest
+ * level at least 4 cells and 2 deformation cells per axis, and fewer than
+ * 2^30 voxels (32-bit byte offsets into the images); otherwise NGF_E_SHAPE.
+ * Synchronises before returning. */
 ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
                              const ngf_grid* g, int32_t host_ptrs);
 

@@ -33,6 +33,21 @@ namespace {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Raw buffer access to R, T and y: byte offsets in 32 bits (the host keeps
+// the images below 2^30 voxels), the uniform part of an offset in a scalar
+// register, no 64-bit address arithmetic per load.  A load past the buffer
+// size returns 0 instead of faulting.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const float* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), 0, bytes, 0x00020000);
+}
+__device__ inline float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ inline float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+}
+
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     return v;
@@ -117,6 +132,10 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
     const int qly = max(y0 - 2, 0) / R, qlz = max(z0 - 2, 0) / R;
     const int jx_first = x0 / R;
     const int xend = min(x0 + CX, mx);  // first plane past the chunk (in the domain)
+    const uint32_t nbytes = static_cast<uint32_t>(mx) * static_cast<uint32_t>(sxT) * 4u;
+    const __amdgpu_buffer_rsrc_t rT = make_rsrc(a.T, nbytes), rR = make_rsrc(a.R, nbytes);
+    const __amdgpu_buffer_rsrc_t rY = make_rsrc(a.y, 3u * static_cast<uint32_t>(nnod) * 4u);
+    const uint32_t plane4 = static_cast<uint32_t>(sxT) * 4u;  // bytes per image plane
     // steps: the chunk's planes plus two lead-in and two lead-out planes; a
     // chunk cut short by the domain stops after its last plane
     const int nstep = xend - x0 + 4;
@@ -138,9 +157,10 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
                 const int r = i - c * L::NQ;
                 const int qz = r % L::NQZ, qy = r / L::NQZ;
                 const int gy = min(qly + qy, a.ny - 1), gz = min(qlz + qz, a.nz - 1);
-                const float* yc = a.y + c * nnod + gy * a.nz + gz;
-                qv0[k] = yc[jx * a.ny * a.nz];
-                qv1[k] = yc[(jx + 1) * a.ny * a.nz];
+                const uint32_t off = static_cast<uint32_t>(c * nnod + gy * a.nz + gz) * 4u;
+                const uint32_t nplane4 = static_cast<uint32_t>(a.ny * a.nz) * 4u;
+                qv0[k] = bload(rY, off, static_cast<uint32_t>(jx) * nplane4);
+                qv1[k] = bload(rY, off, static_cast<uint32_t>(jx + 1) * nplane4);
             }
         }
     };
@@ -183,19 +203,23 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         const int mm[3] = {mx, my, mz};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double xi = POW2 ? fma(yh[d], ih[d], -0.5) : yh[d] / hh[d] - 0.5;
-            const double hi = static_cast<double>(mm[d] - 1);
-            s[d] = (xi >= 0.0 && xi <= hi) ? 1.0f : 0.0f;
-            xi = fmin(fmax(xi, 0.0), hi);
-            const double fl = fmin(floor(xi), static_cast<double>(mm[d] - 2));
-            i0[d] = static_cast<int>(fl);
-            f[d] = static_cast<float>(xi - fl);
+            const double xi = POW2 ? fma(yh[d], ih[d], -0.5) : yh[d] / hh[d] - 0.5;
+            // clamped into [0, m - 1] (a NaN goes to 0); inside the domain iff
+            // unchanged.  On [0, m - 1] the floor is the truncation, and the
+            // last cell is m - 2 (the fraction reaches 1 at the far end).
+            const double xc = fmin(fmax(xi, 0.0), static_cast<double>(mm[d] - 1));
+            s[d] = xc == xi ? 1.0f : 0.0f;
+            const int i = min(static_cast<int>(xc), mm[d] - 2);
+            i0[d] = i;
+            f[d] = static_cast<float>(xc - static_cast<double>(i));
         }
         (void)pc;
-        const float* Tb = a.T + i0[0] * sxT + i0[1] * mz + i0[2];
-        const float v000 = Tb[0], v001 = Tb[1], v010 = Tb[mz], v011 = Tb[mz + 1];
-        const float v100 = Tb[sxT], v101 = Tb[sxT + 1], v110 = Tb[sxT + mz],
-                    v111 = Tb[sxT + mz + 1];
+        const uint32_t tb = static_cast<uint32_t>(i0[0] * sxT + i0[1] * mz + i0[2]) * 4u;
+        const uint32_t row4 = static_cast<uint32_t>(mz) * 4u;
+        const float2 t00 = bload2(rT, tb, 0u), t01 = bload2(rT, tb, row4);
+        const float2 t10 = bload2(rT, tb, plane4), t11 = bload2(rT, tb, plane4 + row4);
+        const float v000 = t00.x, v001 = t00.y, v010 = t01.x, v011 = t01.y;
+        const float v100 = t10.x, v101 = t10.y, v110 = t11.x, v111 = t11.y;
         const float qx = 1.0f - f[0], qy = 1.0f - f[1], qz = 1.0f - f[2];
         const float c00 = fmaf(f[2], v001, qz * v000), c01 = fmaf(f[2], v011, qz * v010);
         const float c10 = fmaf(f[2], v101, qz * v100), c11 = fmaf(f[2], v111, qz * v110);
@@ -276,8 +300,8 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         if (k + 1 < nstep) load_q(pw + 1);
         float rxm[L::KP + 1], rxp[L::KP + 1];
         if (vok) {
-            const float* Rm = a.R + max(pv - 1, 0) * sxT;
-            const float* Rq = a.R + min(pv + 1, mx - 1) * sxT;
+            const uint32_t sm = static_cast<uint32_t>(max(pv - 1, 0)) * plane4;
+            const uint32_t sp = static_cast<uint32_t>(min(pv + 1, mx - 1)) * plane4;
 #pragma unroll
             for (int kk = 0; kk <= L::KP; ++kk) {
                 int b1y, b1z;
@@ -289,16 +313,17 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
                     ring1_pos(min(static_cast<int>(threadIdx.x), L::NRING1 - 1), b1y, b1z);
                 }
                 const int cy = clampi(y0 - 1 + b1y, 0, my - 1), cz = clampi(z0 - 1 + b1z, 0, mz - 1);
-                rxm[kk] = Rm[cy * mz + cz];
-                rxp[kk] = Rq[cy * mz + cz];
+                const uint32_t off = static_cast<uint32_t>(cy * mz + cz) * 4u;
+                rxm[kk] = bload(rR, off, sm);
+                rxp[kk] = bload(rR, off, sp);
             }
         }
         if (vok) {
-            const float* Rp = a.R + pv * sxT;
+            const uint32_t s0 = static_cast<uint32_t>(pv) * plane4;
             for (int i = threadIdx.x; i < L::NH2; i += kThreads) {
                 const int by = i / L::H2Z, bz = i - by * L::H2Z;
                 const int gy = clampi(y0 - 2 + by, 0, my - 1), gz = clampi(z0 - 2 + bz, 0, mz - 1);
-                sR[i] = Rp[gy * mz + gz];
+                sR[i] = bload(rR, static_cast<uint32_t>(gy * mz + gz) * 4u, s0);
             }
         }
         __syncthreads();
@@ -497,16 +522,18 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
 }
 
 // The 16 x 32 tile needs 36 KiB of LDS, so up to four workgroups fit a CU;
-// its registers are held to three waves per SIMD.  The 16 x 64 tile is
-// limited to two workgroups per CU by LDS anyway.
+// its registers are held to four waves per SIMD (128 VGPRs, no spills).  The
+// 16 x 64 tile is limited to two workgroups per CU by LDS anyway.
 template <int TY, int TZ, int R, bool GRAD, bool POW2>
-__global__ __launch_bounds__(kThreads, TZ == 32 ? 3 : 2) void k_image_march(ImagePassArgs a,
+__global__ __launch_bounds__(kThreads, TZ == 32 ? 4 : 2) void k_image_march(ImagePassArgs a,
                                                                             int CX) {
     if (a.gate && *a.gate == kOpNone) return;
     march_body<TY, TZ, R, GRAD, POW2>(a, CX, blockIdx.x);
 }
 
 // each pair's chunk length is its own (a.cx)
+// The batched form indexes its arguments per block and needs a few more
+// registers: three waves per SIMD keep it free of spills.
 template <int TY, int TZ, int R, bool POW2>
 __global__ __launch_bounds__(kThreads, TZ == 32 ? 3 : 2) void k_image_march_batch(
     const ImagePassArgs* args, const BlockRef* blk) {

@@ -653,7 +653,8 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
             return fail(c, NGF_E_SHAPE, "coarsest level needs >= 4 cells and >= 2 node cells");
         N *= g->m[d];
     }
-    if (N >= (static_cast<int64_t>(1) << 31)) return fail(c, NGF_E_SHAPE, "image too large");
+    if (N >= (static_cast<int64_t>(1) << 30))
+        return fail(c, NGF_E_SHAPE, "image too large (at most 2^30 - 1 voxels)");
     c->lb_level = -1;
     c->lv.assign(L, Level{});
     for (int l = 0; l < L; ++l) {

@@ -354,6 +354,13 @@ def test_error_paths(gpu_lib):
     with pytest.raises(ngf.NgfError) as e:
         ctx.build_pyramid(R, R)  # coarsest level would have 2 cells per axis
     assert e.value.status == ngf.E_SHAPE
+    # 2^30 voxels: beyond the 32-bit byte offsets of the image kernels
+    # (rejected before the images are read; the tensors are never filled)
+    big = torch.empty((1024, 1024, 1024), device="cuda")
+    with pytest.raises(ngf.NgfError) as e:
+        ctx.build_pyramid(big, big)
+    assert e.value.status == ngf.E_SHAPE
+    del big
     R = torch.zeros((32, 32, 32), device="cuda")
     bad = R.clone()
     bad[3, 4, 5] = float("nan")
