@@ -533,23 +533,36 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
     }
     const int64_t xslab = static_cast<int64_t>(a.nty) * a.ntz * 3 * NP;
 
+    // y of this thread's entries of the u plane, loaded one step ahead so
+    // that the loads overlap the previous plane's A u and output phases
+    float upre[KU];
+    auto load_u = [&](int pu) {
+        if (pu < 0 || pu >= nx) return;  // planes outside the grid are never read
+        const float* ycp = yc + pu * ny * nz;
+#pragma unroll
+        for (int kk = 0; kk < KU; ++kk) {
+            const int i = threadIdx.x + kk * kThreads;
+            upre[kk] = i < NU ? ycp[uoff[kk]] : 0.0f;
+        }
+    };
+    load_u(x0 - 2);
     double ssum = 0.0, gmax = 0.0, g2 = 0.0;
     for (int k = 0; k < nstep; ++k) {
-        // u of plane pu (planes outside the grid are never read)
+        // u of plane pu
         const int pu = x0 - 2 + k;
         if (pu >= 0 && pu < nx) {
             float* U = su[k % 3];
-            const float* ycp = yc + pu * ny * nz;
 #pragma unroll
             for (int kk = 0; kk < KU; ++kk) {
                 const int i = threadIdx.x + kk * kThreads;
                 if (i < NU) {
                     const int gc = c == 0 ? pu : ugc[kk];
-                    U[i] = static_cast<float>(static_cast<double>(ycp[uoff[kk]]) -
+                    U[i] = static_cast<float>(static_cast<double>(upre[kk]) -
                                               static_cast<double>(gc) * hyc);
                 }
             }
         }
+        if (k + 1 < nstep) load_u(pu + 1);
         __syncthreads();
         // A u of plane pa, from u planes pa - 1, pa, pa + 1 (replicated ghosts)
         const int pa = pu - 1;

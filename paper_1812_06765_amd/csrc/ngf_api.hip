@@ -76,7 +76,7 @@ Geo geometry(const Level& L, int variant) {
         g.tz = march_tz(variant);
         g.tx = march_cx(variant);
         if (g.tx == 0)
-            g.tx = fit_chunk(L.m[0], int64_t{tiles(L.m[1], g.ty)} * tiles(L.m[2], g.tz), 4, 8,
+            g.tx = fit_chunk(L.m[0], int64_t{tiles(L.m[1], g.ty)} * tiles(L.m[2], g.tz), 4, 4,
                              image_march_slots(g.tz));
     }
     g.ntx = tiles(L.m[0], g.tx);
