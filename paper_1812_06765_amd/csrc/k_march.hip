@@ -533,9 +533,9 @@ __global__ __launch_bounds__(kThreads, TZ == 32 ? 4 : 2) void k_image_march(Imag
 
 // each pair's chunk length is its own (a.cx)
 // The batched form indexes its arguments per block and needs a few more
-// registers: three waves per SIMD keep it free of spills.
+// registers: at four waves per SIMD a few of them spill to scratch.
 template <int TY, int TZ, int R, bool POW2>
-__global__ __launch_bounds__(kThreads, TZ == 32 ? 3 : 2) void k_image_march_batch(
+__global__ __launch_bounds__(kThreads, TZ == 32 ? 4 : 2) void k_image_march_batch(
     const ImagePassArgs* args, const BlockRef* blk) {
     const BlockRef e = blk[blockIdx.x];
     if (e.pair < 0) return;
