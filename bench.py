@@ -224,6 +224,8 @@ def main():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--max-iter", type=int, default=50)
     ap.add_argument("--finest-evals", type=int, default=200)
+    ap.add_argument("--host-reps", type=int, default=3,
+                    help="registrations from pinned host arrays (PCIe-inclusive timing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead: the uneven batch of this many pairs (axes drawn from "
@@ -317,6 +319,20 @@ def main():
     Ny = li.my[0] * li.my[1] * li.my[2]
     finest_bytes = 8 * N + 24 * Ny
 
+    # the paper's convention: registration from host arrays (pinned), with the
+    # copies of R and T to the device, the pyramid and the copy of y back
+    Rh, Th = R.cpu().pin_memory(), T.cpu().pin_memory()
+    ctx.register(Rh, Th)
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    for _ in range(args.host_reps):
+        ctx.register(Rh, Th)
+    torch.cuda.synchronize()
+    th = (time.perf_counter() - th) / max(args.host_reps, 1)
+    del Rh, Th
+    print(f"[bench] registration from host arrays: {th * 1e3:.1f} ms", file=sys.stderr,
+          flush=True)
+
     # roofline of the dominant kernel (the image pass at the finest level)
     # over the timed region: it is bound by vector-ALU issue, not by HBM
     # (its traffic is a few hundred MB per launch at well under 1 TB/s)
@@ -348,6 +364,9 @@ def main():
         "registration_s": dt / args.steps,
         "evals_per_registration": evals / args.steps,
         "levels": reports[-1],
+        "from_host": {"registration_s": th, "reps": args.host_reps,
+                      "note": "pinned host R and T in, y out: includes both copies over PCIe "
+                              "and the pyramid (not the metric's value)"},
         "finest": {"evals_per_s": args.finest_evals / tf,
                    "eval_us": 1e6 * tf / args.finest_evals,
                    "compulsory_bytes": finest_bytes,
