@@ -459,14 +459,23 @@ __global__ __launch_bounds__(kThreads) void k_image_pass(ImagePassArgs a) {
 // (for u and for A u): in-plane through clamped loads and zero offsets, across
 // planes by reading the boundary plane's slot.  Step k loads u of plane
 // x0 - 2 + k, forms A u of plane x0 - 3 + k and A(A u) of plane x0 - 4 + k.
-template <int NY, int NZ>
+//
+// The loop is kept free of per-lane branches and of per-plane index
+// arithmetic on the scalar unit: the LDS planes are padded to whole passes of
+// the workgroup (the surplus lanes work on a clamped copy and write into the
+// padding), the plane slots rotate, the plane offsets advance by one plane
+// per step, and lanes outside the grid compute on clamped data and store
+// nothing.  GRAD: the gradient is wanted; GATHER: it collects the image-tile
+// partials (else grad holds grad D on entry).
+template <int NY, int NZ, bool GRAD, bool GATHER>
 __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block) {
     static_assert(NY * NZ == kThreads, "one node per thread and plane");
     constexpr int UY = NY + 4, UZ = NZ + 4, NU = UY * UZ;  // u plane, halo 2
     constexpr int AY = NY + 2, AZ = NZ + 2, NA = AY * AZ;  // A u plane, halo 1
     constexpr int KU = (NU + kThreads - 1) / kThreads, KA = (NA + kThreads - 1) / kThreads;
-    __shared__ float su[3][NU];
-    __shared__ float sAu[3][NA];
+    constexpr int SU = KU * kThreads, SA = KA * kThreads;  // padded plane sizes
+    __shared__ float su[3 * SU];
+    __shared__ float sAu[3 * SA];
     __shared__ double red[4];
 
     const int ntile = a.nbx * a.nby * a.nbz;
@@ -479,12 +488,12 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
     const int x0 = bx * a.cxn, y0 = byy * NY, z0 = bz * NZ;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int nn = nx * ny * nz;
+    const int plane = ny * nz;
     const int xend = min(x0 + a.cxn, nx);
     const int nstep = xend - x0 + 4;  // a chunk cut short by the grid stops after its last plane
     const int PX = a.bx + 1, PY = a.by + 1, PZ = a.bz + 1;
     const int NP = PX * PY * PZ;
-    const float sc = (!a.gather && a.gscale != nullptr) ? static_cast<float>(*a.gscale) : 1.0f;
-    const float* yc = a.y + c * nn;
+    const float sc = (!GATHER && a.gscale != nullptr) ? static_cast<float>(*a.gscale) : 1.0f;
     const double hyc = c == 0 ? a.hyx : (c == 1 ? a.hyy : a.hyz);
 
     // this thread's node (y, z) and its fixed in-plane data
@@ -494,122 +503,133 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
     const int q = (ly + 1) * AZ + (lz + 1);
     const int dyp = gy + 1 < ny ? AZ : 0, dym = gy > 0 ? AZ : 0;
     const int dzp = gz + 1 < nz ? 1 : 0, dzm = gz > 0 ? 1 : 0;
-    // u halo entries of this thread: clamped in-plane offset and coordinate
-    int uoff[KU], ugc[KU];
+    const int gofs = min(gy, ny - 1) * nz + min(gz, nz - 1);  // in-plane offset (clamped)
+    // u halo entries of this thread (the padding lanes repeat the last one):
+    // clamped in-plane offset and the coordinate X is taken along
+    int uoff[KU];
+    float ugc[KU];
 #pragma unroll
     for (int k = 0; k < KU; ++k) {
-        const int i = threadIdx.x + k * kThreads;
+        const int i = min(static_cast<int>(threadIdx.x) + k * kThreads, NU - 1);
         const int iy = i / UZ, iz = i - (i / UZ) * UZ;
         const int cy = clampi(y0 - 2 + iy, 0, ny - 1), cz = clampi(z0 - 2 + iz, 0, nz - 1);
         uoff[k] = cy * nz + cz;
-        ugc[k] = c == 1 ? cy : cz;
+        ugc[k] = static_cast<float>(c == 1 ? cy : cz);
     }
     // A u halo entries of this thread: their (clamped) node's place in the u plane
     int apos[KA];
 #pragma unroll
     for (int k = 0; k < KA; ++k) {
-        const int i = threadIdx.x + k * kThreads;
+        const int i = min(static_cast<int>(threadIdx.x) + k * kThreads, NA - 1);
         const int iy = i / AZ, iz = i - (i / AZ) * AZ;
         const int cy = clampi(y0 - 1 + iy, 0, ny - 1), cz = clampi(z0 - 1 + iz, 0, nz - 1);
         apos[k] = (cy - y0 + 2) * UZ + (cz - z0 + 2);
     }
-    // gather of the image-tile partials: the (y, z) part is fixed
-    const float ibx = 1.0f / a.bx, iby = 1.0f / a.by, ibz = 1.0f / a.bz;
-    const int tyh = div_small(gy, a.by, iby), tzh = div_small(gz, a.bz, ibz);
-    const int ry = gy - tyh * a.by, rz = gz - tzh * a.bz;
-    const int noy = (ry == 0 && tyh > 0) ? 2 : 1, noz = (rz == 0 && tzh > 0) ? 2 : 1;
-    // the (y, z) part of the node's place in each image tile that holds it
-    // (j = 2 oy + oz, the tile oy rows and oz columns back), fixed over the
-    // chunk; the x part is the same for the whole workgroup.  The part array
-    // of one x-slab of tiles is below 2^31 floats (checked by the host).
+    // gather of the image-tile partials: the (y, z) part of the node's place
+    // in each image tile that holds it (j = 2 oy + oz, the tile oy rows and oz
+    // columns back) is fixed over the chunk; the x part is the same for the
+    // whole workgroup.  An entry that does not apply reads offset 0 of the
+    // tile row and is not added.  The part array of one x-slab of tiles is
+    // below 2^31 floats (checked by the host).
     int yzoff[4];
     bool yzok[4];
+    {
+        const float iby = 1.0f / a.by, ibz = 1.0f / a.bz;
+        const int tyh = div_small(gy, a.by, iby), tzh = div_small(gz, a.bz, ibz);
+        const int ry = gy - tyh * a.by, rz = gz - tzh * a.bz;
+        const int noy = (ry == 0 && tyh > 0) ? 2 : 1, noz = (rz == 0 && tzh > 0) ? 2 : 1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int oy = j >> 1, oz = j & 1;
-        const int tty = tyh - oy, ttz = tzh - oz;
-        yzok[j] = own && oy < noy && oz < noz && tty < a.nty && ttz < a.ntz;
-        yzoff[j] = ((tty * a.ntz + ttz) * 3 + c) * NP + (ry + oy * a.by) * PZ + (rz + oz * a.bz);
+        for (int j = 0; j < 4; ++j) {
+            const int oy = j >> 1, oz = j & 1;
+            const int tty = tyh - oy, ttz = tzh - oz;
+            yzok[j] = own && oy < noy && oz < noz && tty < a.nty && ttz < a.ntz;
+            yzoff[j] = yzok[j] ? ((tty * a.ntz + ttz) * 3 + c) * NP + (ry + oy * a.by) * PZ +
+                                     (rz + oz * a.bz)
+                               : 0;
+        }
     }
     const int64_t xslab = static_cast<int64_t>(a.nty) * a.ntz * 3 * NP;
+    // x tile of the first output plane and the plane's place in it; both
+    // advance with the output plane
+    int txh = x0 / a.bx;
+    int rx = x0 - txh * a.bx;
 
     // y of this thread's entries of the u plane, loaded one step ahead so
     // that the loads overlap the previous plane's A u and output phases
+    int64_t ycur = static_cast<int64_t>(c) * nn + static_cast<int64_t>(x0 - 2) * plane;
     float upre[KU];
-    auto load_u = [&](int pu) {
+    auto load_u = [&](int pu, int64_t yo) {
         if (pu < 0 || pu >= nx) return;  // planes outside the grid are never read
-        const float* ycp = yc + pu * ny * nz;
+        const float* yp = a.y + yo;
 #pragma unroll
-        for (int kk = 0; kk < KU; ++kk) {
-            const int i = threadIdx.x + kk * kThreads;
-            upre[kk] = i < NU ? ycp[uoff[kk]] : 0.0f;
-        }
+        for (int kk = 0; kk < KU; ++kk) upre[kk] = yp[uoff[kk]];
     };
-    load_u(x0 - 2);
+    load_u(x0 - 2, ycur);
+    // this thread's output element: component c, plane po, in-plane offset
+    int64_t grow = static_cast<int64_t>(c) * nn + static_cast<int64_t>(x0) * plane + gofs;
+    // slots of the three rolling planes: s0 = k mod 3, s1 = (k + 1) mod 3, s2 = (k + 2) mod 3
+    int s0 = 0, s1 = 1, s2 = 2;
     double ssum = 0.0, gmax = 0.0, g2 = 0.0;
     for (int k = 0; k < nstep; ++k) {
         // u of plane pu
         const int pu = x0 - 2 + k;
         if (pu >= 0 && pu < nx) {
-            float* U = su[k % 3];
+            float* U = su + s0 * SU;
+            const double gx = static_cast<double>(pu);
 #pragma unroll
             for (int kk = 0; kk < KU; ++kk) {
-                const int i = threadIdx.x + kk * kThreads;
-                if (i < NU) {
-                    const int gc = c == 0 ? pu : ugc[kk];
-                    U[i] = static_cast<float>(static_cast<double>(upre[kk]) -
-                                              static_cast<double>(gc) * hyc);
-                }
+                const double gcd = c == 0 ? gx : static_cast<double>(ugc[kk]);
+                U[threadIdx.x + kk * kThreads] =
+                    static_cast<float>(static_cast<double>(upre[kk]) - gcd * hyc);
             }
         }
-        if (k + 1 < nstep) load_u(pu + 1);
+        ycur += plane;
+        if (k + 1 < nstep) load_u(pu + 1, ycur);
         __syncthreads();
         // A u of plane pa, from u planes pa - 1, pa, pa + 1 (replicated ghosts)
         const int pa = pu - 1;
         if (pa >= 0 && pa < nx) {
-            const float* U0 = su[(k + 2) % 3];                      // plane pa
-            const float* Um = pa > 0 ? su[(k + 1) % 3] : U0;          // plane pa - 1
-            const float* Up = pa + 1 < nx ? su[k % 3] : U0;           // plane pa + 1
-            float* A = sAu[k % 3];
+            const float* U0 = su + s2 * SU;                        // plane pa
+            const float* Um = pa > 0 ? su + s1 * SU : U0;          // plane pa - 1
+            const float* Up = pa + 1 < nx ? su + s0 * SU : U0;     // plane pa + 1
+            float* A = sAu + s0 * SA;
 #pragma unroll
             for (int kk = 0; kk < KA; ++kk) {
-                const int i = threadIdx.x + kk * kThreads;
-                if (i < NA) {
-                    const int p = apos[kk];
-                    const float u0 = U0[p];
-                    const float lx = Up[p] - 2.0f * u0 + Um[p];
-                    const float lyv = U0[p + UZ] - 2.0f * u0 + U0[p - UZ];
-                    const float lzv = U0[p + 1] - 2.0f * u0 + U0[p - 1];
-                    A[i] = fmaf(lx, a.ihy2x, fmaf(lyv, a.ihy2y, lzv * a.ihy2z));
-                }
+                const int p = apos[kk];
+                const float u0 = U0[p];
+                const float lx = Up[p] - 2.0f * u0 + Um[p];
+                const float lyv = U0[p + UZ] - 2.0f * u0 + U0[p - UZ];
+                const float lzv = U0[p + 1] - 2.0f * u0 + U0[p - 1];
+                A[threadIdx.x + kk * kThreads] = fmaf(lx, a.ihy2x, fmaf(lyv, a.ihy2y, lzv * a.ihy2z));
             }
         }
         __syncthreads();
         // A(A u) and the gradient at plane po
         const int po = pu - 2;
-        if (po >= x0 && po < xend && own) {
-            const float* A0 = sAu[(k + 2) % 3];                     // plane po
-            const float* Am = po > 0 ? sAu[(k + 1) % 3] : A0;         // plane po - 1
-            const float* Ap = po + 1 < nx ? sAu[k % 3] : A0;          // plane po + 1
+        if (po >= x0 && po < xend) {
+            const float* A0 = sAu + s2 * SA;                       // plane po
+            const float* Am = po > 0 ? sAu + s1 * SA : A0;         // plane po - 1
+            const float* Ap = po + 1 < nx ? sAu + s0 * SA : A0;    // plane po + 1
             const float au = A0[q];
-            ssum += static_cast<double>(au) * static_cast<double>(au);
-            if (a.want_grad) {
+            ssum += own ? static_cast<double>(au) * static_cast<double>(au) : 0.0;
+            if (GRAD) {
                 float gd = 0.0f;
-                if (!a.gather) {
-                    gd = a.grad[c * nn + (po * ny + gy) * nz + gz];
+                if (!GATHER) {
+                    gd = a.grad[grow];
                 } else {
                     // Eq. 3 completed: the (at most 8) image-tile partials of the
                     // node, in the order (ox, oy, oz)
-                    const int txh = div_small(po, a.bx, ibx);
-                    const int rx = po - txh * a.bx;
                     const int nox = (rx == 0 && txh > 0) ? 2 : 1;
-                    for (int ox = 0; ox < nox; ++ox) {
+#pragma unroll
+                    for (int ox = 0; ox < 2; ++ox) {
                         const int ttx = txh - ox;
-                        if (ttx >= a.ntx) continue;
+                        if (ox >= nox || ttx >= a.ntx) continue;
                         const float* px = a.part + ttx * xslab + (rx + ox * a.bx) * (PY * PZ);
 #pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            if (yzok[j]) gd += px[yzoff[j]];
+                        for (int j = 0; j < 4; ++j) {
+                            const float v = px[yzoff[j]];
+                            gd = yzok[j] ? gd + v : gd;
+                        }
                     }
                 }
                 const float lxx = Ap[q] - 2.0f * au + Am[q];
@@ -617,15 +637,27 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
                 const float lzz = A0[q + dzp] - 2.0f * au + A0[q - dzm];
                 const float aau = fmaf(lxx, a.ihy2x, fmaf(lyy, a.ihy2y, lzz * a.ihy2z));
                 const float g = fmaf(a.alpha_hbary * sc, aau, gd);
-                a.grad[c * nn + (po * ny + gy) * nz + gz] = g;
-                gmax = fmax(gmax, static_cast<double>(fabsf(g)));
-                g2 += static_cast<double>(g) * static_cast<double>(g);
+                if (own) a.grad[grow] = g;
+                gmax = own ? fmax(gmax, static_cast<double>(fabsf(g))) : gmax;
+                g2 += own ? static_cast<double>(g) * static_cast<double>(g) : 0.0;
+                grow += plane;
+            }
+            if (GATHER) {
+                rx += 1;
+                if (rx == a.bx) {
+                    rx = 0;
+                    txh += 1;
+                }
             }
         }
+        const int t = s0;
+        s0 = s1;
+        s1 = s2;
+        s2 = t;
     }
     const double st = block_sum(ssum, red);
     if (threadIdx.x == 0) a.spart[bid] = st;
-    if (a.want_grad) {
+    if (GRAD) {
         const double gm = block_max(gmax, red);
         const double gq = block_sum(g2, red);
         if (threadIdx.x == 0) {
@@ -762,20 +794,24 @@ __device__ __forceinline__ void node_tile_body(const NodePassArgs& a, int block)
     }
 }
 
-template <bool MARCH>
+// MARCH: marching form, with the gradient and gather choice fixed at compile
+// time (GRAD, GATHER); otherwise the 3D-tile form, which reads them from the
+// arguments
+template <bool MARCH, bool GRAD, bool GATHER>
 __device__ __forceinline__ void node_body(const NodePassArgs& a, int block) {
     if (MARCH)
-        node_march_body<kNMY, kNMZ>(a, block);
+        node_march_body<kNMY, kNMZ, GRAD, GATHER>(a, block);
     else
         node_tile_body<kNTX, kNTY, kNTZ>(a, block);
 }
 
-template <bool MARCH>
+template <bool MARCH, bool GRAD, bool GATHER>
 __global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
     if (a.gate && *a.gate == kOpNone) return;
-    node_body<MARCH>(a, blockIdx.x);
+    node_body<MARCH, GRAD, GATHER>(a, blockIdx.x);
 }
 
+// the batched rounds always want the gradient gathered from the image pass
 template <bool MARCH>
 __global__ __launch_bounds__(kThreads) void k_node_pass_batch(const NodePassArgs* args,
                                                               const BlockRef* blk) {
@@ -783,7 +819,7 @@ __global__ __launch_bounds__(kThreads) void k_node_pass_batch(const NodePassArgs
     if (e.pair < 0) return;
     const NodePassArgs& a = args[e.pair];
     if (a.gate && *a.gate == kOpNone) return;
-    node_body<MARCH>(a, e.block);
+    node_body<MARCH, true, true>(a, e.block);
 }
 
 template <int TX, int TY, int TZ, int RATIO, bool POW2>
@@ -911,7 +947,8 @@ int node_march_slots() {
     int v = slot.load();
     if (v > 0) return v;
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_node_pass<true>, kThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_node_pass<true, true, true>,
+                                                     kThreads, 0) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 8;
@@ -926,10 +963,18 @@ int node_march_slots() {
 
 void launch_node_pass(const NodePassArgs& a, bool march, hipStream_t s) {
     const int blocks = 3 * a.nbx * a.nby * a.nbz;
-    if (march)
-        hipLaunchKernelGGL((k_node_pass<true>), dim3(blocks), dim3(kThreads), 0, s, a);
+    if (!march)
+        hipLaunchKernelGGL((k_node_pass<false, true, true>), dim3(blocks), dim3(kThreads), 0, s,
+                           a);
+    else if (!a.want_grad)
+        hipLaunchKernelGGL((k_node_pass<true, false, false>), dim3(blocks), dim3(kThreads), 0, s,
+                           a);
+    else if (a.gather)
+        hipLaunchKernelGGL((k_node_pass<true, true, true>), dim3(blocks), dim3(kThreads), 0, s,
+                           a);
     else
-        hipLaunchKernelGGL((k_node_pass<false>), dim3(blocks), dim3(kThreads), 0, s, a);
+        hipLaunchKernelGGL((k_node_pass<true, true, false>), dim3(blocks), dim3(kThreads), 0, s,
+                           a);
 }
 
 }  // namespace ngf
