@@ -667,159 +667,21 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
     }
 }
 
-// Node pass, 3D-tile form (small grids, where the marching form has too few
-// workgroups): one workgroup per (node tile, component) with the u box of a
-// two-node halo and the A u box of a one-node halo in LDS.
-template <int NX, int NY, int NZ>
-__device__ __forceinline__ void node_tile_body(const NodePassArgs& a, int block) {
-    // one workgroup per (node tile, component)
-    constexpr int B2X = NX + 4, B2Y = NY + 4, B2Z = NZ + 4, NB2 = B2X * B2Y * B2Z;
-    constexpr int B1X = NX + 2, B1Y = NY + 2, B1Z = NZ + 2, NB1 = B1X * B1Y * B1Z;
-    constexpr int NT = NX * NY * NZ, KT = NT / kThreads;
-    static_assert(NT % kThreads == 0, "node tile must be a multiple of the workgroup");
-    __shared__ float su[NB2];
-    __shared__ float sAu[NB1];
-    __shared__ double red[4];
-
-    const int ntile = a.nbx * a.nby * a.nbz;
-    const int bid = xcd_tile(block, 3 * ntile);
-    const int c = bid / ntile;
-    const int blk = bid - c * ntile;
-    const int bz = blk % a.nbz;
-    const int byy = (blk / a.nbz) % a.nby;
-    const int bx = blk / (a.nbz * a.nby);
-    const int n0x = bx * NX, n0y = byy * NY, n0z = bz * NZ;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int nn = nx * ny * nz;
-    const int PX = a.bx + 1, PY = a.by + 1, PZ = a.bz + 1;
-    const int NP = PX * PY * PZ;
-    const float sc = (!a.gather && a.gscale != nullptr) ? static_cast<float>(*a.gscale) : 1.0f;
-
-    const float ibx = 1.0f / a.bx, iby = 1.0f / a.by, ibz = 1.0f / a.bz;
-    // grad D of this thread's nodes: issued first, it does not depend on LDS.
-    // Gather form: add the (at most 8) image-tile partials of the node, which
-    // completes Eq. 3; scatter form: grad already holds grad D.
-    float gd[KT];
-    for (int k = 0; k < KT; ++k) {
-        const int t = threadIdx.x + k * kThreads;
-        const int lz = t % NZ, ly = (t / NZ) % NY, lx = t / (NZ * NY);
-        const int gx = n0x + lx, gy = n0y + ly, gz = n0z + lz;
-        gd[k] = 0.0f;
-        if (!a.want_grad || gx >= nx || gy >= ny || gz >= nz) continue;
-        if (!a.gather) {
-            gd[k] = a.grad[c * nn + (gx * ny + gy) * nz + gz];
-            continue;
-        }
-        const int txh = div_small(gx, a.bx, ibx), tyh = div_small(gy, a.by, iby),
-                  tzh = div_small(gz, a.bz, ibz);
-        const int rx = gx - txh * a.bx, ry = gy - tyh * a.by, rz = gz - tzh * a.bz;
-        const int nox = (rx == 0 && txh > 0) ? 2 : 1, noy = (ry == 0 && tyh > 0) ? 2 : 1,
-                  noz = (rz == 0 && tzh > 0) ? 2 : 1;
-        float acc = 0.0f;
-        for (int ox = 0; ox < nox; ++ox) {
-            const int ttx = txh - ox, llx = rx + ox * a.bx;
-            if (ttx >= a.ntx) continue;
-            for (int oy = 0; oy < noy; ++oy) {
-                const int tty = tyh - oy, lly = ry + oy * a.by;
-                if (tty >= a.nty) continue;
-                for (int oz = 0; oz < noz; ++oz) {
-                    const int ttz = tzh - oz, llz = rz + oz * a.bz;
-                    if (ttz >= a.ntz) continue;
-                    const int tile = (ttx * a.nty + tty) * a.ntz + ttz;
-                    acc += a.part[(static_cast<int64_t>(tile) * 3 + c) * NP +
-                                  (llx * PY + lly) * PZ + llz];
-                }
-            }
-        }
-        gd[k] = acc;
-    }
-
-    // u = y - X on the tile and a two-node halo (replicated ghost nodes)
-    const float* yc = a.y + c * nn;
-    const double hyc = c == 0 ? a.hyx : (c == 1 ? a.hyy : a.hyz);
-    for (int i = threadIdx.x; i < NB2; i += kThreads) {
-        const int z = i % B2Z, yy = (i / B2Z) % B2Y, x = i / (B2Z * B2Y);
-        const int gx = clampi(n0x - 2 + x, 0, nx - 1), gy = clampi(n0y - 2 + yy, 0, ny - 1),
-                  gz = clampi(n0z - 2 + z, 0, nz - 1);
-        const int gc = c == 0 ? gx : (c == 1 ? gy : gz);
-        su[i] = static_cast<float>(static_cast<double>(yc[(gx * ny + gy) * nz + gz]) -
-                                   static_cast<double>(gc) * hyc);
-    }
-    __syncthreads();
-    // A u on the tile and a one-node halo (A u of the clamped node)
-    for (int i = threadIdx.x; i < NB1; i += kThreads) {
-        const int z = i % B1Z, yy = (i / B1Z) % B1Y, x = i / (B1Z * B1Y);
-        const int gx = clampi(n0x - 1 + x, 0, nx - 1), gy = clampi(n0y - 1 + yy, 0, ny - 1),
-                  gz = clampi(n0z - 1 + z, 0, nz - 1);
-        const int p = ((gx - n0x + 2) * B2Y + (gy - n0y + 2)) * B2Z + (gz - n0z + 2);
-        const float u0 = su[p];
-        const float lx = su[p + B2Y * B2Z] - 2.0f * u0 + su[p - B2Y * B2Z];
-        const float ly = su[p + B2Z] - 2.0f * u0 + su[p - B2Z];
-        const float lz = su[p + 1] - 2.0f * u0 + su[p - 1];
-        sAu[i] = fmaf(lx, a.ihy2x, fmaf(ly, a.ihy2y, lz * a.ihy2z));
-    }
-    __syncthreads();
-    double ssum = 0.0, gmax = 0.0, g2 = 0.0;
-    for (int k = 0; k < KT; ++k) {
-        const int t = threadIdx.x + k * kThreads;
-        const int lz = t % NZ, ly = (t / NZ) % NY, lx = t / (NZ * NY);
-        const int gx = n0x + lx, gy = n0y + ly, gz = n0z + lz;
-        if (gx >= nx || gy >= ny || gz >= nz) continue;
-        const int q = ((lx + 1) * B1Y + (ly + 1)) * B1Z + (lz + 1);
-        // neighbours of the node, clamped to the grid (replicated ghost nodes)
-        const int dxp = gx + 1 < nx ? B1Y * B1Z : 0, dxm = gx > 0 ? B1Y * B1Z : 0;
-        const int dyp = gy + 1 < ny ? B1Z : 0, dym = gy > 0 ? B1Z : 0;
-        const int dzp = gz + 1 < nz ? 1 : 0, dzm = gz > 0 ? 1 : 0;
-        const float au = sAu[q];
-        ssum += static_cast<double>(au) * static_cast<double>(au);
-        if (!a.want_grad) continue;
-        const float lxx = sAu[q + dxp] - 2.0f * au + sAu[q - dxm];
-        const float lyy = sAu[q + dyp] - 2.0f * au + sAu[q - dym];
-        const float lzz = sAu[q + dzp] - 2.0f * au + sAu[q - dzm];
-        const float aau = fmaf(lxx, a.ihy2x, fmaf(lyy, a.ihy2y, lzz * a.ihy2z));
-        const float g = fmaf(a.alpha_hbary * sc, aau, gd[k]);
-        a.grad[c * nn + (gx * ny + gy) * nz + gz] = g;
-        gmax = fmax(gmax, static_cast<double>(fabsf(g)));
-        g2 += static_cast<double>(g) * static_cast<double>(g);
-    }
-    const double st = block_sum(ssum, red);
-    if (threadIdx.x == 0) a.spart[bid] = st;
-    if (a.want_grad) {
-        const double gm = block_max(gmax, red);
-        const double gq = block_sum(g2, red);
-        if (threadIdx.x == 0) {
-            a.gpart[2 * bid] = gm;
-            a.gpart[2 * bid + 1] = gq;
-        }
-    }
-}
-
-// MARCH: marching form, with the gradient and gather choice fixed at compile
-// time (GRAD, GATHER); otherwise the 3D-tile form, which reads them from the
-// arguments
-template <bool MARCH, bool GRAD, bool GATHER>
-__device__ __forceinline__ void node_body(const NodePassArgs& a, int block) {
-    if (MARCH)
-        node_march_body<kNMY, kNMZ, GRAD, GATHER>(a, block);
-    else
-        node_tile_body<kNTX, kNTY, kNTZ>(a, block);
-}
-
-template <bool MARCH, bool GRAD, bool GATHER>
+// GRAD: the gradient is wanted; GATHER: it collects the image-tile partials
+template <bool GRAD, bool GATHER>
 __global__ __launch_bounds__(kThreads) void k_node_pass(NodePassArgs a) {
     if (a.gate && *a.gate == kOpNone) return;
-    node_body<MARCH, GRAD, GATHER>(a, blockIdx.x);
+    node_march_body<kNMY, kNMZ, GRAD, GATHER>(a, blockIdx.x);
 }
 
 // the batched rounds always want the gradient gathered from the image pass
-template <bool MARCH>
 __global__ __launch_bounds__(kThreads) void k_node_pass_batch(const NodePassArgs* args,
                                                               const BlockRef* blk) {
     const BlockRef e = blk[blockIdx.x];
     if (e.pair < 0) return;
     const NodePassArgs& a = args[e.pair];
     if (a.gate && *a.gate == kOpNone) return;
-    node_body<MARCH, true, true>(a, e.block);
+    node_march_body<kNMY, kNMZ, true, true>(a, e.block);
 }
 
 template <int TX, int TY, int TZ, int RATIO, bool POW2>
@@ -922,14 +784,9 @@ void launch_image_pass_batch(const ImagePassArgs* args, const BlockRef* blk, int
 }
 
 void launch_node_pass_batch(const NodePassArgs* args, const BlockRef* blk, int nblk,
-                            bool march, hipStream_t s) {
+                            hipStream_t s) {
     if (nblk <= 0) return;
-    if (march)
-        hipLaunchKernelGGL((k_node_pass_batch<true>), dim3(nblk), dim3(kThreads), 0, s, args,
-                           blk);
-    else
-        hipLaunchKernelGGL((k_node_pass_batch<false>), dim3(nblk), dim3(kThreads), 0, s, args,
-                           blk);
+    hipLaunchKernelGGL(k_node_pass_batch, dim3(nblk), dim3(kThreads), 0, s, args, blk);
 }
 
 void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s) {
@@ -947,8 +804,8 @@ int node_march_slots() {
     int v = slot.load();
     if (v > 0) return v;
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_node_pass<true, true, true>,
-                                                     kThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_node_pass<true, true>, kThreads,
+                                                     0) !=
             hipSuccess ||
         per_cu < 1)
         per_cu = 8;
@@ -961,20 +818,14 @@ int node_march_slots() {
     return v;
 }
 
-void launch_node_pass(const NodePassArgs& a, bool march, hipStream_t s) {
+void launch_node_pass(const NodePassArgs& a, hipStream_t s) {
     const int blocks = 3 * a.nbx * a.nby * a.nbz;
-    if (!march)
-        hipLaunchKernelGGL((k_node_pass<false, true, true>), dim3(blocks), dim3(kThreads), 0, s,
-                           a);
-    else if (!a.want_grad)
-        hipLaunchKernelGGL((k_node_pass<true, false, false>), dim3(blocks), dim3(kThreads), 0, s,
-                           a);
+    if (!a.want_grad)
+        hipLaunchKernelGGL((k_node_pass<false, false>), dim3(blocks), dim3(kThreads), 0, s, a);
     else if (a.gather)
-        hipLaunchKernelGGL((k_node_pass<true, true, true>), dim3(blocks), dim3(kThreads), 0, s,
-                           a);
+        hipLaunchKernelGGL((k_node_pass<true, true>), dim3(blocks), dim3(kThreads), 0, s, a);
     else
-        hipLaunchKernelGGL((k_node_pass<true, true, false>), dim3(blocks), dim3(kThreads), 0, s,
-                           a);
+        hipLaunchKernelGGL((k_node_pass<true, false>), dim3(blocks), dim3(kThreads), 0, s, a);
 }
 
 }  // namespace ngf

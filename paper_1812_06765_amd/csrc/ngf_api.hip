@@ -94,18 +94,16 @@ bool pow2(double h) {
     int e = 0;
     return std::frexp(h, &e) == 0.5;
 }
-// node-pass workgroups: one per node tile and component
-bool node_march(const Level& L) { return L.Ny() >= kNodeMarchMin; }
-// node-pass workgroups per axis of the form the level uses
+// node-pass x chunk (node planes), fitted like the image pass's
 int node_chunk(const Level& L) {
     return fit_chunk(L.my[0], 3 * int64_t{tiles(L.my[1], kNMY)} * tiles(L.my[2], kNMZ), 1, 4,
                      node_march_slots());
 }
+// node-pass workgroups per axis (one per node tile and component)
 void node_grid(const Level& L, int nb[3]) {
-    const bool m = node_march(L);
-    nb[0] = tiles(L.my[0], m ? node_chunk(L) : kNTX);
-    nb[1] = tiles(L.my[1], m ? kNMY : kNTY);
-    nb[2] = tiles(L.my[2], m ? kNMZ : kNTZ);
+    nb[0] = tiles(L.my[0], node_chunk(L));
+    nb[1] = tiles(L.my[1], kNMY);
+    nb[2] = tiles(L.my[2], kNMZ);
 }
 int64_t node_blocks(const Level& L) {
     int nb[3];
@@ -310,7 +308,7 @@ EvalArgs eval_args(ngf_ctx* c, const Level& L, const float* R, const float* T, c
     b.nbx = nb[0];
     b.nby = nb[1];
     b.nbz = nb[2];
-    b.cxn = node_march(L) ? node_chunk(L) : kNTX;
+    b.cxn = node_chunk(L);
     b.hyx = L.hy[0];
     b.hyy = L.hy[1];
     b.hyz = L.hy[2];
@@ -366,7 +364,7 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
         launch();
     }
     HIPCHK(c, hipGetLastError());
-    launch_node_pass(e.b, node_march(L), c->stream);
+    launch_node_pass(e.b, c->stream);
     HIPCHK(c, hipGetLastError());
     launch_reduce(e.r, c->stream);
     HIPCHK(c, hipGetLastError());
@@ -1139,7 +1137,7 @@ ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], con
     b.nbx = nb[0];
     b.nby = nb[1];
     b.nbz = nb[2];
-    b.cxn = node_march(P) ? node_chunk(P) : kNTX;
+    b.cxn = node_chunk(P);
     b.hyx = P.hy[0];
     b.hyy = P.hy[1];
     b.hyz = P.hy[2];
@@ -1152,7 +1150,7 @@ ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], con
     b.want_grad = grad_y ? 1 : 0;
     b.gather = 0;
     b.gscale = gscale;
-    launch_node_pass(b, node_march(P), c->stream);
+    launch_node_pass(b, c->stream);
     HIPCHK(c, hipGetLastError());
     ReduceArgs rd{};
     rd.dpart = c->dpart;

@@ -97,7 +97,7 @@ struct LevelTables {
         size_t off = 0;
     };
     std::vector<Group> groups;
-    std::vector<BlockRef> node_blk[2], vec_blk;  // node pass: 3D-tile form, marching form
+    std::vector<BlockRef> node_blk, vec_blk;
 };
 
 template <class T>
@@ -204,7 +204,7 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
                 g = &t.groups.back();
             }
             add_blocks(g->blk, i, geometry(lv, lv.variant).ntiles());
-            add_blocks(t.node_blk[node_march(lv) ? 1 : 0], i, node_blocks(lv));
+            add_blocks(t.node_blk, i, node_blocks(lv));
             add_blocks(t.vec_blk, i, v.nblocks);
         }
         // upload the tables (one device buffer, grown outside the rounds)
@@ -214,7 +214,7 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
         const size_t o_red0 = put(host, t.red0), o_red1 = put(host, t.red1);
         const size_t o_vec = put(host, t.vec);
         for (auto& g : t.groups) g.off = put(host, g.blk);
-        const size_t o_nblk[2] = {put(host, t.node_blk[0]), put(host, t.node_blk[1])};
+        const size_t o_nblk = put(host, t.node_blk);
         const size_t o_vblk = put(host, t.vec_blk);
         const size_t o_ctl = align_up(host.size(), 256);
         host.resize(o_ctl + np * sizeof(LbCtl));
@@ -249,10 +249,9 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
         const auto* vec = static_cast<const LbVecArgs*>(P(o_vec));
         const int nvb = static_cast<int>(t.vec_blk.size());
         auto node_stage = [&](size_t o_args) {
-            for (int f = 0; f < 2; ++f)
-                launch_node_pass_batch(static_cast<const NodePassArgs*>(P(o_args)),
-                                       static_cast<const BlockRef*>(P(o_nblk[f])),
-                                       static_cast<int>(t.node_blk[f].size()), f == 1, s);
+            launch_node_pass_batch(static_cast<const NodePassArgs*>(P(o_args)),
+                                   static_cast<const BlockRef*>(P(o_nblk)),
+                                   static_cast<int>(t.node_blk.size()), s);
         };
         // level start: evaluation at the start point, state reset
         image_stage(o_img0);

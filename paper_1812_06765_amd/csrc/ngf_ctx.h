@@ -112,7 +112,6 @@ struct Geo {
 Geo geometry(const Level& L, int variant);
 int tiles(int m, int t);
 int64_t node_blocks(const Level& L);
-bool node_march(const Level& L);
 int node_chunk(const Level& L);
 ngf_status fail(ngf_ctx* c, ngf_status s, const std::string& msg);
 

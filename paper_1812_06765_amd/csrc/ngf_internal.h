@@ -21,12 +21,9 @@ constexpr int kTX = 8, kTY = 8, kTZ = 32;
 // Marching image pass: (y, z) tile of kMY x (32 or 64); the x chunk is a
 // run-time choice.
 constexpr int kMY = 16;
-// Node pass: marching form ((y, z) tile of kNMY x kNMZ nodes, x chunk fitted
-// to the grid and the device) from kNodeMarchMin nodes on, 3D-tile form
-// (kNTX x kNTY x kNTZ nodes) below.
+// Node pass: (y, z) tile of kNMY x kNMZ nodes, marching along x in a chunk
+// fitted to the grid and the device.
 constexpr int kNMY = 8, kNMZ = 32;
-constexpr int kNTX = 4, kNTY = 8, kNTZ = 32;
-constexpr int64_t kNodeMarchMin = int64_t{1} << 20;
 
 // Image-pass variants the autotuner chooses from: the 3D-tile kernel at three
 // tile sizes, and the marching kernel with in-plane tile 16 x 64 or 16 x 32
@@ -270,7 +267,7 @@ void launch_image_pass_batch(const ImagePassArgs* args, const BlockRef* blk, int
 void launch_image_march_batch(const ImagePassArgs* args, const BlockRef* blk, int nblk,
                               int ratio, int variant, bool pow2, hipStream_t s);
 void launch_node_pass_batch(const NodePassArgs* args, const BlockRef* blk, int nblk,
-                            bool march, hipStream_t s);
+                            hipStream_t s);
 void launch_reduce_batch(const ReduceArgs* args, int npairs, hipStream_t s);
 void launch_lb_init_batch(const LbVecArgs* args, int npairs, hipStream_t s);
 void launch_lb_plan_batch(const LbVecArgs* args, int npairs, hipStream_t s);
@@ -287,7 +284,7 @@ void launch_identity(float* y, int nx, int ny, int nz, double hx, double hy, dou
 void launch_prolongate(const float* yc, float* yf, int cx, int cy, int cz, hipStream_t s);
 void launch_image_pass(const ImagePassArgs& a, int ratio, int variant, hipStream_t s);
 void launch_image_march(const ImagePassArgs& a, int ratio, int tz, int cx, hipStream_t s);
-void launch_node_pass(const NodePassArgs& a, bool march, hipStream_t s);
+void launch_node_pass(const NodePassArgs& a, hipStream_t s);
 void launch_reduce(const ReduceArgs& a, hipStream_t s);
 void launch_check_finite(const float* v, int64_t n, int* flag, hipStream_t s);
 void launch_fill(float* p, int64_t n, float v, hipStream_t s);
