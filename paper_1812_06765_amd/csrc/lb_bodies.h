@@ -17,7 +17,7 @@ constexpr int kDots = 6 * kSlots + 6;
 // inner products formed per update
 static_assert(kDots <= 64, "one lane per inner product in the Gram update");
 
-constexpr int kLbBlocks = 1024;
+constexpr int kLbBlocks = 768;
 
 __device__ inline double lb_wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -140,14 +140,15 @@ __device__ inline void lb_solve_one(LbState* st, double* jds, SolveLds& w) {
 }
 
 // d = sum_l coef_l b_l over the active basis; yt = y + d.  Four elements per
-// thread and iteration (16-byte loads), then a scalar tail.
+// thread and iteration (16-byte loads), then a scalar tail.  The pairs are
+// visited in a loop (two history streams at a time): unrolling it over all
+// pairs measured slower.
 __device__ __forceinline__ void lb_combine_body(const LbState* st,
-                                                         const float* __restrict__ hist,
-                                                         int64_t ld, int64_t n,
-                                                         const float* __restrict__ y,
-                                                         const float* __restrict__ g,
-                                                         float* __restrict__ d,
-                                                         float* __restrict__ yt, int block, int nblocks) {
+                                                const float* __restrict__ hist, int64_t ld,
+                                                int64_t n, const float* __restrict__ y,
+                                                const float* __restrict__ g,
+                                                float* __restrict__ d, float* __restrict__ yt,
+                                                int block, int nblocks) {
     __shared__ double cs[kSlots], ct[kSlots];
     __shared__ int sl[kSlots];
     __shared__ double cg;
@@ -253,37 +254,50 @@ __device__ __forceinline__ void lb_dots_pass(const int* sl, int fs, float* __res
         acc[6 * C + 4] += td * gd;
         acc[6 * C + 5] += gd * gd;
     };
-    const int64_t n2 = n >> 1;
+    const int64_t n4 = n >> 2;
     const int64_t stride = static_cast<int64_t>(nblocks) * kThreads;
-    for (int64_t q = block * static_cast<int64_t>(kThreads) + threadIdx.x; q < n2;
+    const float* hk[C > 0 ? C : 1];
+#pragma unroll
+    for (int k = 0; k < C; ++k) hk[k] = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
+    for (int64_t q = block * static_cast<int64_t>(kThreads) + threadIdx.x; q < n4;
          q += stride) {
-        const float2 yv = reinterpret_cast<const float2*>(y)[q];
-        const float2 ytv = reinterpret_cast<const float2*>(yt)[q];
-        const float2 gv = reinterpret_cast<const float2*>(g)[q];
-        const float2 gtv = reinterpret_cast<const float2*>(gt)[q];
-        const float2 s = make_float2(ytv.x - yv.x, ytv.y - yv.y);
-        const float2 t = make_float2(gtv.x - gv.x, gtv.y - gv.y);
-        reinterpret_cast<float2*>(sn)[q] = s;
-        reinterpret_cast<float2*>(tn)[q] = t;
-        if (ACCEPT) {
-            reinterpret_cast<float2*>(y)[q] = ytv;
-            reinterpret_cast<float2*>(g)[q] = gtv;
-        }
-        float a0[C > 0 ? C : 1], b0[C > 0 ? C : 1], a1[C > 0 ? C : 1], b1[C > 0 ? C : 1];
+        const float4 yv = reinterpret_cast<const float4*>(y)[q];
+        const float4 ytv = reinterpret_cast<const float4*>(yt)[q];
+        const float4 gv = reinterpret_cast<const float4*>(g)[q];
+        const float4 gtv = reinterpret_cast<const float4*>(gt)[q];
+        float4 av[C > 0 ? C : 1], bv[C > 0 ? C : 1];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
-            const float2 av = reinterpret_cast<const float2*>(sk)[q];
-            const float2 bv = reinterpret_cast<const float2*>(sk + ld)[q];
-            a0[k] = av.x;
-            a1[k] = av.y;
-            b0[k] = bv.x;
-            b1[k] = bv.y;
+            av[k] = reinterpret_cast<const float4*>(hk[k])[q];
+            bv[k] = reinterpret_cast<const float4*>(hk[k] + ld)[q];
+        }
+        const float4 s = make_float4(ytv.x - yv.x, ytv.y - yv.y, ytv.z - yv.z, ytv.w - yv.w);
+        const float4 t = make_float4(gtv.x - gv.x, gtv.y - gv.y, gtv.z - gv.z, gtv.w - gv.w);
+        reinterpret_cast<float4*>(sn)[q] = s;
+        reinterpret_cast<float4*>(tn)[q] = t;
+        if (ACCEPT) {
+            reinterpret_cast<float4*>(y)[q] = ytv;
+            reinterpret_cast<float4*>(g)[q] = gtv;
+        }
+        float a0[C > 0 ? C : 1], b0[C > 0 ? C : 1], a1[C > 0 ? C : 1], b1[C > 0 ? C : 1];
+        float a2[C > 0 ? C : 1], b2[C > 0 ? C : 1], a3[C > 0 ? C : 1], b3[C > 0 ? C : 1];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            a0[k] = av[k].x;
+            a1[k] = av[k].y;
+            a2[k] = av[k].z;
+            a3[k] = av[k].w;
+            b0[k] = bv[k].x;
+            b1[k] = bv[k].y;
+            b2[k] = bv[k].z;
+            b3[k] = bv[k].w;
         }
         add(s.x, t.x, gtv.x, a0, b0);
         add(s.y, t.y, gtv.y, a1, b1);
+        add(s.z, t.z, gtv.z, a2, b2);
+        add(s.w, t.w, gtv.w, a3, b3);
     }
-    for (int64_t i = 2 * n2 + block * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
+    for (int64_t i = 4 * n4 + block * static_cast<int64_t>(kThreads) + threadIdx.x; i < n;
          i += stride) {
         const float yti = yt[i], gti = gt[i];
         const float s = yti - y[i];
@@ -321,8 +335,8 @@ __device__ __forceinline__ void lb_dots_pass(const int* sl, int fs, float* __res
 
 // Forms the new pair s = yt - y, t = gt - g in the free slot and all inner
 // products of {s, t, gt} with the stored pairs and with each other.
-// Per-block float64 partials: dotpart[block][kDots].  Two elements per
-// thread and iteration (8-byte loads), then a scalar tail.
+// Per-block float64 partials: dotpart[block][kDots].  Four elements per
+// thread and iteration (16-byte loads), then a scalar tail.
 // CMAX: the largest pair count the kernel is built for (the L-BFGS memory
 // rounded up to 5 or 8); registers are allocated for the largest case.
 template <bool ACCEPT, int CMAX>
