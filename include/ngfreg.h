@@ -146,7 +146,7 @@ ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
                              const ngf_grid* g, int32_t host_ptrs);
 
 /* Image-grid kernel of the evaluation.  `variant`: -2 = by level size (no
- * timing runs: at least 1 Mi voxels -> 11, else 8);
+ * timing runs: at least 8 Mi voxels -> 13, at least 1 Mi -> 11, else 8);
  * -1 = autotune (default:
  * at ngf_build_pyramid every level times each variant over three evaluations
  * at the identity and keeps the fastest; choices are cached per image shape
@@ -158,7 +158,8 @@ ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
  * over 16x64 or 16x32 tiles in chunks of 16 planes; 11, 12 = x-marching over
  * 16x32 or 16x64 tiles in chunks whose length is fitted to the level's shape
  * and to the number of workgroups the device holds at once (so that the
- * launch fills the device in as few full rounds as possible).  All variants
+ * launch fills the device in as few full rounds as possible); 13 = the same
+ * over 32x32 tiles with 512-thread workgroups.  All variants
  * compute the same quantities; only the summation order of the P^T partial
  * sums differs.  Applies at once to a built pyramid.  ngf_get_kernel reports
  * a level's choice. */

@@ -53,15 +53,23 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// threads of the marching workgroup: 256 (512 for the 32 x 32 tile, so that
+// every thread keeps two voxels of a plane)
+template <int TY, int TZ>
+constexpr int march_threads() {
+    return TY == 32 && TZ == 32 ? 512 : kThreads;
+}
+
 template <int TY, int TZ, int R>
 struct March {
+    static constexpr int NT = march_threads<TY, TZ>();
     static constexpr int H2Y = TY + 4, H2Z = TZ + 4, NH2 = H2Y * H2Z;
     static constexpr int H1Y = TY + 2, H1Z = TZ + 2;
-    static constexpr int NI = TY * TZ, KP = NI / kThreads;
+    static constexpr int NI = TY * TZ, KP = NI / NT;
     static constexpr int NRING2 = NH2 - NI;             // in-plane halo-2 ring
     static constexpr int NRING1 = 2 * TZ + 2 * TY;      // in-plane face halo-1 ring
     static constexpr int BY = TY / R, BZ = TZ / R, PY = BY + 1, PZ = BZ + 1;
-    static constexpr int NOUT = 3 * PY * PZ, KO = (NOUT + kThreads - 1) / kThreads;
+    static constexpr int NOUT = 3 * PY * PZ, KO = (NOUT + NT - 1) / NT;
     static constexpr int NQY = TY / R + 4, NQZ = TZ / R + 4, NQ = NQY * NQZ;
     static constexpr int GZ = 3 * TY * PZ;
     // LDS layout (floats)
@@ -74,10 +82,10 @@ struct March {
     static constexpr int SZ_G = (3 * NI > 6 * NQ ? 3 * NI : 6 * NQ);
     static constexpr int OFF_GZ = OFF_G + SZ_G;               // GZ
     static constexpr int LDS_FLOATS = OFF_GZ + GZ;
-    static_assert(NI % kThreads == 0, "tile plane must be a multiple of the workgroup");
+    static_assert(NI % NT == 0, "tile plane must be a multiple of the workgroup");
     static_assert(TY % R == 0 && TZ % R == 0, "ratio-aligned tile");
     static_assert((OFF_G % 2) == 0, "double alignment of Q");
-    static_assert(NRING1 <= kThreads, "face ring in one pass");
+    static_assert(NRING1 <= NT, "face ring in one pass");
     static_assert(LDS_FLOATS * 4 <= 81920, "two workgroups per CU");
 };
 
@@ -108,6 +116,7 @@ __device__ inline void ring1_pos_t(int s, int& b1y, int& b1z) {
 template <int TY, int TZ, int R, bool GRAD, bool POW2>
 __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int block) {
     using L = March<TY, TZ, R>;
+    constexpr int NT = L::NT;
     auto ring1_pos = [](int s, int& b1y, int& b1z) { ring1_pos_t<TY, TZ>(s, b1y, b1z); };
     extern __shared__ float smem[];
     float* sTy = smem + L::OFF_TY;
@@ -118,7 +127,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
     float* sG = smem + L::OFF_G;
     double* sQ = reinterpret_cast<double*>(smem + L::OFF_G);
     float* sGz = smem + L::OFF_GZ;
-    __shared__ double red[4];
+    __shared__ double red[NT / 64];
 
     // tile decode, spread over the XCDs so that neighbouring tiles share an L2
     const int tile = xcd_tile(block, a.ntx * a.nty * a.ntz);
@@ -144,14 +153,14 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
     // The node values are loaded into registers one phase ahead of the store
     // (load_q during the warp phase, store_q after the last read of sG), so
     // their latency overlaps the warp's gathers.
-    constexpr int KQ = (3 * L::NQ + kThreads - 1) / kThreads;
+    constexpr int KQ = (3 * L::NQ + NT - 1) / NT;
     float qv0[KQ], qv1[KQ];
     auto load_q = [&](int p) {
         const int pc = clampi(p, 0, mx - 1);
         const int jx = node_of<R>(pc);
 #pragma unroll
         for (int k = 0; k < KQ; ++k) {
-            const int i = threadIdx.x + k * kThreads;
+            const int i = threadIdx.x + k * NT;
             if (i < 3 * L::NQ) {
                 const int c = i / L::NQ;
                 const int r = i - c * L::NQ;
@@ -169,7 +178,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         const double w1 = w1_of<R>(pc), w0 = 1.0 - w1;
 #pragma unroll
         for (int k = 0; k < KQ; ++k) {
-            const int i = threadIdx.x + k * kThreads;
+            const int i = threadIdx.x + k * NT;
             if (i < 3 * L::NQ)
                 sQ[i] = w0 * static_cast<double>(qv0[k]) + w1 * static_cast<double>(qv1[k]);
         }
@@ -252,7 +261,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         if (lx < 0 || lx > CX / R) return;
 #pragma unroll
         for (int o = 0; o < L::KO; ++o) {
-            const int i = threadIdx.x + o * kThreads;
+            const int i = threadIdx.x + o * NT;
             if (i < L::NOUT) {
                 const int c = i / (L::PY * L::PZ);
                 const int r = i - c * (L::PY * L::PZ);
@@ -273,12 +282,12 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         const bool wgrad = GRAD && pw >= x0 && pw < xend;
 #pragma unroll
         for (int kk = 0; kk < L::KP; ++kk) {
-            const int t = threadIdx.x + kk * kThreads;
+            const int t = threadIdx.x + kk * NT;
             const int ly = t / TZ, lz = t % TZ;
             const int gy = min(y0 + ly, my - 1), gz = min(z0 + lz, mz - 1);
             Ty[(ly + 2) * L::H2Z + (lz + 2)] = warp_at(pwc, gy, gz, wgrad ? dTw[kk] : nullptr);
         }
-        for (int s = threadIdx.x; s < L::NRING2; s += kThreads) {
+        for (int s = threadIdx.x; s < L::NRING2; s += NT) {
             int by, bz;
             if (s < 4 * L::H2Z) {
                 const int row = s / L::H2Z;
@@ -306,7 +315,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
             for (int kk = 0; kk <= L::KP; ++kk) {
                 int b1y, b1z;
                 if (kk < L::KP) {
-                    const int t = threadIdx.x + kk * kThreads;
+                    const int t = threadIdx.x + kk * NT;
                     b1y = t / TZ + 1;
                     b1z = t % TZ + 1;
                 } else {
@@ -320,7 +329,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         }
         if (vok) {
             const uint32_t s0 = static_cast<uint32_t>(pv) * plane4;
-            for (int i = threadIdx.x; i < L::NH2; i += kThreads) {
+            for (int i = threadIdx.x; i < L::NH2; i += NT) {
                 const int by = i / L::H2Z, bz = i - by * L::H2Z;
                 const int gy = clampi(y0 - 2 + by, 0, my - 1), gz = clampi(z0 - 2 + bz, 0, mz - 1);
                 sR[i] = bload(rR, static_cast<uint32_t>(gy * mz + gz) * 4u, s0);
@@ -393,7 +402,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
             };
 #pragma unroll
             for (int kk = 0; kk < L::KP; ++kk) {
-                const int t = threadIdx.x + kk * kThreads;
+                const int t = threadIdx.x + kk * NT;
                 ngf_at(t / TZ + 1, t % TZ + 1, true, rxm[kk], rxp[kk]);
             }
             if (GRAD && threadIdx.x < L::NRING1) {
@@ -421,7 +430,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
             const float* Vz = sVz + (pe & 1) * (TY * L::H1Z);
 #pragma unroll
             for (int kk = 0; kk < L::KP; ++kk) {
-                const int t = threadIdx.x + kk * kThreads;
+                const int t = threadIdx.x + kk * NT;
                 const int ly = t / TZ, lz = t % TZ;
                 const float vxm = Vm ? Vm[t] : -V0[t];
                 const float vxp = Vp ? Vp[t] : -V0[t];
@@ -442,7 +451,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         // weights (2k+1)/(2R) rising then falling (the two halves of a cell)
         const int jz0 = z0 / R, jy0 = y0 / R;
         if (eok) {
-            for (int i = threadIdx.x; i < L::GZ; i += kThreads) {
+            for (int i = threadIdx.x; i < L::GZ; i += NT) {
                 const int nz = i % L::PZ;
                 const float* g = sG + (i / L::PZ) * TZ;  // (c, ly) row
                 float acc = 0.0f;
@@ -475,7 +484,7 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
             }
 #pragma unroll
             for (int o = 0; o < L::KO; ++o) {
-                const int i = threadIdx.x + o * kThreads;
+                const int i = threadIdx.x + o * NT;
                 if (i < L::NOUT) {
                     const int nz = i % L::PZ;
                     const int ny = (i / L::PZ) % L::PY;
@@ -516,17 +525,22 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
         __syncthreads();
         if ((threadIdx.x & 63) == 0) red[w] = v;
         __syncthreads();
-        return (red[0] + red[1]) + (red[2] + red[3]);
+        if constexpr (NT == 256)
+            return (red[0] + red[1]) + (red[2] + red[3]);
+        else
+            return ((red[0] + red[1]) + (red[2] + red[3])) +
+                   ((red[4] + red[5]) + (red[6] + red[7]));
     }();
     if (threadIdx.x == 0) a.dpart[tile] = dt;
 }
 
 // The 16 x 32 tile needs 36 KiB of LDS, so up to four workgroups fit a CU;
 // its registers are held to four waves per SIMD (128 VGPRs, no spills).  The
-// 16 x 64 tile is limited to two workgroups per CU by LDS anyway.
+// 32 x 32 tile (512 threads, 68 KiB) fits two workgroups, also four waves
+// per SIMD.  The 16 x 64 tile is limited to two workgroups per CU by LDS.
 template <int TY, int TZ, int R, bool GRAD, bool POW2>
-__global__ __launch_bounds__(kThreads, TZ == 32 ? 4 : 2) void k_image_march(ImagePassArgs a,
-                                                                            int CX) {
+__global__ __launch_bounds__((march_threads<TY, TZ>()), TZ == 32 ? 4 : 2) void k_image_march(
+    ImagePassArgs a, int CX) {
     if (a.gate && *a.gate == kOpNone) return;
     march_body<TY, TZ, R, GRAD, POW2>(a, CX, blockIdx.x);
 }
@@ -535,7 +549,7 @@ __global__ __launch_bounds__(kThreads, TZ == 32 ? 4 : 2) void k_image_march(Imag
 // The batched form indexes its arguments per block and needs a few more
 // registers: at four waves per SIMD a few of them spill to scratch.
 template <int TY, int TZ, int R, bool POW2>
-__global__ __launch_bounds__(kThreads, TZ == 32 ? 4 : 2) void k_image_march_batch(
+__global__ __launch_bounds__((march_threads<TY, TZ>()), TZ == 32 ? 4 : 2) void k_image_march_batch(
     const ImagePassArgs* args, const BlockRef* blk) {
     const BlockRef e = blk[blockIdx.x];
     if (e.pair < 0) return;
@@ -550,10 +564,10 @@ void launch_march_batch_t(const ImagePassArgs* args, const BlockRef* blk, int nb
     using L = March<TY, TZ, R>;
     const size_t lds = sizeof(float) * L::LDS_FLOATS;
     if (pow2)
-        hipLaunchKernelGGL((k_image_march_batch<TY, TZ, R, true>), dim3(nblk), dim3(kThreads),
+        hipLaunchKernelGGL((k_image_march_batch<TY, TZ, R, true>), dim3(nblk), dim3(L::NT),
                            lds, s, args, blk);
     else
-        hipLaunchKernelGGL((k_image_march_batch<TY, TZ, R, false>), dim3(nblk), dim3(kThreads),
+        hipLaunchKernelGGL((k_image_march_batch<TY, TZ, R, false>), dim3(nblk), dim3(L::NT),
                            lds, s, args, blk);
 }
 
@@ -566,17 +580,17 @@ void launch_march_t(const ImagePassArgs& a, int cx, hipStream_t s) {
     if (a.want_grad) {
         if (a.pow2h)
             hipLaunchKernelGGL((k_image_march<TY, TZ, R, true, true>), dim3(blocks),
-                               dim3(kThreads), lds, s, a, cx);
+                               dim3(L::NT), lds, s, a, cx);
         else
             hipLaunchKernelGGL((k_image_march<TY, TZ, R, true, false>), dim3(blocks),
-                               dim3(kThreads), lds, s, a, cx);
+                               dim3(L::NT), lds, s, a, cx);
     } else {
         if (a.pow2h)
             hipLaunchKernelGGL((k_image_march<TY, TZ, R, false, true>), dim3(blocks),
-                               dim3(kThreads), lds, s, a, cx);
+                               dim3(L::NT), lds, s, a, cx);
         else
             hipLaunchKernelGGL((k_image_march<TY, TZ, R, false, false>), dim3(blocks),
-                               dim3(kThreads), lds, s, a, cx);
+                               dim3(L::NT), lds, s, a, cx);
     }
 }
 
@@ -586,7 +600,13 @@ void launch_march_t(const ImagePassArgs& a, int cx, hipStream_t s) {
 void launch_image_march_batch(const ImagePassArgs* args, const BlockRef* blk, int nblk,
                               int ratio, int variant, bool pow2, hipStream_t s) {
     if (nblk <= 0) return;
-    if (march_tz(variant) == 64) {
+    const int ty = march_ty(variant), tz = march_tz(variant);
+    if (ty == 32) {
+        if (ratio == 2)
+            launch_march_batch_t<32, 32, 2>(args, blk, nblk, pow2, s);
+        else if (ratio == 4)
+            launch_march_batch_t<32, 32, 4>(args, blk, nblk, pow2, s);
+    } else if (tz == 64) {
         if (ratio == 2)
             launch_march_batch_t<kMY, 64, 2>(args, blk, nblk, pow2, s);
         else if (ratio == 4)
@@ -599,26 +619,33 @@ void launch_image_march_batch(const ImagePassArgs* args, const BlockRef* blk, in
     }
 }
 
-int image_march_slots(int tz) {
+namespace {
+template <int TY, int TZ>
+int march_per_cu() {
+    using L = March<TY, TZ, 2>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_image_march<TY, TZ, 2, true, true>,
+                                                     L::NT, sizeof(float) * L::LDS_FLOATS) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return per_cu;
+}
+}  // namespace
+
+int image_march_slots(int ty, int tz) {
     // occupancy per CU, queried once per device and tile (the ratio-2
     // instance stands for both ratios: same launch bounds, same LDS)
-    static std::atomic<int> cache[16][2];
+    static std::atomic<int> cache[16][3];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
-    std::atomic<int>& slot = cache[dev & 15][tz == 64 ? 1 : 0];
+    const int form = ty == 32 ? 2 : (tz == 64 ? 1 : 0);
+    std::atomic<int>& slot = cache[dev & 15][form];
     int v = slot.load();
     if (v > 0) return v;
-    int per_cu = 0, cus = 0;
-    hipError_t e;
-    if (tz == 64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, k_image_march<kMY, 64, 2, true, true>, kThreads,
-            sizeof(float) * March<kMY, 64, 2>::LDS_FLOATS);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, k_image_march<kMY, 32, 2, true, true>, kThreads,
-            sizeof(float) * March<kMY, 32, 2>::LDS_FLOATS);
-    if (e != hipSuccess || per_cu < 1) per_cu = tz == 64 ? 2 : 3;
+    const int per_cu = form == 2 ? march_per_cu<32, 32>()
+                                 : (form == 1 ? march_per_cu<kMY, 64>() : march_per_cu<kMY, 32>());
+    int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus < 1)
         cus = 256;
@@ -628,8 +655,14 @@ int image_march_slots(int tz) {
     return v;
 }
 
-void launch_image_march(const ImagePassArgs& a, int ratio, int tz, int cx, hipStream_t s) {
-    if (tz == 64) {
+void launch_image_march(const ImagePassArgs& a, int ratio, int ty, int tz, int cx,
+                        hipStream_t s) {
+    if (ty == 32) {
+        if (ratio == 2)
+            launch_march_t<32, 32, 2>(a, cx, s);
+        else if (ratio == 4)
+            launch_march_t<32, 32, 4>(a, cx, s);
+    } else if (tz == 64) {
         if (ratio == 2)
             launch_march_t<kMY, 64, 2>(a, cx, s);
         else if (ratio == 4)

@@ -72,12 +72,12 @@ Geo geometry(const Level& L, int variant) {
         g.ty = tile3d_y(variant);
         g.tz = tile3d_z(variant);
     } else {
-        g.ty = kMY;
+        g.ty = march_ty(variant);
         g.tz = march_tz(variant);
         g.tx = march_cx(variant);
         if (g.tx == 0)
             g.tx = fit_chunk(L.m[0], int64_t{tiles(L.m[1], g.ty)} * tiles(L.m[2], g.tz), 4, 4,
-                             image_march_slots(g.tz));
+                             image_march_slots(g.ty, g.tz));
     }
     g.ntx = tiles(L.m[0], g.tx);
     g.nty = tiles(L.m[1], g.ty);
@@ -348,7 +348,8 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
         if (!is_march(L.variant))
             launch_image_pass(e.a, c->p.ratio, L.variant, c->stream);
         else
-            launch_image_march(e.a, c->p.ratio, march_tz(L.variant), e.a.cx, c->stream);
+            launch_image_march(e.a, c->p.ratio, march_ty(L.variant), march_tz(L.variant), e.a.cx,
+                               c->stream);
     };
     int li = -1;
     if (c->prof)
@@ -414,7 +415,9 @@ void tune_cache_store(const std::string& key, int v) {
 // work): the choices the timed selection makes on gfx950 at cubic levels of
 // 256^3 and 128^3, and of 64^3 and below.
 int variant_by_size(const Level& L) {
-    return L.N() >= (int64_t{1} << 20) ? kMarch32Fit : kTile3DTiny;
+    const int64_t n = L.N();
+    if (n >= (int64_t{8} << 20)) return kMarchSqFit;
+    return n >= (int64_t{1} << 20) ? kMarch32Fit : kTile3DTiny;
 }
 
 // Pick the image-pass variant of every level: forced, cached for this shape,

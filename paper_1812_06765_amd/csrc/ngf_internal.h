@@ -37,11 +37,12 @@ enum Variant {
     kTile3DTiny = 8,   // 3D tile of 4 x 4 x 16 voxels (many workgroups for small levels)
     kMarch64x16 = 9, kMarch32x16 = 10,
     kMarch32Fit = 11, kMarch64Fit = 12,
-    kNumVariants = 13
+    kMarchSqFit = 13,  // 32 x 32 (y, z) tile, 512-thread workgroups, fitted x chunk
+    kNumVariants = 14
 };
 constexpr int kVariantBySize = -2;  // selection rule instead of timed selection
 inline bool is_march(int v) {
-    return (v >= kMarch64x8 && v <= kMarch32x32) || (v >= kMarch64x16 && v <= kMarch64Fit);
+    return (v >= kMarch64x8 && v <= kMarch32x32) || (v >= kMarch64x16 && v <= kMarchSqFit);
 }
 // 3D-tile extents (x, y, z) of the 3D-tile variants
 inline int tile3d_x(int v) { return v == kTile3D ? 8 : 4; }
@@ -57,9 +58,10 @@ inline int march_cx(int v) {
 inline int march_tz(int v) {
     return (v <= kMarch64x32 || v == kMarch64x16 || v == kMarch64Fit) ? 64 : 32;
 }
-// Workgroups of the marching kernel with (y, z) tile kMY x tz that the
+inline int march_ty(int v) { return v == kMarchSqFit ? 32 : kMY; }
+// Workgroups of the marching kernel with (y, z) tile ty x tz that the
 // current device holds at once (occupancy per CU times the CU count).
-int image_march_slots(int tz);
+int image_march_slots(int ty, int tz);
 // Chunk length along x for a launch of `across` x-columns of workgroups over
 // an axis of `len` planes: the multiple of `step` (at least `lo`) that
 // minimises the launch's predicted duration, taken as the number of full
@@ -283,7 +285,8 @@ void launch_identity(float* y, int nx, int ny, int nz, double hx, double hy, dou
                      hipStream_t s);
 void launch_prolongate(const float* yc, float* yf, int cx, int cy, int cz, hipStream_t s);
 void launch_image_pass(const ImagePassArgs& a, int ratio, int variant, hipStream_t s);
-void launch_image_march(const ImagePassArgs& a, int ratio, int tz, int cx, hipStream_t s);
+void launch_image_march(const ImagePassArgs& a, int ratio, int ty, int tz, int cx,
+                        hipStream_t s);
 void launch_node_pass(const NodePassArgs& a, hipStream_t s);
 void launch_reduce(const ReduceArgs& a, hipStream_t s);
 void launch_check_finite(const float* v, int64_t n, int* flag, hipStream_t s);

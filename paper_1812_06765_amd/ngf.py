@@ -357,7 +357,8 @@ class Context:
     # -- kernel choice --------------------------------------------------------
     VARIANTS = {"by_size": -2, "auto": -1, "tile3d": 0, "march64x8": 1, "march64x20": 2, "march64x32": 3,
                 "march32x8": 4, "march32x20": 5, "march32x32": 6, "tile3d_small": 7, "tile3d_tiny": 8,
-                "march64x16": 9, "march32x16": 10, "march32fit": 11, "march64fit": 12}
+                "march64x16": 9, "march32x16": 10, "march32fit": 11, "march64fit": 12,
+                "march32sq": 13}
 
     def set_kernel(self, variant):
         """Image-pass variant: 'auto' (autotune), 'by_size' (size rule), a name
