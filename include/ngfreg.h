@@ -200,6 +200,23 @@ ngf_status ngf_eval_J_grad(ngf_ctx* ctx, int32_t level, const float* y, double* 
 /* Device address of the double[3] {J, D, S} written by the last evaluation. */
 ngf_status ngf_eval_J_device(ngf_ctx* ctx, const double** JDS);
 
+/* The same objective and gradient as ngf_eval_J_grad (Eq. 1-3, Sec. 2.2)
+ * with every value in float64, for studies of the float32 arithmetic the
+ * paper uses (Sec. 3 compares float32 GPU results with float64 CPU ones):
+ * exact rational grid-conversion weights, float64 warp, NGF terms, adjoint,
+ * P^T and curvature; the level's float32 images are widened exactly.
+ *   y      device float64 [3][m^y_x][m^y_y][m^y_z], the deformation
+ *   J      host double, receives J(y); may be NULL (then nothing synchronises)
+ *   grad   device float64 like y, receives grad J(y); may be NULL
+ *   DS     host double[2], receives (D, S); may be NULL
+ * Plain unfused kernels (about 56 bytes of float64 scratch per voxel); the
+ * scratch is allocated on the first call and grown when a later call needs a
+ * larger level, so this call is not for graph capture.  Reductions have a
+ * fixed order: equal inputs give equal outputs.  Not affected by
+ * ngf_set_kernel. */
+ngf_status ngf_eval_J_grad_f64(ngf_ctx* ctx, int32_t level, const double* y, double* J,
+                               double* grad, double* DS);
+
 /* Start L-BFGS (Sec. 2.1; Nocedal 1980) on a level from y0 (device): drops the
  * stored pairs and evaluates J and grad J at y0.  Synchronises. */
 ngf_status ngf_lbfgs_reset(ngf_ctx* ctx, int32_t level, const float* y0);

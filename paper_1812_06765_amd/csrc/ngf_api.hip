@@ -618,7 +618,7 @@ void ngf_destroy(ngf_ctx* c) {
                     static_cast<void*>(c->lyt), static_cast<void*>(c->lgt),
                     static_cast<void*>(c->ld), static_cast<void*>(c->ltmp),
                     static_cast<void*>(c->hist), static_cast<void*>(c->st),
-                    static_cast<void*>(c->dotpart)})
+                    static_cast<void*>(c->dotpart), static_cast<void*>(c->f64)})
         dfree(p);
     for (void* p : c->pair_owned) dfree(p);
     if (c->host_jds) (void)hipHostFree(c->host_jds);

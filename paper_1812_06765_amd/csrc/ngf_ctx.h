@@ -81,6 +81,12 @@ struct ngf_ctx {
     double lb_gmax = 0.0;
     int lb_evals = 0;
 
+    // float64 evaluation (precision study): one scratch buffer of doubles,
+    // allocated on the first float64 evaluation and grown when a later one
+    // needs more
+    double* f64 = nullptr;
+    size_t f64_cap = 0;  // doubles
+
     bool host_driven = false;  // register_levels: host-side line search (one sync per trial)
 
     // image-pass variant: -1 = autotune, else forced for every level

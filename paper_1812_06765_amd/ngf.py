@@ -77,6 +77,8 @@ def load():
         "ngf_identity": ([_P, i32, _P], i32),
         "ngf_eval_J_grad": ([_P, i32, _P, ctypes.POINTER(f64), _P, ctypes.POINTER(f64)], i32),
         "ngf_eval_J_device": ([_P, ctypes.POINTER(_P)], i32),
+        "ngf_eval_J_grad_f64": ([_P, i32, _P, ctypes.POINTER(f64), _P, ctypes.POINTER(f64)],
+                                i32),
         "ngf_lbfgs_reset": ([_P, i32, _P], i32),
         "ngf_lbfgs_step": ([_P, ctypes.POINTER(f64), ctypes.POINTER(i32)], i32),
         "ngf_lbfgs_get": ([_P, _P, _P, ctypes.POINTER(f64)], i32),
@@ -242,6 +244,20 @@ class Context:
         DS = (ctypes.c_double * 2)()
         self._chk(self.lib.ngf_eval_J_grad(self.h, int(level), _ptr(y), ctypes.byref(J), _ptr(g),
                                            DS))
+        return J.value, g, (DS[0], DS[1])
+
+    def eval_J_grad_f64(self, level, y, want_grad=True):
+        """The float64 evaluation: y a contiguous float64 GPU tensor shaped like
+        the level's deformation.  Returns (J, grad or None, (D, S))."""
+        li = self.level_info(level)
+        if not (isinstance(y, torch.Tensor) and y.dtype == torch.float64 and y.is_cuda
+                and y.is_contiguous() and tuple(y.shape) == (3,) + li.my):
+            raise TypeError(f"y must be a contiguous float64 GPU tensor of shape {(3,) + li.my}")
+        g = torch.empty_like(y) if want_grad else None
+        J = ctypes.c_double()
+        DS = (ctypes.c_double * 2)()
+        self._chk(self.lib.ngf_eval_J_grad_f64(self.h, int(level), _ptr(y), ctypes.byref(J),
+                                               _ptr(g), DS))
         return J.value, g, (DS[0], DS[1])
 
     def eval_J_grad_async(self, level, y, grad):

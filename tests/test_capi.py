@@ -66,6 +66,8 @@ def test_version_and_argument_checks_without_gpu(lib):
     assert lib.ngf_batch_create(ctypes.byref(p), 4, None) == E_ARG
     lib.ngf_batch_register.restype = ctypes.c_int32
     assert lib.ngf_batch_register(None, 0, None, None, None, None, None, None) == E_ARG
+    lib.ngf_eval_J_grad_f64.restype = ctypes.c_int32
+    assert lib.ngf_eval_J_grad_f64(None, 0, None, None, None, None) == E_ARG
 
 
 def test_build_sources_and_flags():
