@@ -9,51 +9,47 @@ namespace ngf {
 
 namespace {
 
-// Fixed-order sums of the per-block partials: thread t adds entries t,
-// t + 256, ... in order, then a fixed tree over the 256 thread sums.
-__device__ inline double block_sum_fixed(const double* a, int n, double* sh) {
-    double s = 0.0;
-#pragma unroll 4
-    for (int i = threadIdx.x; i < n; i += kThreads) s += a[i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
+// Fixed-order reduction of the per-block partials: thread t combines entries
+// t, t + 256, ... in order, each wave folds its 64 lanes by a fixed
+// shuffle tree, and thread 0 combines the four wave results in order.
+__device__ inline double rd_wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+__device__ inline double rd_wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    return v;
 }
 
 __device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
-    __shared__ double sh[kThreads];
-    const double d = block_sum_fixed(a.dpart, a.nd, sh);
-    const double s = block_sum_fixed(a.spart, a.ns, sh);
-    double gm = 0.0, g2 = 0.0;
-    if (a.ng > 0) {
-        double m = 0.0, q = 0.0;
+    static_assert(kThreads == 256, "four waves");
+    __shared__ double sh[4][4];
+    double d = 0.0, s = 0.0, m = 0.0, q = 0.0;
 #pragma unroll 4
-        for (int i = threadIdx.x; i < a.ng; i += kThreads) {
-            m = fmax(m, a.gpart[2 * i]);
-            q += a.gpart[2 * i + 1];
-        }
-        sh[threadIdx.x] = m;
-        __syncthreads();
-        for (int w = kThreads / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
-            __syncthreads();
-        }
-        gm = sh[0];
-        __syncthreads();
-        sh[threadIdx.x] = q;
-        __syncthreads();
-        for (int w = kThreads / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
-        }
-        g2 = sh[0];
+    for (int i = threadIdx.x; i < a.nd; i += kThreads) d += a.dpart[i];
+#pragma unroll 4
+    for (int i = threadIdx.x; i < a.ns; i += kThreads) s += a.spart[i];
+#pragma unroll 4
+    for (int i = threadIdx.x; i < a.ng; i += kThreads) {
+        m = fmax(m, a.gpart[2 * i]);
+        q += a.gpart[2 * i + 1];
     }
+    d = rd_wave_sum(d);
+    s = rd_wave_sum(s);
+    m = rd_wave_max(m);
+    q = rd_wave_sum(q);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = d;
+        sh[1][w] = s;
+        sh[2][w] = m;
+        sh[3][w] = q;
+    }
+    __syncthreads();
+    d = (sh[0][0] + sh[0][1]) + (sh[0][2] + sh[0][3]);
+    s = (sh[1][0] + sh[1][1]) + (sh[1][2] + sh[1][3]);
+    const double gm = fmax(fmax(sh[2][0], sh[2][1]), fmax(sh[2][2], sh[2][3]));
+    const double g2 = (sh[3][0] + sh[3][1]) + (sh[3][2] + sh[3][3]);
     if (threadIdx.x == 0) {
         const double D = a.half_hbar * d;
         const double S = a.half_hbary * s;
