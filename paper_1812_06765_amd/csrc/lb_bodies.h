@@ -399,7 +399,9 @@ __device__ __forceinline__ void lb_gram_body(LbState* st,
         const int j = threadIdx.x & 63;
         double s = 0.0;
         if (j < kDots) {
-#pragma unroll 16
+            // all loads of a phase in flight at once (768 blocks: 48 each);
+            // the additions keep the block order
+#pragma unroll 48
             for (int b = p; b < nblocks; b += kGramPhases)
                 s += dotpart[static_cast<int64_t>(b) * kDots + j];
         }
