@@ -146,7 +146,7 @@ ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
                              const ngf_grid* g, int32_t host_ptrs);
 
 /* Image-grid kernel of the evaluation.  `variant`: -2 = by level size (no
- * timing runs: at least 8 Mi voxels -> 13, at least 1 Mi -> 11, else 8);
+ * timing runs: at least 1 Mi voxels -> 13, else 8);
  * -1 = autotune (default:
  * at ngf_build_pyramid every level times each variant over three evaluations
  * at the identity and keeps the fastest; choices are cached per image shape

@@ -412,12 +412,11 @@ void tune_cache_store(const std::string& key, int v) {
 
 // Image-pass variant from the level size alone, for callers that cannot
 // afford timing runs (or whose timings would be disturbed by concurrent
-// work): the choices the timed selection makes on gfx950 at cubic levels of
-// 256^3 and 128^3, and of 64^3 and below.
+// work): the fastest variants measured on gfx950 at cubic levels of 256^3
+// and 128^3 (the 32 x 32 marching tile) and of 64^3 and below (the small 3D
+// tile).
 int variant_by_size(const Level& L) {
-    const int64_t n = L.N();
-    if (n >= (int64_t{8} << 20)) return kMarchSqFit;
-    return n >= (int64_t{1} << 20) ? kMarch32Fit : kTile3DTiny;
+    return L.N() >= (int64_t{1} << 20) ? kMarchSqFit : kTile3DTiny;
 }
 
 // Pick the image-pass variant of every level: forced, cached for this shape,
