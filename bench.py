@@ -51,15 +51,18 @@ def _src_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_hash):
+def _traffic(kernel_hash, shape, variant):
     """HBM bytes per launch of the 256^3 image-pass kernel from the committed
-    counter summary, only if it was taken from the current kernel source."""
+    counter summary, only if it was taken from the current kernel source, on
+    the same image shape and with the same image-pass variant."""
     path = os.path.join(ROOT, "profiles", "image_pass_256_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_src_sha256_16") != kernel_hash:
+    if (t.get("kernel_src_sha256_16") != kernel_hash
+            or t.get("image_shape") != [int(v) for v in shape]
+            or t.get("variant") != variant):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -340,8 +343,8 @@ def main():
     flops_launch = FLOPS_PER_VOXEL * vox / max(launches, 1)
     achieved = flops_launch / avg_s / 1e12 if kms > 0 else 0.0
     khash = _src_hash()
-    traffic = _traffic(khash)
     kname = {v: k for k, v in ngf.Context.VARIANTS.items()}[ctx.get_kernel(0)]
+    traffic = _traffic(khash, shape, kname)
     out = {
         "metric": METRIC,
         "value": evals / dt,
