@@ -77,3 +77,25 @@ def test_build_sources_and_flags():
     assert "--offload-arch=gfx950" in build.CFLAGS
     i = build.CFLAGS.index("-target-feature")
     assert build.CFLAGS[i + 2] == "-packed-fp32-ops"
+
+
+def _build_c_check(tmp_path):
+    """Compile tests/c/ngf_c_check.c as C99 against the public header and
+    link it with the library (no Python or torch on the caller's side)."""
+    import subprocess
+    pkg = os.path.join(ROOT, "paper_1812_06765_amd")
+    exe = str(tmp_path / "ngf_c_check")
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", f"-I{os.path.join(ROOT, 'include')}",
+           os.path.join(ROOT, "tests", "c", "ngf_c_check.c"), f"-L{pkg}", "-lngfreg",
+           f"-Wl,-rpath,{pkg}", "-lm", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def test_c_caller_compiles_links_and_checks_arguments(tmp_path):
+    import subprocess
+    exe = _build_c_check(tmp_path)
+    r = subprocess.run([exe, "cpu"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "cpu checks ok" in r.stdout
