@@ -28,8 +28,8 @@ from .grids import (  # noqa: F401
     level_shapes,
 )
 from .ngf import (  # noqa: F401
-    warp, warp_T_adjoint, cdiff, cdiff_adj, ngf_terms, ngf_value, ngf_dgT,
+    warp, warp_T_adjoint, cdiff, cdiff_adj, ngf_terms, ngf_dgT,
 )
 from .regulariser import laplacian, curvature  # noqa: F401
 from .objective import Problem, eval_J_grad, eval_J_grad_T  # noqa: F401
-from .lbfgs import LBFGS, register, INFO  # noqa: F401
+from .lbfgs import LBFGS, register, early_stop_met, INFO  # noqa: F401

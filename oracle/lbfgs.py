@@ -72,6 +72,32 @@ class LBFGS:
             return self.first_direction(g)
         return self.two_loop(g)
 
+    def descent_direction(self, g):
+        """(d, g^T d) for this iteration: the quasi-Newton direction, or, if it
+        does not descend (g^T d >= 0), the first-step direction after the
+        memory is dropped."""
+        d = self.direction(g)
+        gtd = float(np.vdot(g, d))
+        if not gtd < 0.0:
+            self.reset()
+            d = self.first_direction(g)
+            gtd = float(np.vdot(g, d))
+        return d, gtd
+
+    @staticmethod
+    def keep_pair(s, tv) -> bool:
+        """Curvature test of a new pair: stored only if s^T t > 1e-10 |s| |t|."""
+        st = float(np.vdot(s, tv))
+        return st > 1e-10 * float(np.linalg.norm(s)) * float(np.linalg.norm(tv))
+
+    def store_pair(self, s, tv):
+        """Append the newest pair; beyond m_L pairs the oldest is dropped."""
+        self.S.append(s)
+        self.Tp.append(tv)
+        if len(self.S) > self.mem:
+            self.S.pop(0)
+            self.Tp.pop(0)
+
     def step(self):
         """One iteration; returns (info, t)."""
         g = self.g
@@ -79,12 +105,7 @@ class LBFGS:
             return INFO["NONFINITE"], 0.0
         if float(np.max(np.abs(g))) == 0.0:
             return INFO["CONVERGED"], 0.0
-        d = self.direction(g)
-        gtd = float(np.vdot(g, d))
-        if not gtd < 0.0:
-            self.reset()
-            d = self.first_direction(g)
-            gtd = float(np.vdot(g, d))
+        d, gtd = self.descent_direction(g)
         t = 1.0
         for _ in range(self.max_halvings + 1):
             yt = self.y + t * d
@@ -93,17 +114,18 @@ class LBFGS:
             if np.isfinite(Jt) and Jt <= self.J + self.c1 * t * gtd:
                 s = yt - self.y
                 tv = gt - g
-                st = float(np.vdot(s, tv))
-                if st > 1e-10 * float(np.linalg.norm(s)) * float(np.linalg.norm(tv)):
-                    self.S.append(s)
-                    self.Tp.append(tv)
-                    if len(self.S) > self.mem:
-                        self.S.pop(0)
-                        self.Tp.pop(0)
+                if self.keep_pair(s, tv):
+                    self.store_pair(s, tv)
                 self.y, self.J, self.g = yt, float(Jt), gt
                 return INFO["OK"], t
             t *= 0.5
         return INFO["LINESEARCH_FAIL"], 0.0
+
+
+def early_stop_met(J_old: float, J_new: float, tol: float) -> bool:
+    """Early-stop test of a level: the accepted step lowered J by at most
+    tol (1 + |J|), measured at the objective before the step."""
+    return (J_old - J_new) <= tol * (1.0 + abs(J_old))
 
 
 def register(R, T, h, levels=3, ratio=2, alpha=0.1, tau=1.0, rho=1.0, max_iter=50,
@@ -137,7 +159,7 @@ def register(R, T, h, levels=3, ratio=2, alpha=0.1, tau=1.0, rho=1.0, max_iter=5
             it += 1
             if record is not None:
                 record.append((lev, opt.J))
-            if early_stop and (J_old - opt.J) <= tol * (1.0 + abs(J_old)):
+            if early_stop and early_stop_met(J_old, opt.J, tol):
                 info = INFO["CONVERGED"]
                 break
         y = opt.y

@@ -120,12 +120,6 @@ def ngf_terms(gT, gR, tau: float, rho: float):
     return r, nT, nR, c
 
 
-def ngf_value(gT, gR, tau: float, rho: float, hbar: float) -> float:
-    """Eq. 2: D = (hbar/2) sum_i (1 - r_i^2)."""
-    r, _, _, _ = ngf_terms(gT, gR, tau, rho)
-    return float(0.5 * hbar * np.sum(1.0 - r * r))
-
-
 def ngf_dgT(gT, gR, tau: float, rho: float, hbar: float) -> np.ndarray:
     """Derivative of D with respect to the template gradient at each point:
     v = -hbar r / (nT nR) * (grad R - (c / nT^2) grad T)."""

@@ -72,3 +72,51 @@ def test_curvature_gradient_homogeneity_and_fd():
         um[idx] -= eps
         fd = (O.curvature(up, hy)[0] - O.curvature(um, hy)[0]) / (2 * eps)
         assert abs(fd - g[idx]) < 1e-6 * max(1.0, abs(g[idx]))
+
+
+def _gaussian_bump_field(hy, amps, s=1.0, extent=10.0):
+    """Node field u_c = amps[c] * exp(-|X - centre|^2 / (2 s^2)) on a nodal grid
+    of spacing hy spanning [0, extent]^3, centred in the box."""
+    my = [int(round(extent / hy[d])) + 1 for d in range(3)]
+    x = [np.arange(my[d]) * hy[d] - 0.5 * extent for d in range(3)]
+    r2 = x[0][:, None, None] ** 2 + x[1][None, :, None] ** 2 + x[2][None, None, :] ** 2
+    g = np.exp(-r2 / (2.0 * s * s))
+    return np.stack([a * g for a in amps])
+
+
+def test_curvature_absolute_weight_converges_to_continuous_functional():
+    """The discrete S approximates (1/2) int (Laplace u)^2 dx.  For a Gaussian
+    bump u = a exp(-r^2 / (2 s^2)) in 3D, Laplace u = (r^2/s^4 - 3/s^2) u, and
+    the integral has the closed form int (Laplace u)^2 dx = 15 pi^(3/2) a^2 / (4 s)
+    (moments of the normal distribution of variance s^2/2 per axis:
+    E r^2 = 3 s^2 / 2, E r^4 = 15 s^4 / 4).  The bump is 5 s from every face,
+    so the replicated boundary rows play no part, the nodal sum of a smooth
+    decaying integrand is exact to far below the stencil error, and the
+    seven-point stencil makes the error O(h^2): it must fall fourfold when h
+    halves, and the Richardson extrapolation must hit the closed form.  This
+    fixes the absolute weight (the node volume hbar^y and the factor 1/2)
+    that the relative pins (FD of S, <grad S, u> = 2 S) leave free."""
+    s = 1.0
+    amps = (1.0, -0.5, 2.0)
+    exact = sum(a * a for a in amps) * 15.0 * np.pi ** 1.5 / (8.0 * s)
+    hy1 = (0.25, 0.2, 0.125)                    # anisotropic node spacing
+    hy2 = tuple(v / 2 for v in hy1)
+    S1, _ = O.curvature(_gaussian_bump_field(hy1, amps, s), hy1)
+    S2, _ = O.curvature(_gaussian_bump_field(hy2, amps, s), hy2)
+    e1, e2 = S1 - exact, S2 - exact
+    assert abs(e1) < 0.03 * exact and abs(e2) < 0.01 * exact
+    assert 3.5 < e1 / e2 < 4.5                  # second order
+    rich = (4.0 * S2 - S1) / 3.0
+    assert abs(rich - exact) < 2e-4 * exact
+
+
+def test_curvature_gradient_absolute_weight():
+    """With S pinned absolutely, <grad S, w> must equal the directional
+    derivative of S along w; for the quadratic S that is (S(u + w) - S(u - w)) / 2
+    exactly (no step error), here with u and w two different bumps."""
+    hy = (0.25, 0.2, 0.125)
+    u = _gaussian_bump_field(hy, (1.0, 0.3, -0.7), s=1.0)
+    w = _gaussian_bump_field(hy, (0.2, -1.0, 0.5), s=1.5)
+    S, g = O.curvature(u, hy)
+    dd = (O.curvature(u + w, hy)[0] - O.curvature(u - w, hy)[0]) / 2.0
+    assert abs(float(np.vdot(g, w)) - dd) < 1e-10 * abs(dd)

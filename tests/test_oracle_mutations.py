@@ -68,6 +68,50 @@ def _two_loop_bad_gamma(self, g):
     return d / gamma**2
 
 
+def _curvature_double_weight(u, hy):
+    S, g = _orig["curvature"](u, hy)
+    return 2.0 * S, 2.0 * g
+
+
+def _curvature_hbar_image(u, hy):
+    # the image-cell volume (h^y / 2 per axis at ratio 2) in place of the node volume
+    S, g = _orig["curvature"](u, hy)
+    return S / 8.0, g / 8.0
+
+
+def _curvature_no_half_grad_doubled(u, hy):
+    S, g = _orig["curvature"](u, hy)
+    return 2.0 * S, 2.0 * g
+
+
+def _descent_no_reset(self, g):
+    d = self.direction(g)
+    gtd = float(np.vdot(g, d))
+    if not gtd < 0.0:
+        d = self.first_direction(g)
+        gtd = float(np.vdot(g, d))
+    return d, gtd
+
+
+def _descent_no_fallback(self, g):
+    d = self.direction(g)
+    return d, float(np.vdot(g, d))
+
+
+def _keep_every_pair(s, tv):
+    return True
+
+
+def _keep_positive_pair(s, tv):
+    return float(np.vdot(s, tv)) > 0.0
+
+
+def _early_stop_on_new(J_old, J_new, tol):
+    return (J_old - J_new) <= tol * (1.0 + abs(J_new))
+
+
+_orig_keep_pair_func = OL.LBFGS.__dict__["keep_pair"].__func__
+
 _orig = {
     "cdiff_adj": ON.cdiff_adj,
     "ngf_terms": ON.ngf_terms,
@@ -76,6 +120,11 @@ _orig = {
     "laplacian": OC.laplacian,
     "warp": ON.warp,
     "two_loop": OL.LBFGS.two_loop,
+    "curvature": OC.curvature,
+    "descent_direction": OL.LBFGS.descent_direction,
+    "keep_pair": OL.LBFGS.keep_pair,
+    "early_stop_met": OL.early_stop_met,
+    "store_pair": OL.LBFGS.store_pair,
 }
 
 
@@ -139,9 +188,63 @@ def test_mutation_lbfgs_scaling(monkeypatch):
     assert _fails(tl.test_two_loop_equals_dense_bfgs, 20, 3)
 
 
+@pytest.mark.parametrize("bad", [_curvature_double_weight, _curvature_hbar_image,
+                                 _curvature_no_half_grad_doubled])
+def test_mutation_curvature_weight(monkeypatch, bad):
+    # a consistent slip of the quadrature weight in both S and grad S passes
+    # every relative pin (FD of S, <grad S, u> = 2 S); the continuum limit
+    # fixes it
+    monkeypatch.setattr(OC, "curvature", bad)
+    monkeypatch.setattr(O, "curvature", bad)
+    tc.test_curvature_gradient_homogeneity_and_fd()
+    assert _fails(tc.test_curvature_absolute_weight_converges_to_continuous_functional)
+
+
+def test_mutation_no_memory_drop(monkeypatch):
+    monkeypatch.setattr(OL.LBFGS, "descent_direction", _descent_no_reset)
+    assert _fails(tl.test_lbfgs_non_descent_direction_drops_memory)
+
+
+def test_mutation_no_descent_fallback(monkeypatch):
+    monkeypatch.setattr(OL.LBFGS, "descent_direction", _descent_no_fallback)
+    assert _fails(tl.test_lbfgs_non_descent_direction_drops_memory)
+
+
+@pytest.mark.parametrize("bad", [_keep_every_pair, _keep_positive_pair])
+def test_mutation_pair_test(monkeypatch, bad):
+    monkeypatch.setattr(OL.LBFGS, "keep_pair", staticmethod(bad))
+    assert _fails(tl.test_lbfgs_pair_curvature_test, 0.5e-10, False)
+
+
+def _store_drop_newest(self, s, tv):
+    # when full, the new pair replaces the newest instead of evicting the oldest
+    if len(self.S) >= self.mem:
+        self.S[-1], self.Tp[-1] = s, tv
+    else:
+        self.S.append(s)
+        self.Tp.append(tv)
+
+
+def test_mutation_memory_order(monkeypatch):
+    monkeypatch.setattr(OL.LBFGS, "store_pair", _store_drop_newest)
+    assert _fails(tl.test_lbfgs_memory_keeps_newest_pairs)
+
+
+def test_mutation_early_stop_on_new_value(monkeypatch):
+    monkeypatch.setattr(OL, "early_stop_met", _early_stop_on_new)
+    monkeypatch.setattr(O, "early_stop_met", _early_stop_on_new)
+    assert _fails(tl.test_early_stop_rule_on_hand_made_sequence)
+
+
 @pytest.mark.parametrize("name", sorted(_orig))
 def test_originals_restored(name):
     # the planted mistakes are undone after each case
     mod = {"cdiff_adj": ON, "ngf_terms": ON, "index_map": OG, "omega_sets": OG, "laplacian": OC,
-           "warp": ON, "two_loop": OL.LBFGS}[name]
-    assert getattr(mod, name) is _orig[name]
+           "warp": ON, "two_loop": OL.LBFGS, "curvature": OC,
+           "descent_direction": OL.LBFGS, "keep_pair": OL.LBFGS,
+           "early_stop_met": OL, "store_pair": OL.LBFGS}[name]
+    got = getattr(mod, name)
+    if name == "keep_pair":
+        assert OL.LBFGS.__dict__["keep_pair"].__func__ is _orig_keep_pair_func
+    else:
+        assert got is _orig[name]
