@@ -8,10 +8,13 @@ J + grad J evaluation (P, warp, NGF, adjoint, P^T gather, curvature, fused
 reductions) in the library's kernels.
 
 Printed (one JSON line):
-* value       J + grad J evaluations per second over the timed steps (all
-              levels, line-search trials included), i.e. whole-job throughput;
-* ms_per_step the full-registration time;
-* finest      a dedicated loop of evaluations at the 256^3 level alone;
+* value       J + grad J evaluations per second at the 256^3 level (a loop of
+              evaluations back to back at the registered deformation);
+* ms_per_step the full-registration time (pyramid and all four levels);
+  evals_per_s_registration the evaluations of the timed registrations (all
+              levels, line-search trials included) per second;
+* accuracy_voxels  distance of the registration to the true correspondence at
+              sampled body and edge voxels, next to the identity's;
 * roofline    the dominant kernel (the fused image-grid pass), timed with HIP
               events on the library's stream over the timed region;
 * cpu_baseline the FP64 oracle on the host, one 256^3 evaluation.
@@ -67,6 +70,57 @@ def _traffic(kernel_hash, shape, variant):
     return t.get("hbm_bytes_per_launch")
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _nproc():
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def accuracy(ctx, y, pr, samples=20000, seed=5):
+    """Mean distance (voxels) between the registration's correspondence P y and
+    the true one at sampled voxels: inside the body (R > -500 HU) and on
+    strong edges (|grad R| > 200 HU per voxel), next to the same distance for
+    the identity.  The true correspondence of T(x) = R(x + u(x)) is z(x)
+    with z + u(z) = x (fixed point).  P y is applied by the library."""
+    import numpy as np
+    import torch
+
+    from paper_1812_06765_amd import synth
+    R = pr.R
+    rng = np.random.default_rng(seed)
+    g = np.stack(np.gradient(R.astype(np.float32)))
+    gn = np.sqrt((g.astype(np.float64) ** 2).sum(0))
+    del g
+    yh = ctx.apply_P(0, y)
+    yid = ctx.apply_P(0, ctx.identity(0))
+    out = {"samples_per_region": samples}
+    for name, mask in (("body", R > -500.0), ("edges", gn > 200.0)):
+        cand = np.flatnonzero(mask)
+        pick = np.unravel_index(rng.choice(cand, size=min(samples, cand.size), replace=False),
+                                R.shape)
+        zstar = synth.invert_displacement(pr.field, np.stack(pick).astype(np.float64) + 0.5)
+        idx = tuple(torch.from_numpy(p.astype(np.int64)).cuda() for p in pick)
+        res = []
+        for v in (yid, yh):
+            at = v[:, idx[0], idx[1], idx[2]].double().cpu().numpy()
+            res.append(float(np.sqrt(((at - zstar) ** 2).sum(0)).mean()))
+        out[name] = {"identity": res[0], "registered": res[1]}
+    return out
+
+
 def cpu_baseline(R, T, evals=2):
     """J + grad J evaluations of the FP64 oracle at the 256^3 level."""
     import numpy as np
@@ -89,7 +143,7 @@ def cpu_baseline(R, T, evals=2):
         dt += time.perf_counter() - t0
         print(f"[bench] oracle evaluation {k + 1}/{evals} done", file=sys.stderr, flush=True)
     return {"value": evals / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "seconds": dt,
+            "seconds": dt, "cpu_model": _cpu_model(), "nproc": _nproc(),
             "sample": f"{evals} J+grad J evaluations of the float64 numpy oracle at the "
                       f"{m[0]}x{m[1]}x{m[2]} finest level ({my[0]}x{my[1]}x{my[2]} nodes; "
                       "identity and a smooth displacement of up to 2 voxels), "
@@ -230,6 +284,8 @@ def main():
     ap.add_argument("--host-reps", type=int, default=3,
                     help="registrations from pinned host arrays (PCIe-inclusive timing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the distance of the registration to the true correspondence")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead: the uneven batch of this many pairs (axes drawn from "
                          "96..256, 3 levels) through the batched form")
@@ -347,8 +403,11 @@ def main():
     traffic = _traffic(khash, shape, kname)
     out = {
         "metric": METRIC,
-        "value": evals / dt,
+        "value": args.finest_evals / tf,
         "unit": "evals/s",
+        "value_note": f"J + grad J evaluations per second at the {sname} finest level "
+                      f"({args.finest_evals} back to back at the registered y); "
+                      "ms_per_step is one full registration (pyramid + all levels)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -366,6 +425,7 @@ def main():
                    "global_batch": 1, "seq_len": None, "parallelism": "single GPU"},
         "registration_s": dt / args.steps,
         "evals_per_registration": evals / args.steps,
+        "evals_per_s_registration": evals / dt,
         "levels": reports[-1],
         "from_host": {"registration_s": th, "reps": args.host_reps,
                       "note": "pinned host R and T in, y out: includes both copies over PCIe "
@@ -391,6 +451,9 @@ def main():
             "kernel_src": khash,
         },
     }
+    if not args.no_accuracy and shape[0] * shape[1] * shape[2] <= (1 << 26):
+        out["accuracy_voxels"] = accuracy(ctx, y, pr)
+        print("[bench] accuracy sampled", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, 256^3 eval)...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pr.R, pr.T)

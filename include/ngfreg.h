@@ -317,6 +317,22 @@ ngf_status ngf_set_profiling(ngf_ctx* ctx, int32_t enable, int32_t level);
 ngf_status ngf_kernel_time(ngf_ctx* ctx, int32_t level, int32_t* launches, double* total_ms,
                            int64_t* voxels, int64_t* nodes);
 
+/* Failure injection, for tests of the error paths (no other use).  `flags`
+ * is a bit set; 0 clears it.
+ *   NGF_FAULT_REJECT_STEPS  every L-BFGS trial point fails the Armijo test
+ *     (Sec. 2.1, L-BFGS line search), so each iteration ends after its 11
+ *     trial evaluations with NGF_INFO_LINESEARCH_FAIL and y unchanged; both
+ *     drivers (ngf_set_driver) honour it.  Takes effect at the next
+ *     ngf_lbfgs_reset (and so at every level of ngf_register).
+ *   NGF_FAULT_ALLOC  every device allocation the context attempts from now
+ *     on fails as if the device were out of memory: the call returns
+ *     NGF_E_OOM and the context stays usable once the flag is cleared
+ *     (buffers already allocated are kept).
+ * Errors: NGF_E_ARG for unknown bits. */
+#define NGF_FAULT_REJECT_STEPS 1
+#define NGF_FAULT_ALLOC 2
+ngf_status ngf_set_faults(ngf_ctx* ctx, int32_t flags);
+
 /* Batched form: many independent registrations (one image pair each, any
  * mix of shapes) on one device, each computed as by ngf_register (Sec. 2:
  * pyramid, multi-level L-BFGS on Eq. 1).  Two modes (ngf_batch_set_mode):

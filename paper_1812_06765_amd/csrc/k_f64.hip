@@ -356,7 +356,8 @@ extern "C" ngf_status ngf_eval_J_grad_f64(ngf_ctx* c, int32_t level, const doubl
         if (c->f64) (void)hipFree(c->f64);
         c->f64 = nullptr;
         c->f64_cap = 0;
-        if (hipMalloc(reinterpret_cast<void**>(&c->f64), need * sizeof(double)) != hipSuccess) {
+        if ((c->faults & NGF_FAULT_ALLOC) ||
+            hipMalloc(reinterpret_cast<void**>(&c->f64), need * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             c->f64 = nullptr;
             return fail(c, NGF_E_OOM, "hipMalloc of the float64 scratch failed");

@@ -55,6 +55,7 @@ __device__ inline void lb_init_one(LbState* st, int mem, double hmin, const doub
     for (int i = 0; i < kBasis * kBasis; ++i) st->G[i] = 0.0;
     for (int i = 0; i < kBasis; ++i) st->coef[i] = 0.0;
     st->G[kBasisG * kBasis + kBasisG] = jds[4];
+    st->reject_all = 0;  // failure injection: set by the host after this kernel
 }
 
 // Direction coefficients by the two-loop recursion over the Gram matrix.

@@ -38,6 +38,8 @@ ngf_status fail(ngf_ctx* c, ngf_status s, const std::string& msg) {
 template <class T>
 ngf_status dalloc(ngf_ctx* c, T** p, size_t count) {
     *p = nullptr;
+    if (c && (c->faults & NGF_FAULT_ALLOC))
+        return fail(c, NGF_E_OOM, "hipMalloc failed: allocation failure injected");
     if (count == 0) count = 1;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
     if (e != hipSuccess) {
@@ -733,6 +735,14 @@ ngf_status ngf_set_driver(ngf_ctx* c, int32_t mode) {
     return NGF_OK;
 }
 
+ngf_status ngf_set_faults(ngf_ctx* c, int32_t flags) {
+    if (!c) return NGF_E_ARG;
+    if (flags & ~(NGF_FAULT_REJECT_STEPS | NGF_FAULT_ALLOC))
+        return fail(c, NGF_E_ARG, "unknown fault bits");
+    c->faults = flags;
+    return NGF_OK;
+}
+
 ngf_status ngf_get_kernel(const ngf_ctx* c, int32_t level, int32_t* variant) {
     if (!c || !variant) return NGF_E_ARG;
     const ngf_status s = check_level(c, level);
@@ -838,6 +848,9 @@ ngf_status ngf_lbfgs_reset(ngf_ctx* c, int32_t level, const float* y0) {
     launch_lb_init(c->st, c->p.lbfgs_mem, hmin, c->jds, c->p.max_iter, c->p.early_stop,
                    c->p.tol_J, c->stream);
     HIPCHK(c, hipGetLastError());
+    const int reject = (c->faults & NGF_FAULT_REJECT_STEPS) ? 1 : 0;
+    HIPCHK(c, hipMemcpyAsync(&c->st->reject_all, &reject, sizeof(int), hipMemcpyHostToDevice,
+                             c->stream));
     if (read_jds(c) != NGF_OK) return NGF_E_HIP;
     c->lb_level = level;
     c->lb_J = c->host_jds[0];
@@ -875,7 +888,7 @@ ngf_status ngf_lbfgs_step(ngf_ctx* c, double* J, int32_t* info) {
             if (read_jds(c) != NGF_OK) return NGF_E_HIP;  // J of the trial and g^T d
             if (h == 0) gtd = c->host_jds[5];
             const double Jt = c->host_jds[0];
-            if (armijo_ok(Jt, c->lb_J, c1, t, gtd)) {
+            if (armijo_ok(Jt, c->lb_J, c1, t, gtd) && !(c->faults & NGF_FAULT_REJECT_STEPS)) {
                 ok = true;
                 break;
             }

@@ -87,6 +87,7 @@ struct ngf_ctx {
     double* f64 = nullptr;
     size_t f64_cap = 0;  // doubles
 
+    int faults = 0;            // failure injection (NGF_FAULT_*)
     bool host_driven = false;  // register_levels: host-side line search (one sync per trial)
 
     // image-pass variant: -1 = autotune, else forced for every level

@@ -206,6 +206,7 @@ struct LbState {
     double hmin;
     double G[kBasis * kBasis];      // inner products of the basis vectors
     double coef[kBasis];            // direction coefficients over the basis
+    int reject_all;                 // failure injection: every trial fails the Armijo test
 };
 
 __device__ inline void lb_finish(LbCtl& c, int info) {
@@ -223,7 +224,7 @@ __device__ inline void lb_decide_one(LbState* st, double Jt) {
     if (c.op == kOpNone) return;
     c.evals += 1;
     const double c1 = 1e-4;
-    if (isfinite(Jt) && Jt <= c.J + c1 * c.t * st->gtd) {
+    if (isfinite(Jt) && Jt <= c.J + c1 * c.t * st->gtd && !st->reject_all) {
         c.phase = kPhAccepted;
     } else {
         c.t *= 0.5;

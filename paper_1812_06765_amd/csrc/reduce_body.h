@@ -57,7 +57,10 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs& a) {
         a.out[0] = J;
         a.out[1] = D;
         a.out[2] = S;
-        a.out[3] = gm;
+        // fmax drops NaN, the sum of squares keeps it: a gradient with a NaN
+        // or infinite entry reports a non-finite maximum, which ends L-BFGS
+        // with the non-finite outcome
+        a.out[3] = isfinite(g2) ? gm : g2;
         a.out[4] = g2;
         if (a.lb) lb_decide_one(a.lb, J);
     }

@@ -90,6 +90,7 @@ def load():
         "ngf_set_profiling": ([_P, i32, i32], i32),
         "ngf_set_kernel": ([_P, i32], i32),
         "ngf_set_driver": ([_P, i32], i32),
+        "ngf_set_faults": ([_P, i32], i32),
         "ngf_apply_P": ([_P, i32, _P, _P], i32),
         "ngf_apply_PT": ([_P, i32, _P, _P, i32], i32),
         "ngf_get_kernel": ([_P, i32, ctypes.POINTER(i32)], i32),
@@ -385,6 +386,15 @@ class Context:
     def set_driver(self, mode):
         """Line search of register(): 'device' (default) or 'host'."""
         self._chk(self.lib.ngf_set_driver(self.h, {"device": 0, "host": 1}[mode]))
+
+    FAULT_REJECT_STEPS = 1
+    FAULT_ALLOC = 2
+
+    def set_faults(self, flags):
+        """Failure injection for tests of the error paths: a bit set of
+        FAULT_REJECT_STEPS (every line-search trial fails) and FAULT_ALLOC
+        (every device allocation fails); 0 clears."""
+        self._chk(self.lib.ngf_set_faults(self.h, int(flags)))
 
     def get_kernel(self, level):
         v = ctypes.c_int32()
