@@ -145,6 +145,19 @@ ngf_status ngf_set_params(ngf_ctx* ctx, const ngf_params* p);
 ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
                              const ngf_grid* g, int32_t host_ptrs);
 
+/* Deformation grid of level 0 per axis (Sec. 2.2, "Grid conversion": the
+ * index sets and weights of P are fixed per dimension by the two grids, so
+ * each axis may have its own node count).  my0[d] = 0 keeps the default
+ * m_d / ratio + 1; a NULL my0 resets all three.  Level l then has
+ * (my0[d] - 1) / 2^l + 1 nodes along axis d, so ngf_build_pyramid requires
+ * my0[d] - 1 divisible by 2^(levels-1), at least 2 node cells on the
+ * coarsest level, and at least two image cells per node cell
+ * (2 (my0[d] - 1) <= m_d; the ratio need not be an integer).  Levels whose
+ * grids are m/2 + 1 or m/4 + 1 on every axis may use every image-pass
+ * variant; any other grid uses variant 14.  Clears a built pyramid.
+ * Errors: NGF_E_ARG for a count in 1..2. */
+ngf_status ngf_set_node_grid(ngf_ctx* ctx, const int32_t my0[3]);
+
 /* Image-grid kernel of the evaluation.  `variant`: -2 = by level size (no
  * timing runs: at least 1 Mi voxels -> 13, else 8);
  * -1 = autotune (default:
@@ -159,7 +172,11 @@ ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
  * 16x32 or 16x64 tiles in chunks whose length is fitted to the level's shape
  * and to the number of workgroups the device holds at once (so that the
  * launch fills the device in as few full rounds as possible); 13 = the same
- * over 32x32 tiles with 512-thread workgroups.  All variants
+ * over 32x32 tiles with 512-thread workgroups; 14 = x-marching over 32x32
+ * tiles reading the exact index maps (any deformation grid, one barrier per
+ * plane step, the reference side of the NGF term prepared per pyramid).
+ * A variant that needs a ratio of 2 or 4 is replaced by 14 on other grids.
+ * All variants
  * compute the same quantities; only the summation order of the P^T partial
  * sums differs.  Applies at once to a built pyramid.  ngf_get_kernel reports
  * a level's choice. */
@@ -287,6 +304,43 @@ ngf_status ngf_eval_pair(ngf_ctx* ctx, const ngf_grid* g, const int32_t my[3],
                          const float* R, const float* T, const float* y,
                          const double* gscale, double* J, double* J_dev,
                          float* grad_y, float* grad_T);
+
+/* ngf_eval_pair without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results as
+ * ngf_eval_pair; the pair's index maps and the partial sums live in a static
+ * device array of 2 MiB per device (held until the process ends), so the
+ * grid is limited to what fits there (about 512^3 voxels; larger grids get
+ * NGF_E_SHAPE with the bytes needed).  The ratio is the context's (2 or 4).
+ * Every call on one device shares that array and leaves its contents
+ * behind: calls that overlap on one device (several contexts or streams at
+ * once) race and must be serialised by the caller.  Nothing is cleared with
+ * a memset (the partial sums are written before they are read, the
+ * gradients are zeroed by a fill kernel), so with J == NULL the call can be
+ * captured. */
+ngf_status ngf_eval_pair_static(ngf_ctx* ctx, const ngf_grid* g, const int32_t my[3],
+                                const float* R, const float* T, const float* y,
+                                const double* gscale, double* J, double* J_dev,
+                                float* grad_y, float* grad_T);
+
+/* The differentiation form on a pyramid level (Sec. 2.1, Eq. 1; Sec. 2.2,
+ * Eq. 2 and the matrix-free chain rule): J at y on level `level` with its
+ * gradients with respect to y and to the level's template image, computed
+ * as by ngf_eval_pair (atomic scatter of the P^T blocks and of e W(i -> k)
+ * into the warp corners) but on the pyramid's images and index maps, with
+ * buffers sized by ngf_build_pyramid: nothing is allocated, so the call can
+ * be captured in a graph when J is NULL.
+ *   y       device float32 deformation of the level
+ *   gscale  device double multiplying both gradients, or NULL for 1
+ *   J       host double (the call then synchronises) or NULL
+ *   J_dev   device double receiving J, or NULL
+ *   grad_y  device float32 like y, or NULL
+ *   grad_T  device float32 of the level's image shape, or NULL
+ * Errors: NGF_E_SHAPE on a level whose deformation grid is not m/2 + 1 or
+ * m/4 + 1 on every axis (the scatter kernel holds those ratios);
+ * NGF_E_NONFINITE when J is requested and not finite. */
+ngf_status ngf_eval_J_grad_T(ngf_ctx* ctx, int32_t level, const float* y, const double* gscale,
+                             double* J, double* J_dev, float* grad_y, float* grad_T);
 
 /* Grid conversion as standalone operators on a level's grids (Sec. 2.2,
  * "Grid conversion"; the evaluation fuses them and does not call these).

@@ -157,17 +157,25 @@ def downsample(u: np.ndarray) -> np.ndarray:
     return (0.125 * s).astype(np.float32)
 
 
-def level_shapes(m, h, levels: int, ratio: int = 2):
+def level_shapes(m, h, levels: int, ratio: int = 2, my0=None):
     """Image shape, spacing and deformation-grid shape of every pyramid level.
 
     Level 0 is the input; level l has m / 2^l cells and spacing h 2^l, and a
-    deformation grid of m_l / ratio + 1 nodes per axis.
+    deformation grid of m_l / ratio + 1 nodes per axis.  With ``my0`` (node
+    counts of level 0 per axis) level l instead has (my0 - 1) / 2^l + 1
+    nodes: every coarser level halves the node cells as it halves the image
+    cells, so the nodal prolongation between levels stays exact (the
+    multi-level scheme of Sec. 2.1 with the grid conversion of Sec. 2.2 on
+    any grid).
     """
     out = []
     for lev in range(levels):
         ml = tuple(int(m[d]) >> lev for d in range(3))
         hl = tuple(float(h[d]) * (1 << lev) for d in range(3))
-        myl = tuple(ml[d] // ratio + 1 for d in range(3))
+        if my0 is None:
+            myl = tuple(ml[d] // ratio + 1 for d in range(3))
+        else:
+            myl = tuple(((int(my0[d]) - 1) >> lev) + 1 for d in range(3))
         out.append((ml, hl, myl))
     return out
 

@@ -129,15 +129,16 @@ def early_stop_met(J_old: float, J_new: float, tol: float) -> bool:
 
 
 def register(R, T, h, levels=3, ratio=2, alpha=0.1, tau=1.0, rho=1.0, max_iter=50,
-             mem=5, tol=1e-6, early_stop=False, record=None):
+             mem=5, tol=1e-6, early_stop=False, record=None, my0=None):
     """Multi-level registration (Sec. 2.1): returns the finest-level y and a
     per-level list of (iterations, evaluations, final J, final info).
 
     ``record``, if given, is a list that receives one (level, J) tuple per
-    accepted iteration.
+    accepted iteration.  ``my0``: deformation-grid node counts of level 0
+    (default m / ratio + 1 per axis), see ``level_shapes``.
     """
     m = R.shape
-    shapes = level_shapes(m, h, levels, ratio)
+    shapes = level_shapes(m, h, levels, ratio, my0)
     Rs, Ts = pyramid(R, T, levels)
     y = None
     report = []

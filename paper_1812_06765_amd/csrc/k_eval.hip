@@ -32,16 +32,6 @@ namespace {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// n / d for 0 <= n < 2^22, d >= 1, with inv = 1/d in float32: the product is
-// within one of the quotient, and one integer correction makes it exact.
-// (An integer division by a run-time divisor costs tens of instructions.)
-__device__ inline int div_small(int n, int d, float inv) {
-    int q = static_cast<int>(static_cast<float>(n) * inv);
-    if (q * d > n) q -= 1;
-    if ((q + 1) * d <= n) q += 1;
-    return q;
-}
-
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     return v;
@@ -491,7 +481,7 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
     const int plane = ny * nz;
     const int xend = min(x0 + a.cxn, nx);
     const int nstep = xend - x0 + 4;  // a chunk cut short by the grid stops after its last plane
-    const int PX = a.bx + 1, PY = a.by + 1, PZ = a.bz + 1;
+    const int PX = a.px, PY = a.py, PZ = a.pz;
     const int NP = PX * PY * PZ;
     const float sc = (!GATHER && a.gscale != nullptr) ? static_cast<float>(*a.gscale) : 1.0f;
     const double hyc = c == 0 ? a.hyx : (c == 1 ? a.hyy : a.hyz);
@@ -525,34 +515,34 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
         const int cy = clampi(y0 - 1 + iy, 0, ny - 1), cz = clampi(z0 - 1 + iz, 0, nz - 1);
         apos[k] = (cy - y0 + 2) * UZ + (cz - z0 + 2);
     }
-    // gather of the image-tile partials: the (y, z) part of the node's place
-    // in each image tile that holds it (j = 2 oy + oz, the tile oy rows and oz
-    // columns back) is fixed over the chunk; the x part is the same for the
-    // whole workgroup.  An entry that does not apply reads offset 0 of the
-    // tile row and is not added.  The part array of one x-slab of tiles is
-    // below 2^31 floats (checked by the host).
-    int yzoff[4];
-    bool yzok[4];
-    {
-        const float iby = 1.0f / a.by, ibz = 1.0f / a.bz;
-        const int tyh = div_small(gy, a.by, iby), tzh = div_small(gz, a.bz, ibz);
-        const int ry = gy - tyh * a.by, rz = gz - tzh * a.bz;
-        const int noy = (ry == 0 && tyh > 0) ? 2 : 1, noz = (rz == 0 && tzh > 0) ? 2 : 1;
+    // gather of the image-tile partials (Eq. 3 completed): a node lies in the
+    // blocks of at most two image tiles per axis, those of the first and the
+    // last image point of its index set.  The (y, z) part of the node's place
+    // in each (j = 2 oy + oz: second tile along y if oy, along z if oz) is
+    // fixed over the chunk; the x part is the same for the whole workgroup
+    // and is tabulated per plane of the chunk.  An entry that does not apply
+    // reads offset 0 of the tile row and is not added.  The part array of one
+    // x-slab of tiles is below 2^31 floats (checked by the host).
+    int yzoff[4] = {0, 0, 0, 0};
+    bool yzok[4] = {false, false, false, false};
+    if constexpr (GATHER) {
+        const NodeTiles ty = node_tiles(min(gy, ny - 1), a.my, ny, a.tey);
+        const NodeTiles tz = node_tiles(min(gz, nz - 1), a.mz, nz, a.tez);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int oy = j >> 1, oz = j & 1;
-            const int tty = tyh - oy, ttz = tzh - oz;
-            yzok[j] = own && oy < noy && oz < noz && tty < a.nty && ttz < a.ntz;
-            yzoff[j] = yzok[j] ? ((tty * a.ntz + ttz) * 3 + c) * NP + (ry + oy * a.by) * PZ +
-                                     (rz + oz * a.bz)
-                               : 0;
+            const int tty = oy ? ty.tb : ty.ta, ttz = oz ? tz.tb : tz.ta;
+            const int lyy = oy ? ty.lb : ty.la, lzz = oz ? tz.lb : tz.la;
+            yzok[j] = own && tty >= 0 && ttz >= 0;
+            yzoff[j] = yzok[j] ? ((tty * a.ntz + ttz) * 3 + c) * NP + lyy * PZ + lzz : 0;
         }
     }
     const int64_t xslab = static_cast<int64_t>(a.nty) * a.ntz * 3 * NP;
-    // x tile of the first output plane and the plane's place in it; both
-    // advance with the output plane
-    int txh = x0 / a.bx;
-    int rx = x0 - txh * a.bx;
+    __shared__ int4 sxt[GATHER ? kNodeChunkMax : 1];
+    for (int i = threadIdx.x; GATHER && i < xend - x0; i += kThreads) {
+        const NodeTiles tx = node_tiles(x0 + i, a.mx, nx, a.tex);
+        sxt[i] = make_int4(tx.ta, tx.la, tx.tb, tx.lb);
+    }
 
     // y of this thread's entries of the u plane, loaded one step ahead so
     // that the loads overlap the previous plane's A u and output phases
@@ -619,12 +609,12 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
                 } else {
                     // Eq. 3 completed: the (at most 8) image-tile partials of the
                     // node, in the order (ox, oy, oz)
-                    const int nox = (rx == 0 && txh > 0) ? 2 : 1;
+                    const int4 xt = sxt[po - x0];
 #pragma unroll
                     for (int ox = 0; ox < 2; ++ox) {
-                        const int ttx = txh - ox;
-                        if (ox >= nox || ttx >= a.ntx) continue;
-                        const float* px = a.part + ttx * xslab + (rx + ox * a.bx) * (PY * PZ);
+                        const int ttx = ox ? xt.z : xt.x;
+                        if (ttx < 0) continue;
+                        const float* px = a.part + ttx * xslab + (ox ? xt.w : xt.y) * (PY * PZ);
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             const float v = px[yzoff[j]];
@@ -641,13 +631,6 @@ __device__ __forceinline__ void node_march_body(const NodePassArgs& a, int block
                 gmax = own ? fmax(gmax, static_cast<double>(fabsf(g))) : gmax;
                 g2 += own ? static_cast<double>(g) * static_cast<double>(g) : 0.0;
                 grow += plane;
-            }
-            if (GATHER) {
-                rx += 1;
-                if (rx == a.bx) {
-                    rx = 0;
-                    txh += 1;
-                }
             }
         }
         const int t = s0;

@@ -67,9 +67,25 @@ bool params_ok(const ngf_params* p, std::string* why) {
 
 int tiles(int m, int t) { return (m + t - 1) / t; }
 
+// Nodes in the largest block of P^T partial sums over tiles of extent te
+// along an axis: a tile's block runs from the lower node of its first image
+// point to the upper node of its last.
+int block_nodes(int m, int n, int te) {
+    int best = 0;
+    for (int t0 = 0; t0 < m; t0 += te) {
+        const int last = std::min(t0 + te, m) - 1;
+        best = std::max(best, map_lower(last, m, n) + 2 - map_lower(t0, m, n));
+    }
+    return best;
+}
+
 Geo geometry(const Level& L, int variant) {
     Geo g{};
-    if (is_tile3d(variant)) {
+    if (is_gen(variant)) {
+        g.ty = g.tz = 32;
+        g.tx = fit_chunk(L.m[0], int64_t{tiles(L.m[1], 32)} * tiles(L.m[2], 32), 4, 4,
+                         image_gen_slots());
+    } else if (is_tile3d(variant)) {
         g.tx = tile3d_x(variant);
         g.ty = tile3d_y(variant);
         g.tz = tile3d_z(variant);
@@ -84,14 +100,17 @@ Geo geometry(const Level& L, int variant) {
     g.ntx = tiles(L.m[0], g.tx);
     g.nty = tiles(L.m[1], g.ty);
     g.ntz = tiles(L.m[2], g.tz);
+    g.px = block_nodes(L.m[0], L.my[0], g.tx);
+    g.py = block_nodes(L.m[1], L.my[1], g.ty);
+    g.pz = block_nodes(L.m[2], L.my[2], g.tz);
     return g;
 }
-int64_t part_floats(const Level& L, int ratio, int variant) {
+int64_t part_floats(const Level& L, int variant) {
     const Geo g = geometry(L, variant);
-    const int64_t np = static_cast<int64_t>(g.tx / ratio + 1) * (g.ty / ratio + 1) *
-                       (g.tz / ratio + 1);
-    return g.ntiles() * 3 * np;
+    return g.ntiles() * 3 * int64_t{g.px} * g.py * g.pz;
 }
+// whether an image-pass variant can run on a level
+bool variant_ok(const Level& L, int v) { return !needs_dyadic(v) || L.dyadic != 0; }
 bool pow2(double h) {
     int e = 0;
     return std::frexp(h, &e) == 0.5;
@@ -99,7 +118,7 @@ bool pow2(double h) {
 // node-pass x chunk (node planes), fitted like the image pass's
 int node_chunk(const Level& L) {
     return fit_chunk(L.my[0], 3 * int64_t{tiles(L.my[1], kNMY)} * tiles(L.my[2], kNMZ), 1, 4,
-                     node_march_slots());
+                     node_march_slots(), kNodeChunkMax);
 }
 // node-pass workgroups per axis (one per node tile and component)
 void node_grid(const Level& L, int nb[3]) {
@@ -116,12 +135,12 @@ int64_t node_blocks(const Level& L) {
 ngf_status ensure_scratch(ngf_ctx* c, const Level& L) {
     size_t pf = 0, nt = 0;
     for (int v = 0; v < kNumVariants; ++v) {
-        pf = std::max(pf, static_cast<size_t>(part_floats(L, c->p.ratio, v)));
+        if (!variant_ok(L, v)) continue;
+        pf = std::max(pf, static_cast<size_t>(part_floats(L, v)));
         const Geo g = geometry(L, v);
         nt = std::max(nt, static_cast<size_t>(g.ntiles()));
         // the node pass addresses one x-slab of tile partials with 32-bit offsets
-        const int64_t slab = int64_t{g.nty} * g.ntz * 3 * (g.tx / c->p.ratio + 1) *
-                             (g.ty / c->p.ratio + 1) * (g.tz / c->p.ratio + 1);
+        const int64_t slab = int64_t{g.nty} * g.ntz * 3 * g.px * g.py * g.pz;
         if (slab >= (int64_t{1} << 31))
             return fail(c, NGF_E_SHAPE, "image too large in y and z for the tile layout");
     }
@@ -212,6 +231,9 @@ ngf_status bind_level_storage(ngf_ctx* c, int l) {
         st.p[0] = f;
         if (dalloc(c, &f, n) != NGF_OK) return NGF_E_OOM;
         st.p[1] = f;
+        float4* rn = nullptr;
+        if (dalloc(c, &rn, n) != NGF_OK) return NGF_E_OOM;
+        st.p[11] = rn;
         for (int d = 0; d < 3; ++d) {
             int32_t* j = nullptr;
             if (dalloc(c, &j, cap_m[d]) != NGF_OK) return NGF_E_OOM;
@@ -226,6 +248,7 @@ ngf_status bind_level_storage(ngf_ctx* c, int l) {
     }
     lv.R = static_cast<float*>(st.p[0]);
     lv.T = static_cast<float*>(st.p[1]);
+    lv.rn = static_cast<float4*>(st.p[11]);
     for (int d = 0; d < 3; ++d) {
         lv.j0[d] = static_cast<int32_t*>(st.p[2 + 3 * d]);
         lv.w0[d] = static_cast<float*>(st.p[3 + 3 * d]);
@@ -249,6 +272,7 @@ ImagePassArgs image_args(ngf_ctx* c, const Level& L, const float* R, const float
     a.w1x = L.w1[0];
     a.w1y = L.w1[1];
     a.w1z = L.w1[2];
+    a.rn = L.rn;
     a.part = c->part;
     a.dpart = c->dpart;
     a.mx = L.m[0];
@@ -262,6 +286,9 @@ ImagePassArgs image_args(ngf_ctx* c, const Level& L, const float* R, const float
     a.nty = g.nty;
     a.ntz = g.ntz;
     a.cx = g.tx;
+    a.px = g.px;
+    a.py = g.py;
+    a.pz = g.pz;
     a.hx = L.h[0];
     a.hy = L.h[1];
     a.hz = L.h[2];
@@ -302,9 +329,15 @@ EvalArgs eval_args(ngf_ctx* c, const Level& L, const float* R, const float* T, c
     b.nty = a.nty;
     b.ntz = a.ntz;
     const Geo g = geometry(L, L.variant);
-    b.bx = g.tx / c->p.ratio;
-    b.by = g.ty / c->p.ratio;
-    b.bz = g.tz / c->p.ratio;
+    b.tex = g.tx;
+    b.tey = g.ty;
+    b.tez = g.tz;
+    b.mx = L.m[0];
+    b.my = L.m[1];
+    b.mz = L.m[2];
+    b.px = g.px;
+    b.py = g.py;
+    b.pz = g.pz;
     int nb[3];
     node_grid(L, nb);
     b.nbx = nb[0];
@@ -347,10 +380,12 @@ ngf_status enqueue_eval(ngf_ctx* c, const Level& L, const float* R, const float*
                         LbState* decide = nullptr) {
     const EvalArgs e = eval_args(c, L, R, T, y, grad, gate, decide);
     auto launch = [&] {
-        if (!is_march(L.variant))
-            launch_image_pass(e.a, c->p.ratio, L.variant, c->stream);
+        if (is_gen(L.variant))
+            launch_image_gen(e.a, e.a.cx, c->stream);
+        else if (!is_march(L.variant))
+            launch_image_pass(e.a, L.dyadic, L.variant, c->stream);
         else
-            launch_image_march(e.a, c->p.ratio, march_ty(L.variant), march_tz(L.variant), e.a.cx,
+            launch_image_march(e.a, L.dyadic, march_ty(L.variant), march_tz(L.variant), e.a.cx,
                                c->stream);
     };
     int li = -1;
@@ -381,9 +416,24 @@ ngf_status read_jds(ngf_ctx* c) {
     return NGF_OK;
 }
 
-std::string tune_key(const Level& L, int ratio) {
-    char buf[96];
-    std::snprintf(buf, sizeof(buf), "gfx950 %d %d %d r%d", L.m[0], L.m[1], L.m[2], ratio);
+// Autotune cache key: the device's architecture name, the image grid and
+// the deformation grid of a level.
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');  // drop feature flags (gfx950:sramecc+:xnack-)
+    if (colon != std::string::npos) a.resize(colon);
+    return a.empty() ? "unknown" : a;
+}
+std::string tune_key(const Level& L) {
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "%s %d %d %d n%d,%d,%d", device_arch().c_str(), L.m[0],
+                  L.m[1], L.m[2], L.my[0], L.my[1], L.my[2]);
     return buf;
 }
 
@@ -392,12 +442,13 @@ void tune_cache_load(ngf_ctx* c) {
     if (!path) return;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
-    char arch[32];
-    int m0, m1, m2, r, v;
-    while (std::fscanf(f, "%31s %d %d %d r%d %d", arch, &m0, &m1, &m2, &r, &v) == 6) {
+    char arch[64];
+    int m0, m1, m2, n0, n1, n2, v;
+    while (std::fscanf(f, "%63s %d %d %d n%d,%d,%d %d", arch, &m0, &m1, &m2, &n0, &n1, &n2,
+                       &v) == 8) {
         if (v < 0 || v >= kNumVariants) continue;
-        char buf[96];
-        std::snprintf(buf, sizeof(buf), "%s %d %d %d r%d", arch, m0, m1, m2, r);
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "%s %d %d %d n%d,%d,%d", arch, m0, m1, m2, n0, n1, n2);
         c->tune_cache.emplace_back(buf, v);
     }
     std::fclose(f);
@@ -418,6 +469,7 @@ void tune_cache_store(const std::string& key, int v) {
 // and 128^3 (the 32 x 32 marching tile) and of 64^3 and below (the small 3D
 // tile).
 int variant_by_size(const Level& L) {
+    if (!L.dyadic) return kMarchGen;
     return L.N() >= (int64_t{1} << 20) ? kMarchSqFit : kTile3DTiny;
 }
 
@@ -426,7 +478,10 @@ int variant_by_size(const Level& L) {
 // (whole evaluation: image pass, node pass and reduction).
 ngf_status autotune(ngf_ctx* c) {
     if (c->forced_variant >= 0) {
-        for (Level& L : c->lv) L.variant = c->forced_variant;
+        // a variant that needs a ratio of 2 or 4 gives way to the general
+        // pass on levels with other grids
+        for (Level& L : c->lv)
+            L.variant = variant_ok(L, c->forced_variant) ? c->forced_variant : kMarchGen;
         return NGF_OK;
     }
     if (c->forced_variant == kVariantBySize) {
@@ -444,7 +499,7 @@ ngf_status autotune(ngf_ctx* c) {
     HIPCHK(c, hipEventCreate(&e1));
     ngf_status st = NGF_OK;
     for (Level& L : c->lv) {
-        const std::string key = tune_key(L, c->p.ratio);
+        const std::string key = tune_key(L);
         int found = -1;
         for (auto& kv : c->tune_cache)
             if (kv.first == key) found = kv.second;
@@ -454,9 +509,10 @@ ngf_status autotune(ngf_ctx* c) {
         }
         launch_identity(c->ltmp, L.my[0], L.my[1], L.my[2], L.hy[0], L.hy[1], L.hy[2],
                         c->stream);
-        int best = kTile3D;
+        int best = L.dyadic ? kTile3D : kMarchGen;
         float best_ms = 1e30f;
         for (int v = 0; v < kNumVariants && st == NGF_OK; ++v) {
+            if (!variant_ok(L, v)) continue;
             L.variant = v;
             st = enqueue_eval(c, L, L.R, L.T, c->ltmp, c->lgt);
             if (st != NGF_OK) break;
@@ -561,6 +617,84 @@ ngf_status check_level(const ngf_ctx* c, int level) {
     return NGF_OK;
 }
 
+
+// Differentiation form on level L (its grids and index maps) with images R, T:
+// J, and grad_y / grad_T by atomic scatter (3D-tile kernel), alpha grad S
+// added by the node pass.  Uses only buffers sized beforehand.
+ngf_status eval_scatter(ngf_ctx* c, const Level& P, const float* R, const float* T,
+                        const float* y, const double* gscale, double* J, double* J_dev,
+                        float* grad_y, float* grad_T, const ScatterBufs* sb) {
+    const int r = P.dyadic;
+    double* dpart = sb ? sb->dpart : c->dpart;
+    double* spart = sb ? sb->spart : c->spart;
+    double* gpart = sb ? sb->gpart : c->gpart;
+    const bool want = grad_y != nullptr || grad_T != nullptr;
+    if (grad_y) launch_fill(grad_y, 3 * P.Ny(), 0.0f, c->stream);
+    if (grad_T) launch_fill(grad_T, P.N(), 0.0f, c->stream);
+    ImagePassArgs a = image_args(c, P, R, T, y, want);
+    a.gy_atomic = grad_y;
+    a.gT_atomic = grad_T;
+    a.gscale = gscale;
+    a.dpart = dpart;
+    a.part = nullptr;
+    if (want)
+        launch_image_pass_atomic(a, r, c->stream);
+    else
+        launch_image_pass(a, r, kTile3D, c->stream);
+    HIPCHK(c, hipGetLastError());
+    NodePassArgs b{};
+    b.y = y;
+    b.part = nullptr;
+    b.grad = grad_y;
+    b.spart = spart;
+    b.gpart = gpart;
+    b.nx = P.my[0];
+    b.ny = P.my[1];
+    b.nz = P.my[2];
+    int nb[3];
+    node_grid(P, nb);
+    b.nbx = nb[0];
+    b.nby = nb[1];
+    b.nbz = nb[2];
+    b.cxn = node_chunk(P);
+    b.hyx = P.hy[0];
+    b.hyy = P.hy[1];
+    b.hyz = P.hy[2];
+    b.ihy2x = static_cast<float>(1.0 / (P.hy[0] * P.hy[0]));
+    b.ihy2y = static_cast<float>(1.0 / (P.hy[1] * P.hy[1]));
+    b.ihy2z = static_cast<float>(1.0 / (P.hy[2] * P.hy[2]));
+    const double hbary = P.hy[0] * P.hy[1] * P.hy[2];
+    b.alpha_hbary = static_cast<float>(c->p.alpha * hbary);
+    b.alpha = static_cast<float>(c->p.alpha);
+    b.want_grad = grad_y ? 1 : 0;
+    b.gather = 0;
+    b.gscale = gscale;
+    launch_node_pass(b, c->stream);
+    HIPCHK(c, hipGetLastError());
+    ReduceArgs rd{};
+    rd.dpart = dpart;
+    rd.nd = static_cast<int>(geometry(P, kTile3D).ntiles());
+    rd.spart = spart;
+    rd.ns = static_cast<int>(node_blocks(P));
+    rd.gpart = gpart;
+    rd.ng = grad_y ? rd.ns : 0;
+    rd.half_hbar = 0.5 * P.h[0] * P.h[1] * P.h[2];
+    rd.half_hbary = 0.5 * hbary;
+    rd.alpha = c->p.alpha;
+    rd.out = c->jds;
+    launch_reduce(rd, c->stream);
+    HIPCHK(c, hipGetLastError());
+    if (J_dev)
+        HIPCHK(c, hipMemcpyAsync(J_dev, c->jds, sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream));
+    if (J) {
+        if (read_jds(c) != NGF_OK) return NGF_E_HIP;
+        *J = c->host_jds[0];
+        if (!std::isfinite(*J)) return fail(c, NGF_E_NONFINITE, "J is not finite");
+    }
+    return NGF_OK;
+}
+
 }  // namespace ngf_host
 
 // ---------------------------------------------------------------------------
@@ -591,6 +725,7 @@ ngf_status ngf_create(const ngf_params* p, void* stream, ngf_ctx** out) {
                       8 * sizeof(double) + sizeof(LbCtl), hipHostMallocDefault));
     chk(hipMalloc(reinterpret_cast<void**>(&c->st), sizeof(LbState)));
     chk(hipMalloc(reinterpret_cast<void**>(&c->dflag), sizeof(int)));
+    if (s == NGF_OK) s = static_scratch_setup(c);
     if (s != NGF_OK) {
         ngf_destroy(c);
         return s;
@@ -634,7 +769,14 @@ ngf_status ngf_set_params(ngf_ctx* c, const ngf_params* p) {
     if (!params_ok(p, &why)) return fail(c, NGF_E_ARG, why);
     if (!c->lv.empty() && (p->levels != c->p.levels || p->ratio != c->p.ratio))
         return fail(c, NGF_E_STATE, "levels and ratio are fixed once a pyramid is built");
+    const bool rho_changed = p->rho != c->p.rho;
     c->p = *p;
+    if (rho_changed) {
+        for (const Level& L : c->lv)
+            launch_rn(L.R, L.rn, L.m[0], L.m[1], L.m[2], L.h[0], L.h[1], L.h[2], c->p.rho,
+                      c->stream);
+        HIPCHK(c, hipGetLastError());
+    }
     return NGF_OK;
 }
 
@@ -643,16 +785,26 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
     if (!c) return NGF_E_ARG;
     if (!R || !T || !g) return fail(c, NGF_E_ARG, "null R, T or grid");
     const int L = c->p.levels, r = c->p.ratio;
-    const int64_t div = static_cast<int64_t>(r) << (L - 1);
     int64_t N = 1;
+    int n0[3];  // level-0 deformation-grid nodes per axis
     for (int d = 0; d < 3; ++d) {
         if (!(std::isfinite(g->h[d]) && g->h[d] > 0.0))
             return fail(c, NGF_E_ARG, "spacing must be positive");
-        if (g->m[d] <= 0 || g->m[d] % div != 0)
+        if (g->m[d] <= 0 || g->m[d] > 32768 || g->m[d] % (1 << (L - 1)) != 0)
+            return fail(c, NGF_E_SHAPE,
+                        "each m_d must be at most 32768 and divisible by 2^(levels-1)");
+        if (c->node_grid[d] == 0 && g->m[d] % (r << (L - 1)) != 0)
             return fail(c, NGF_E_SHAPE, "each m_d must be divisible by ratio * 2^(levels-1)");
-        const int mc = g->m[d] >> (L - 1);
-        if (mc < 4 || mc / r < 2)
+        n0[d] = c->node_grid[d] ? c->node_grid[d] : g->m[d] / r + 1;
+        if ((n0[d] - 1) % (1 << (L - 1)) != 0)
+            return fail(c, NGF_E_SHAPE,
+                        "node cells m^y_d - 1 must be divisible by 2^(levels-1)");
+        const int mc = g->m[d] >> (L - 1), nc = ((n0[d] - 1) >> (L - 1)) + 1;
+        if (mc < 4 || nc < 3)
             return fail(c, NGF_E_SHAPE, "coarsest level needs >= 4 cells and >= 2 node cells");
+        if (2 * (n0[d] - 1) > g->m[d])
+            return fail(c, NGF_E_SHAPE,
+                        "at least 2 image cells per deformation cell: 2 (m^y_d - 1) <= m_d");
         N *= g->m[d];
     }
     if (N >= (static_cast<int64_t>(1) << 30))
@@ -664,8 +816,14 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
         for (int d = 0; d < 3; ++d) {
             lv.m[d] = g->m[d] >> l;
             lv.h[d] = g->h[d] * static_cast<double>(1 << l);
-            lv.my[d] = lv.m[d] / r + 1;
+            lv.my[d] = ((n0[d] - 1) >> l) + 1;
             lv.hy[d] = lv.m[d] * lv.h[d] / (lv.my[d] - 1);
+        }
+        lv.dyadic = 0;
+        for (const int q : {2, 4}) {
+            bool all = true;
+            for (int d = 0; d < 3; ++d) all = all && lv.m[d] % q == 0 && lv.my[d] == lv.m[d] / q + 1;
+            if (all) lv.dyadic = q;
         }
         const ngf_status e = bind_level_storage(c, l);
         if (e != NGF_OK) {
@@ -701,6 +859,13 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
                              c->lv[l].my[d], c->stream);
     HIPCHK(c, hipStreamWaitEvent(c->stream, c->join[1], 0));
     HIPCHK(c, hipStreamWaitEvent(c->stream, c->join[2], 0));
+    // reference side of the NGF term, per level (general image pass)
+    for (int l = 0; l < L; ++l) {
+        const Level& lv = c->lv[l];
+        launch_rn(lv.R, lv.rn, lv.m[0], lv.m[1], lv.m[2], lv.h[0], lv.h[1], lv.h[2], c->p.rho,
+                  c->stream);
+    }
+    HIPCHK(c, hipGetLastError());
     // reject non-finite inputs
     int zero = 0;
     HIPCHK(c, hipMemcpyAsync(c->dflag, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
@@ -732,6 +897,18 @@ ngf_status ngf_set_driver(ngf_ctx* c, int32_t mode) {
     if (!c) return NGF_E_ARG;
     if (mode != 0 && mode != 1) return fail(c, NGF_E_ARG, "mode must be 0 or 1");
     c->host_driven = mode == 1;
+    return NGF_OK;
+}
+
+ngf_status ngf_set_node_grid(ngf_ctx* c, const int32_t my0[3]) {
+    if (!c) return NGF_E_ARG;
+    for (int d = 0; d < 3; ++d) {
+        const int v = my0 ? my0[d] : 0;
+        if (v != 0 && v < 3) return fail(c, NGF_E_ARG, "node counts must be 0 or >= 3");
+    }
+    for (int d = 0; d < 3; ++d) c->node_grid[d] = my0 ? my0[d] : 0;
+    c->lv.clear();  // the next ngf_build_pyramid uses the new grid
+    c->lb_level = -1;
     return NGF_OK;
 }
 
@@ -1125,70 +1302,24 @@ ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], con
         HIPCHK(c, hipGetLastError());
     }
     P.variant = kTile3D;  // the scatter form lives in the 3D-tile kernel
+    P.dyadic = r;
     if (const ngf_status st = ensure_scratch(c, P); st != NGF_OK) return st;
-    const bool want = grad_y != nullptr || grad_T != nullptr;
-    if (grad_y) launch_fill(grad_y, 3 * P.Ny(), 0.0f, c->stream);
-    if (grad_T) launch_fill(grad_T, P.N(), 0.0f, c->stream);
-    ImagePassArgs a = image_args(c, P, R, T, y, want);
-    a.gy_atomic = grad_y;
-    a.gT_atomic = grad_T;
-    a.gscale = gscale;
-    if (want)
-        launch_image_pass_atomic(a, r, c->stream);
-    else
-        launch_image_pass(a, r, kTile3D, c->stream);
-    HIPCHK(c, hipGetLastError());
-    NodePassArgs b{};
-    b.y = y;
-    b.part = nullptr;
-    b.grad = grad_y;
-    b.spart = c->spart;
-    b.gpart = c->gpart;
-    b.nx = P.my[0];
-    b.ny = P.my[1];
-    b.nz = P.my[2];
-    int nb[3];
-    node_grid(P, nb);
-    b.nbx = nb[0];
-    b.nby = nb[1];
-    b.nbz = nb[2];
-    b.cxn = node_chunk(P);
-    b.hyx = P.hy[0];
-    b.hyy = P.hy[1];
-    b.hyz = P.hy[2];
-    b.ihy2x = static_cast<float>(1.0 / (P.hy[0] * P.hy[0]));
-    b.ihy2y = static_cast<float>(1.0 / (P.hy[1] * P.hy[1]));
-    b.ihy2z = static_cast<float>(1.0 / (P.hy[2] * P.hy[2]));
-    const double hbary = P.hy[0] * P.hy[1] * P.hy[2];
-    b.alpha_hbary = static_cast<float>(c->p.alpha * hbary);
-    b.alpha = static_cast<float>(c->p.alpha);
-    b.want_grad = grad_y ? 1 : 0;
-    b.gather = 0;
-    b.gscale = gscale;
-    launch_node_pass(b, c->stream);
-    HIPCHK(c, hipGetLastError());
-    ReduceArgs rd{};
-    rd.dpart = c->dpart;
-    rd.nd = static_cast<int>(geometry(P, kTile3D).ntiles());
-    rd.spart = c->spart;
-    rd.ns = static_cast<int>(node_blocks(P));
-    rd.gpart = c->gpart;
-    rd.ng = grad_y ? rd.ns : 0;
-    rd.half_hbar = 0.5 * P.h[0] * P.h[1] * P.h[2];
-    rd.half_hbary = 0.5 * hbary;
-    rd.alpha = c->p.alpha;
-    rd.out = c->jds;
-    launch_reduce(rd, c->stream);
-    HIPCHK(c, hipGetLastError());
-    if (J_dev)
-        HIPCHK(c, hipMemcpyAsync(J_dev, c->jds, sizeof(double), hipMemcpyDeviceToDevice,
-                                 c->stream));
-    if (J) {
-        if (read_jds(c) != NGF_OK) return NGF_E_HIP;
-        *J = c->host_jds[0];
-        if (!std::isfinite(*J)) return fail(c, NGF_E_NONFINITE, "J is not finite");
-    }
-    return NGF_OK;
+    return eval_scatter(c, P, R, T, y, gscale, J, J_dev, grad_y, grad_T, nullptr);
+}
+
+ngf_status ngf_eval_J_grad_T(ngf_ctx* c, int32_t level, const float* y, const double* gscale,
+                             double* J, double* J_dev, float* grad_y, float* grad_T) {
+    if (!c) return NGF_E_ARG;
+    const ngf_status s = check_level(c, level);
+    if (s != NGF_OK) return fail(c, s, "no pyramid or bad level");
+    if (!y) return fail(c, NGF_E_ARG, "null y");
+    const Level& L = c->lv[level];
+    if (!L.dyadic)
+        return fail(c, NGF_E_SHAPE,
+                    "the scatter form needs a deformation grid of m/2 + 1 or m/4 + 1 nodes");
+    Level P = L;  // same grids and buffers; the scatter lives in the 3D-tile kernel
+    P.variant = kTile3D;
+    return eval_scatter(c, P, L.R, L.T, y, gscale, J, J_dev, grad_y, grad_T, nullptr);
 }
 
 }  // extern "C"

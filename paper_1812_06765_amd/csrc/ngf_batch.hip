@@ -240,7 +240,9 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
                 const auto* args = static_cast<const ImagePassArgs*>(P(o_args));
                 const auto* blk = static_cast<const BlockRef*>(P(g.off));
                 const int nb = static_cast<int>(g.blk.size());
-                if (is_march(g.variant))
+                if (is_gen(g.variant))
+                    launch_image_gen_batch(args, blk, nb, g.pow2, s);
+                else if (is_march(g.variant))
                     launch_image_march_batch(args, blk, nb, ratio, g.variant, g.pow2, s);
                 else
                     launch_image_pass_batch(args, blk, nb, ratio, g.variant, g.pow2, s);

@@ -26,7 +26,11 @@ struct Level {
     int32_t* j0[3] = {nullptr, nullptr, nullptr};
     float* w0[3] = {nullptr, nullptr, nullptr};
     float* w1[3] = {nullptr, nullptr, nullptr};
+    float4* rn = nullptr;   // reference side of the NGF term (general image pass)
     int variant = kTile3D;  // image-pass variant (autotuned or forced)
+    // every axis has m^y = m/r + 1 for one r in {2, 4}: 2 or 4; otherwise 0
+    // (then only the general image pass applies)
+    int dyadic = 2;
     int64_t N() const { return static_cast<int64_t>(m[0]) * m[1] * m[2]; }
     int64_t Ny() const { return static_cast<int64_t>(my[0]) * my[1] * my[2]; }
 };
@@ -34,7 +38,7 @@ struct Level {
 struct LevelStore {
     int64_t cap_n = 0;               // floats in R and in T
     int cap_m[3] = {0, 0, 0};        // entries per index-map axis
-    void* p[11] = {};                // R, T, then j0, w0, w1 per axis
+    void* p[12] = {};                // R, T, then j0, w0, w1 per axis, then rn
 };
 
 constexpr int kProfMax = 4096;
@@ -89,6 +93,8 @@ struct ngf_ctx {
 
     int faults = 0;            // failure injection (NGF_FAULT_*)
     bool host_driven = false;  // register_levels: host-side line search (one sync per trial)
+    // level-0 deformation-grid nodes per axis set by ngf_set_node_grid (0: m/ratio + 1)
+    int node_grid[3] = {0, 0, 0};
 
     // image-pass variant: -1 = autotune, else forced for every level
     int forced_variant = -1;  // also kVariantBySize
@@ -114,6 +120,7 @@ namespace ngf_host {
 struct Geo {
     int tx, ty, tz;
     int ntx, nty, ntz;
+    int px, py, pz;  // nodes per tile block of the P^T partial sums
     int64_t ntiles() const { return static_cast<int64_t>(ntx) * nty * ntz; }
 };
 Geo geometry(const Level& L, int variant);
@@ -133,5 +140,19 @@ struct EvalArgs {
 EvalArgs eval_args(ngf_ctx* c, const Level& L, const float* R, const float* T, const float* y,
                    float* grad, const int* gate, LbState* decide);
 bool pow2(double h);
+void node_grid(const Level& L, int nb[3]);
+
+// Partial-sum buffers of the differentiation form (null: the context's own).
+struct ScatterBufs {
+    double* dpart;
+    double* spart;
+    double* gpart;
+};
+ngf_status eval_scatter(ngf_ctx* c, const Level& P, const float* R, const float* T,
+                        const float* y, const double* gscale, double* J, double* J_dev,
+                        float* grad_y, float* grad_T, const ScatterBufs* sb);
+// Device address of the static scratch array of the no-allocation entry
+// point on the current device; taken once per device at context creation.
+ngf_status static_scratch_setup(ngf_ctx* c);
 
 }  // namespace ngf_host

@@ -24,6 +24,7 @@ constexpr int kMY = 16;
 // Node pass: (y, z) tile of kNMY x kNMZ nodes, marching along x in a chunk
 // fitted to the grid and the device.
 constexpr int kNMY = 8, kNMZ = 32;
+constexpr int kNodeChunkMax = 256;  // node planes per node-pass workgroup, at most
 
 // Image-pass variants the autotuner chooses from: the 3D-tile kernel at three
 // tile sizes, and the marching kernel with in-plane tile 16 x 64 or 16 x 32
@@ -38,12 +39,14 @@ enum Variant {
     kMarch64x16 = 9, kMarch32x16 = 10,
     kMarch32Fit = 11, kMarch64Fit = 12,
     kMarchSqFit = 13,  // 32 x 32 (y, z) tile, 512-thread workgroups, fitted x chunk
-    kNumVariants = 14
+    kMarchGen = 14,    // general index maps, 32 x 32 tile, one barrier per plane
+    kNumVariants = 15
 };
 constexpr int kVariantBySize = -2;  // selection rule instead of timed selection
 inline bool is_march(int v) {
     return (v >= kMarch64x8 && v <= kMarch32x32) || (v >= kMarch64x16 && v <= kMarchSqFit);
 }
+inline bool is_gen(int v) { return v == kMarchGen; }
 // 3D-tile extents (x, y, z) of the 3D-tile variants
 inline int tile3d_x(int v) { return v == kTile3D ? 8 : 4; }
 inline int tile3d_y(int v) { return v == kTile3DTiny ? 4 : 8; }
@@ -58,7 +61,10 @@ inline int march_cx(int v) {
 inline int march_tz(int v) {
     return (v <= kMarch64x32 || v == kMarch64x16 || v == kMarch64Fit) ? 64 : 32;
 }
-inline int march_ty(int v) { return v == kMarchSqFit ? 32 : kMY; }
+inline int march_ty(int v) { return (v == kMarchSqFit || v == kMarchGen) ? 32 : kMY; }
+// variants whose kernels hold a grid ratio of 2 or 4 in their code (the
+// general pass reads the index maps and takes any ratio >= 2)
+inline bool needs_dyadic(int v) { return v != kMarchGen; }
 // Workgroups of the marching kernel with (y, z) tile ty x tz that the
 // current device holds at once (occupancy per CU times the CU count).
 int image_march_slots(int ty, int tz);
@@ -69,8 +75,9 @@ int image_march_slots(int ty, int tz);
 // planes a workgroup walks (its chunk plus four lead-in and lead-out steps).
 // A chunk that fills the slots once beats a shorter one that needs a partly
 // empty last round.
-inline int fit_chunk(int len, int64_t across, int step, int lo, int slots) {
-    const int top = ((len + step - 1) / step) * step;
+inline int fit_chunk(int len, int64_t across, int step, int lo, int slots, int hi = 1 << 30) {
+    int top = ((len + step - 1) / step) * step;
+    if (top > hi) top = hi;
     int best = lo;
     int64_t best_cost = -1;
     for (int cx = lo; cx <= (top > lo ? top : lo); cx += step) {
@@ -82,6 +89,42 @@ inline int fit_chunk(int len, int64_t across, int step, int lo, int slots) {
 }
 // Workgroups of the marching node pass the current device holds at once.
 int node_march_slots();
+// Workgroups of the general marching image pass the device holds at once.
+int image_gen_slots();
+
+// Index maps of the grid conversion along one axis of m image cells and n
+// nodes (Sec. 2.2, "Grid conversion"): image point i lies at node coordinate
+// (2i+1)(n-1)/(2m), so its lower node is j0(i) = (2i+1)(n-1) div 2m.
+// first_at_least(k) is the smallest i with j0(i) >= k (m when there is none).
+// Exact in 32-bit integers for m <= 32768 (checked by the host).
+__host__ __device__ inline int map_lower(int i, int m, int n) {
+    return ((2 * i + 1) * (n - 1)) / (2 * m);
+}
+__host__ __device__ inline int first_at_least(int k, int m, int n) {
+    if (k <= 0) return 0;
+    const int c = (2 * m * k + (n - 2)) / (n - 1);  // ceil(2 m k / (n - 1))
+    const int i = c / 2;                            // ceil((c - 1) / 2)
+    return i < m ? i : m;
+}
+// Image tiles of extent te along an axis that hold node j in their blocks of
+// P^T partial sums: the tiles of the first and the last image point of the
+// node's index set (Eq. 3), and the node's place in each block (a tile's
+// block starts at the lower node of the tile's first point).  tb < 0: one
+// tile.
+struct NodeTiles {
+    int ta, la, tb, lb;
+};
+__host__ __device__ inline NodeTiles node_tiles(int j, int m, int n, int te) {
+    const int ilo = first_at_least(j - 1, m, n);
+    const int ihi = first_at_least(j + 1, m, n) - 1;
+    NodeTiles r;
+    r.ta = ilo / te;
+    r.la = j - map_lower(r.ta * te, m, n);
+    const int tb = ihi / te;
+    r.tb = tb != r.ta ? tb : -1;
+    r.lb = tb != r.ta ? j - map_lower(tb * te, m, n) : 0;
+    return r;
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumbering gives each XCD a contiguous range of tiles, so that
@@ -114,12 +157,14 @@ struct ImagePassArgs {
     const int32_t* j0x; const int32_t* j0y; const int32_t* j0z;
     const float* w0x; const float* w0y; const float* w0z;
     const float* w1x; const float* w1y; const float* w1z;
-    float* part;           // P^T partial sums per tile, [tile][3][(BX+1)(BY+1)(BZ+1)]
+    const float4* rn;      // reference side of the NGF term per voxel (general pass)
+    float* part;           // P^T partial sums per tile, [tile][3][px][py][pz]
     double* dpart;         // sum over the tile of (1 - r^2), one per tile
     int mx, my, mz;        // image cells
     int nx, ny, nz;        // deformation nodes
     int ntx, nty, ntz;     // tiles per axis
     int cx;                // x chunk of the marching form (image planes)
+    int px, py, pz;        // nodes per tile block of the P^T partial sums, per axis
     double hx, hy, hz;     // spacing (float64: continuous index of the warp)
     double ihx, ihy, ihz;  // 1 / h, used only when every h is a power of two
     int pow2h;             // 1: every spacing is a power of two (exact reciprocal)
@@ -143,7 +188,9 @@ struct NodePassArgs {
     double* gpart;         // per block: [0] max |grad|, [1] sum grad^2
     int nx, ny, nz;
     int ntx, nty, ntz;     // image-pass tiles per axis
-    int bx, by, bz;        // node cells per image tile per axis
+    int tex, tey, tez;     // image-pass tile extent per axis (voxels)
+    int mx, my, mz;        // image cells per axis (for the index maps)
+    int px, py, pz;        // nodes per tile block of the image-pass partial sums
     int nbx, nby, nbz;     // node-pass blocks per axis
     int cxn;               // x chunk of the marching form (node planes)
     double hyx, hyy, hyz;  // node spacing (float64, for X = j h^y)
@@ -288,6 +335,11 @@ void launch_prolongate(const float* yc, float* yf, int cx, int cy, int cz, hipSt
 void launch_image_pass(const ImagePassArgs& a, int ratio, int variant, hipStream_t s);
 void launch_image_march(const ImagePassArgs& a, int ratio, int ty, int tz, int cx,
                         hipStream_t s);
+void launch_image_gen(const ImagePassArgs& a, int cx, hipStream_t s);
+void launch_image_gen_batch(const ImagePassArgs* args, const BlockRef* blk, int nblk, bool pow2,
+                            hipStream_t s);
+void launch_rn(const float* R, float4* rn, int mx, int my, int mz, double hx, double hy,
+               double hz, double rho, hipStream_t s);
 void launch_node_pass(const NodePassArgs& a, hipStream_t s);
 void launch_reduce(const ReduceArgs& a, hipStream_t s);
 void launch_check_finite(const float* v, int64_t n, int* flag, hipStream_t s);

@@ -91,6 +91,11 @@ def load():
         "ngf_set_kernel": ([_P, i32], i32),
         "ngf_set_driver": ([_P, i32], i32),
         "ngf_set_faults": ([_P, i32], i32),
+        "ngf_eval_pair_static": ([_P, ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_int32 * 3),
+                                  _P, _P, _P, _P, ctypes.POINTER(f64), _P, _P, _P], i32),
+        "ngf_eval_J_grad_T": ([_P, i32, _P, _P, ctypes.POINTER(ctypes.c_double), _P, _P, _P],
+                              i32),
+        "ngf_set_node_grid": ([_P, ctypes.POINTER(i32)], i32),
         "ngf_apply_P": ([_P, i32, _P, _P], i32),
         "ngf_apply_PT": ([_P, i32, _P, _P, i32], i32),
         "ngf_get_kernel": ([_P, i32, ctypes.POINTER(i32)], i32),
@@ -307,7 +312,9 @@ class Context:
             self._f32(R, name="R")
             self._f32(T, R.shape, name="T")
         g = _grid(R.shape, h)
-        my = tuple(int(R.shape[d]) // self.p.ratio + 1 for d in range(3))
+        ng = getattr(self, "node_grid", None)
+        my = tuple((ng[d] if ng and ng[d] else int(R.shape[d]) // self.p.ratio + 1)
+                   for d in range(3))
         y = torch.empty((3,) + my, dtype=torch.float32,
                         device="cpu" if host else self.device)
         if host:
@@ -327,13 +334,14 @@ class Context:
 
     # -- differentiation form -------------------------------------------------
     def eval_pair(self, R, T, y, h=(1.0, 1.0, 1.0), grad_y=True, grad_T=True, gscale=None,
-                  J_dev=None, sync=True):
+                  J_dev=None, sync=True, static=False):
         """J and gradients with respect to y and T on an explicit pair.
 
         Returns (J or None, grad_y or None, grad_T or None).  ``gscale`` is an
         optional device float64 scalar multiplying both gradients; ``J_dev``
         an optional device float64 scalar receiving J; with ``sync=False`` J
-        is not brought to the host.
+        is not brought to the host.  ``static=True`` calls the variant that
+        allocates nothing (scratch in a static device array of the library).
         """
         self._f32(R, name="R")
         self._f32(T, R.shape, name="T")
@@ -347,14 +355,28 @@ class Context:
             if t is not None and not (t.dtype == torch.float64 and t.is_cuda and t.numel() == 1):
                 raise TypeError(f"{name} must be a one-element float64 tensor on the GPU")
         J = ctypes.c_double()
-        self._chk(self.lib.ngf_eval_pair(self.h, ctypes.byref(g), ctypes.byref(myc), _ptr(R),
-                                         _ptr(T), _ptr(y), _ptr(gscale),
-                                         ctypes.byref(J) if sync else None, _ptr(J_dev),
-                                         _ptr(gy), _ptr(gT)))
+        fn = self.lib.ngf_eval_pair_static if static else self.lib.ngf_eval_pair
+        self._chk(fn(self.h, ctypes.byref(g), ctypes.byref(myc), _ptr(R), _ptr(T), _ptr(y),
+                     _ptr(gscale), ctypes.byref(J) if sync else None, _ptr(J_dev), _ptr(gy),
+                     _ptr(gT)))
         return (J.value if sync else None), gy, gT
 
     # -- standalone grid conversion -----------------------------------------
     PT_SCHEMES = {"gather": 0, "atomic": 1, "redblack": 2}
+
+    def eval_J_grad_T(self, level, y, grad_y=True, grad_T=True, gscale=None, J_dev=None,
+                      sync=True):
+        """The differentiation form on pyramid level ``level`` (no allocation
+        in the library).  Returns (J or None, grad_y or None, grad_T or None)."""
+        li = self.level_info(level)
+        self._f32(y, (3,) + li.my, "y")
+        gy = torch.empty_like(y) if grad_y else None
+        gT = torch.empty(li.m, dtype=torch.float32, device=self.device) if grad_T else None
+        J = ctypes.c_double()
+        self._chk(self.lib.ngf_eval_J_grad_T(self.h, int(level), _ptr(y), _ptr(gscale),
+                                             ctypes.byref(J) if sync else None, _ptr(J_dev),
+                                             _ptr(gy), _ptr(gT)))
+        return (J.value if sync else None), gy, gT
 
     def apply_P(self, level, y):
         li = self.level_info(level)
@@ -375,7 +397,7 @@ class Context:
     VARIANTS = {"by_size": -2, "auto": -1, "tile3d": 0, "march64x8": 1, "march64x20": 2, "march64x32": 3,
                 "march32x8": 4, "march32x20": 5, "march32x32": 6, "tile3d_small": 7, "tile3d_tiny": 8,
                 "march64x16": 9, "march32x16": 10, "march32fit": 11, "march64fit": 12,
-                "march32sq": 13}
+                "march32sq": 13, "general": 14}
 
     def set_kernel(self, variant):
         """Image-pass variant: 'auto' (autotune), 'by_size' (size rule), a name
@@ -386,6 +408,16 @@ class Context:
     def set_driver(self, mode):
         """Line search of register(): 'device' (default) or 'host'."""
         self._chk(self.lib.ngf_set_driver(self.h, {"device": 0, "host": 1}[mode]))
+
+    def set_node_grid(self, my0=None):
+        """Level-0 deformation-grid node counts per axis (None or 0 entries:
+        m/ratio + 1).  Takes effect at the next build_pyramid / register."""
+        if my0 is None:
+            self._chk(self.lib.ngf_set_node_grid(self.h, None))
+        else:
+            arr = (ctypes.c_int32 * 3)(*[int(v) for v in my0])
+            self._chk(self.lib.ngf_set_node_grid(self.h, arr))
+        self.node_grid = None if my0 is None else tuple(int(v) for v in my0)
 
     FAULT_REJECT_STEPS = 1
     FAULT_ALLOC = 2

@@ -174,3 +174,46 @@ def test_pair_form_on_a_grid_of_a_million_nodes(gpu_lib):
     _say(f"[pair 1M] J {J} oracle {Jo}; grad y rel-L2 {ey:.2e}, grad T rel-L2 {eT:.2e}")
     assert abs(J - Jo) <= 1e-5 * abs(Jo)
     assert ey <= 1e-4 and eT <= 1e-4
+
+
+def test_level_form_matches_pair_form_and_oracle(gpu_lib):
+    """ngf_eval_J_grad_T on a pyramid level (buffers from the pyramid, no
+    allocation) against the pair form on the same level's images, and both
+    against the oracle's dJ/dy and dJ/dT."""
+    ngf = gpu_lib
+    m = (128, 128, 128)
+    pr = synth.ct_phantom_pair(m, seed_R=3, seed_u=4)
+    ctx = ngf.Context(alpha=0.1, tau=10.0, rho=10.0, levels=2)
+    ctx.build_pyramid(_t(pr.R), _t(pr.T))
+    Rs, Ts = O.pyramid(pr.R, pr.T, 2)
+    for lev in (1, 0):
+        li = ctx.level_info(lev)
+        prob = O.Problem(Rs[lev], Ts[lev], li.h, li.my, 0.1, 10.0, 10.0)
+        d = synth.smooth_node_perturbation(li.my, 8.0, 1.5 * li.h[0], 17 + lev)
+        y32 = (prob.identity() + d).astype(np.float32)
+        J, gy, gT = ctx.eval_J_grad_T(lev, _t(y32))
+        Rl, Tl = ctx.level_images(lev)
+        Jp, gyp, gTp = ctx.eval_pair(Rl, Tl, _t(y32), li.h)
+        Jo, go, gTo, _ = O.eval_J_grad_T(prob, y32.astype(np.float64))
+        gy = gy.cpu().numpy().astype(np.float64)
+        gT = gT.cpu().numpy().astype(np.float64)
+        ey = np.linalg.norm(gy - go) / np.linalg.norm(go)
+        eT = np.linalg.norm(gT - gTo) / np.linalg.norm(gTo)
+        _say(f"[level form] level {lev}: J {J} pair {Jp} oracle {Jo}; grad y {ey:.2e}, "
+             f"grad T {eT:.2e}")
+        assert J == Jp
+        assert abs(J - Jo) <= 1e-5 * abs(Jo)
+        assert ey <= 1e-4 and eT <= 1e-4
+        assert float((gyp.double() - torch_from(gy)).norm() / torch_from(gy).norm()) <= 1e-6
+    # a general grid has no scatter form
+    ctx2 = ngf.Context(alpha=0.1, tau=10.0, rho=10.0, levels=1)
+    ctx2.set_node_grid((37, 37, 37))
+    ctx2.build_pyramid(_t(pr.R), _t(pr.T))
+    with pytest.raises(ngf.NgfError) as e:
+        ctx2.eval_J_grad_T(0, ctx2.identity(0))
+    assert e.value.status == ngf.E_SHAPE
+
+
+def torch_from(a):
+    import torch
+    return torch.from_numpy(a).cuda()

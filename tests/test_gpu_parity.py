@@ -47,7 +47,7 @@ def _y(prob, amp, seed, spacing=8.0):
 
 VARIANTS = ("tile3d", "march64x8", "march64x20", "march64x32", "march32x8", "march32x20",
             "march32x32", "tile3d_small", "tile3d_tiny", "march64x16", "march32x16", "march32fit",
-            "march64fit", "march32sq")
+            "march64fit", "march32sq", "general")
 
 
 def _check_eval(ngf, ctx, level, prob, y32, tag, variants=VARIANTS):

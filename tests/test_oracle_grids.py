@@ -162,3 +162,28 @@ def test_prolongate_matches_np_interp_and_identity(mc):
     Xc = O.identity(tuple(v // 2 for v in m), tuple(2 * v for v in h), mc)
     Xf = O.identity(m, h, mf)
     assert np.array_equal(O.prolongate(Xc), Xf)
+
+
+def test_level_shapes_with_node_counts():
+    """Node counts given at level 0 halve their cells per level; with
+    m/ratio + 1 they reproduce the ratio rule; on a general grid the coarse
+    identity still prolongates to the fine identity (node positions j h^y of
+    the halved grid are the even fine nodes)."""
+    m, h = (48, 64, 96), (1.0, 0.5, 2.0)
+    assert O.level_shapes(m, h, 3, 2, my0=(25, 33, 49)) == O.level_shapes(m, h, 3, 2)
+    sh = O.level_shapes(m, h, 3, my0=(17, 33, 25))  # ratios 3, 2, 4
+    assert [s[2] for s in sh] == [(17, 33, 25), (9, 17, 13), (5, 9, 7)]
+    # non-integer ratios: 64 / 26 and 40 / 18 image cells per node cell
+    sh = O.level_shapes((64, 40, 64), (1.0, 1.0, 1.0), 2, my0=(27, 19, 33))
+    for lev in (1,):
+        (mc, hc, nc), (mf, hf, nf) = sh[lev], sh[lev - 1]
+        Xc, Xf = O.identity(mc, hc, nc), O.identity(mf, hf, nf)
+        assert np.allclose(O.prolongate(Xc), Xf, rtol=0, atol=1e-12)
+    # brute force: P of the identity is the cell centres on these grids too
+    (mf, hf, nf) = sh[0]
+    yh = O.apply_P(O.identity(mf, hf, nf), mf, nf)
+    for d in range(3):
+        c = (np.arange(mf[d]) + 0.5) * hf[d]
+        shp = [1, 1, 1]
+        shp[d] = mf[d]
+        assert np.max(np.abs(yh[d] - c.reshape(shp))) < 1e-12
