@@ -151,8 +151,9 @@ ngf_status ngf_build_pyramid(ngf_ctx* ctx, const float* R, const float* T,
  * m_d / ratio + 1; a NULL my0 resets all three.  Level l then has
  * (my0[d] - 1) / 2^l + 1 nodes along axis d, so ngf_build_pyramid requires
  * my0[d] - 1 divisible by 2^(levels-1), at least 2 node cells on the
- * coarsest level, and at least two image cells per node cell
- * (2 (my0[d] - 1) <= m_d; the ratio need not be an integer).  Levels whose
+ * coarsest level, and between two and sixteen image cells per node cell
+ * (2 (my0[d] - 1) <= m_d <= 16 (my0[d] - 1); the ratio need not be an
+ * integer), else NGF_E_SHAPE there.  Levels whose
  * grids are m/2 + 1 or m/4 + 1 on every axis may use every image-pass
  * variant; any other grid uses variant 14.  Clears a built pyramid.
  * Errors: NGF_E_ARG for a count in 1..2. */

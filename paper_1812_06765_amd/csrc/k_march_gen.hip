@@ -435,7 +435,8 @@ __device__ __forceinline__ void gen_body(const ImagePassArgs& a, int CX, int blo
                 const int gy = gyof(kk), gz = gzof(kk);
                 const int p = (gy - y0 + 2) * GH + (gz - z0 + 2);  // the clamped voxel
                 const float4 rn = bld4(rR, static_cast<uint32_t>(gy * mz + gz) * 16u, 0u);
-                const float gRx = rn.x, gRy = rn.y, gRz = rn.z, ibb = rn.w;
+                const float gRx = rn.x, gRy = rn.y, gRz = rn.z;
+                const float ibb = __builtin_amdgcn_rcpf(rn.w);
                 const float gTx = (tyv[kk][2] - tyv[kk][0]) * a.i2hx;
                 const float gTy = (T0[p + GH] - T0[p - GH]) * a.i2hy;
                 const float gTz = (T0[p + 1] - T0[p - 1]) * a.i2hz;
@@ -595,7 +596,7 @@ __global__ __launch_bounds__(GNI / KP, 4) void k_image_gen_batch(const ImagePass
     gen_body<KP, true, POW2>(a, a.cx, e.block);
 }
 
-// Reference side of the NGF term per voxel: (grad R, 1/(|grad R|^2 + rho^2))
+// Reference side of the NGF term per voxel: (grad R, |grad R|^2 + rho^2)
 // by central differences with replicated ends -- the same expressions, in
 // the same order, as the template side forms in the image passes, so that
 // identical images give identical factors.
@@ -618,7 +619,7 @@ __global__ __launch_bounds__(kThreads) void k_rn(const float* __restrict__ R, fl
         const float gRy = (p[dyp] - p[-dym]) * i2hy;
         const float gRz = (p[dzp] - p[-dzm]) * i2hz;
         const float bb = fmaf(gRx, gRx, fmaf(gRy, gRy, fmaf(gRz, gRz, rho * rho)));
-        rn[i] = make_float4(gRx, gRy, gRz, __builtin_amdgcn_rcpf(bb));
+        rn[i] = make_float4(gRx, gRy, gRz, bb);
     }
 }
 

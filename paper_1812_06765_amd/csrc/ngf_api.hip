@@ -70,6 +70,15 @@ int tiles(int m, int t) { return (m + t - 1) / t; }
 // Nodes in the largest block of P^T partial sums over tiles of extent te
 // along an axis: a tile's block runs from the lower node of its first image
 // point to the upper node of its last.
+// Image points in the largest index set of Eq. 3 along an axis (the points
+// whose lower or upper node is j, over all nodes j).
+int index_set_span(int m, int n) {
+    int s = 0;
+    for (int j = 0; j < n; ++j)
+        s = std::max(s, first_at_least(j + 1, m, n) - first_at_least(j - 1, m, n));
+    return s;
+}
+
 int block_nodes(int m, int n, int te) {
     int best = 0;
     for (int t0 = 0; t0 < m; t0 += te) {
@@ -83,7 +92,11 @@ Geo geometry(const Level& L, int variant) {
     Geo g{};
     if (is_gen(variant)) {
         g.ty = g.tz = 32;
-        g.tx = fit_chunk(L.m[0], int64_t{tiles(L.m[1], 32)} * tiles(L.m[2], 32), 4, 4,
+        // the node pass adds the partial sums of at most two tiles per axis,
+        // so every index set along x must meet at most two chunks: a chunk
+        // of at least (span - 1) planes
+        const int lo = std::max(4, (index_set_span(L.m[0], L.my[0]) + 2) / 4 * 4);
+        g.tx = fit_chunk(L.m[0], int64_t{tiles(L.m[1], 32)} * tiles(L.m[2], 32), 4, lo,
                          image_gen_slots());
     } else if (is_tile3d(variant)) {
         g.tx = tile3d_x(variant);
@@ -805,6 +818,11 @@ ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const n
         if (2 * (n0[d] - 1) > g->m[d])
             return fail(c, NGF_E_SHAPE,
                         "at least 2 image cells per deformation cell: 2 (m^y_d - 1) <= m_d");
+        // the image tiles (32 points in y and z) must each meet every index
+        // set of Eq. 3 in at most two tiles per axis
+        if (g->m[d] > 16 * (n0[d] - 1))
+            return fail(c, NGF_E_SHAPE,
+                        "at most 16 image cells per deformation cell: m_d <= 16 (m^y_d - 1)");
         N *= g->m[d];
     }
     if (N >= (static_cast<int64_t>(1) << 30))

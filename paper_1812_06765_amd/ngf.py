@@ -411,7 +411,8 @@ class Context:
 
     def set_node_grid(self, my0=None):
         """Level-0 deformation-grid node counts per axis (None or 0 entries:
-        m/ratio + 1).  Takes effect at the next build_pyramid / register."""
+        m/ratio + 1), with 2 to 16 image cells per node cell.  Takes effect at
+        the next build_pyramid / register."""
         if my0 is None:
             self._chk(self.lib.ngf_set_node_grid(self.h, None))
         else:
