@@ -113,9 +113,20 @@ Geo geometry(const Level& L, int variant) {
     g.ntx = tiles(L.m[0], g.tx);
     g.nty = tiles(L.m[1], g.ty);
     g.ntz = tiles(L.m[2], g.tz);
-    g.px = block_nodes(L.m[0], L.my[0], g.tx);
-    g.py = block_nodes(L.m[1], L.my[1], g.ty);
-    g.pz = block_nodes(L.m[2], L.my[2], g.tz);
+    if (is_gen(variant)) {
+        // this kernel takes the block extents as arguments: the nodes a
+        // tile's points reach, at most
+        g.px = block_nodes(L.m[0], L.my[0], g.tx);
+        g.py = block_nodes(L.m[1], L.my[1], g.ty);
+        g.pz = block_nodes(L.m[2], L.my[2], g.tz);
+    } else {
+        // the kernels for a ratio of 2 or 4 write blocks of tile/ratio + 1
+        // nodes per axis, also where the level is narrower than the tile
+        const int r = L.dyadic > 0 ? L.dyadic : 2;
+        g.px = g.tx / r + 1;
+        g.py = g.ty / r + 1;
+        g.pz = g.tz / r + 1;
+    }
     return g;
 }
 int64_t part_floats(const Level& L, int variant) {

@@ -291,13 +291,19 @@ def test_register_blob32_against_oracle(gpu_lib):
 
 
 def test_register_multilevel_and_host_path(gpu_lib):
+    """A registration from host arrays equals the one from device arrays bit
+    for bit.  Both contexts take the image-pass variants of the size rule:
+    two autotuning contexts may time a different winner for a level, and
+    the variants sum the P^T partials in different orders."""
     import torch
     ngf = gpu_lib
     pr = synth.ct_phantom_pair((128, 128, 128), seed_R=3, seed_u=4)
     ctx = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=3, max_iter=10)
+    ctx.set_kernel("by_size")
     y_dev, rep = ctx.register(_t(pr.R), _t(pr.T))
     assert len(rep) == 3 and all(r["iters"] >= 1 for r in rep)
     ctx2 = _ctx(ngf, alpha=0.1, tau=10.0, rho=10.0, levels=3, max_iter=10)
+    ctx2.set_kernel("by_size")
     y_host, rep2 = ctx2.register(torch.from_numpy(pr.R), torch.from_numpy(pr.T))
     assert torch.equal(y_dev.cpu(), y_host)
     assert [r["J"] for r in rep] == [r["J"] for r in rep2]
