@@ -350,9 +350,11 @@ ngf_status ngf_eval_J_grad_T(ngf_ctx* ctx, int32_t level, const float* y, const 
  *     the write conflicts of P^T are avoided: 0 = gather, one thread per node
  *     summing its index sets (Eq. 3, the paper's scheme); 1 = scatter with
  *     float atomic additions, one thread per image point (the earlier GPU
- *     scheme the paper cites); 2 = red-black: four colour phases over the
- *     (x, y) cells, one thread per cell column scattering serially (the
- *     earlier CPU scheme).  Results agree up to the order of float32 sums. */
+ *     scheme the paper cites); 2 = red-black: the slices of the odd x cells
+ *     in parallel, then those of the even ones (the earlier scheme the paper
+ *     cites); within a cell one thread per (y, z) node sums the cell's slices
+ *     over its index sets and adds them to the two node planes of the cell.
+ *     Results agree up to the order of float32 sums. */
 ngf_status ngf_apply_P(ngf_ctx* ctx, int32_t level, const float* y, float* yhat);
 ngf_status ngf_apply_PT(ngf_ctx* ctx, int32_t level, const float* z, float* out,
                         int32_t scheme);
@@ -427,6 +429,31 @@ ngf_status ngf_batch_set_mode(ngf_batch* b, int32_t mode);
 ngf_status ngf_batch_register(ngf_batch* b, int32_t npairs, const float* const* R,
                               const float* const* T, const ngf_grid* grids,
                               float* const* y_out, void* stream, ngf_report* reports);
+
+/* The batched evaluation (Sec. 2.1, Eq. 1 and 2, applied pair by pair):
+ * J and grad J of many pairs at given deformations, each stage one launch
+ * covering all pairs (one image pass per image-pass variant in use, one node
+ * pass, one reduction).  Every pair's J and gradient equal those of the
+ * single-pair ngf_eval_J_grad with the same variant bit for bit.
+ *   ngf_batch_build  builds the pyramids of npairs pairs (R[i], T[i]: device
+ *                    float32 images of grids[i]) in the batch's pair
+ *                    contexts (the ones graph mode registers with; an
+ *                    ngf_batch_register in graph mode leaves its pairs built
+ *                    as well); `stream` as for ngf_batch_register.
+ *                    Allocates; synchronises.
+ *   ngf_batch_eval   at pyramid level `level` of every built pair: y[i]
+ *                    device float32 [3][m^y of that level] (ngf_level_info),
+ *                    J (host, npairs doubles, or NULL), grad (NULL for J
+ *                    only, else npairs device float32 buffers like y[i]);
+ *                    ordered after the work queued on `stream`;
+ *                    synchronises.  Allocates only when the batch's table
+ *                    buffer or the pinned J buffer must grow.
+ * Errors: NGF_E_STATE before any build, NGF_E_LEVEL for a level a pair does
+ * not have, NGF_E_ARG for null pointers. */
+ngf_status ngf_batch_build(ngf_batch* b, int32_t npairs, const float* const* R,
+                           const float* const* T, const ngf_grid* grids, void* stream);
+ngf_status ngf_batch_eval(ngf_batch* b, int32_t level, const float* const* y, double* J,
+                          float* const* grad, void* stream);
 
 #ifdef __cplusplus
 }

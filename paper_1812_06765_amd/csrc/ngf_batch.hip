@@ -63,6 +63,9 @@ struct ngf_batch {
     size_t dtab_cap = 0;
     LbCtl* hctl = nullptr;  // pinned
     size_t hctl_cap = 0;
+    double* hJ = nullptr;   // pinned, one J per pair (ngf_batch_eval)
+    size_t hJ_cap = 0;
+    int nbuilt = 0;         // pairs whose pyramids the pair contexts hold
     std::string err;
 };
 
@@ -108,9 +111,11 @@ size_t put(std::vector<char>& host, const std::vector<T>& v) {
     return off;
 }
 
-ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const float* const* T,
-                          const ngf_grid* grids, float* const* y_out, ngf_report* reports) {
-    // contexts, one per pair slot, on the batch stream
+// Pair contexts (one per pair slot, on the batch stream) holding the
+// pyramids of the pairs.
+ngf_status build_pairs(ngf_batch* b, int np, const float* const* R, const float* const* T,
+                       const ngf_grid* grids) {
+    b->nbuilt = 0;
     while (static_cast<int>(b->pctx.size()) < np) {
         ngf_ctx* c = nullptr;
         const ngf_status s = ngf_create(&b->p, b->stream, &c);
@@ -129,6 +134,57 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
         if (s != NGF_OK) return bfail(b, s, "pair " + std::to_string(i) + ": " + c->err);
         b->tune = c->tune_cache;
     }
+    b->nbuilt = np;
+    return NGF_OK;
+}
+
+// Upload a table image to the batch's device buffer (grown on demand, after
+// the work queued on the batch stream is done).
+ngf_status upload_tables(ngf_batch* b, const std::vector<char>& host, size_t bytes) {
+    if (host.size() > b->dtab_cap) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, NGF_E_HIP, "sync");
+        if (b->dtab) (void)hipFree(b->dtab);
+        b->dtab = nullptr;
+        b->dtab_cap = 0;
+        if (hipMalloc(reinterpret_cast<void**>(&b->dtab), host.size() * 2) != hipSuccess)
+            return bfail(b, NGF_E_OOM, "batch tables");
+        b->dtab_cap = host.size() * 2;
+    }
+    if (hipMemcpyAsync(b->dtab, host.data(), bytes, hipMemcpyHostToDevice, b->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess)
+        return bfail(b, NGF_E_HIP, "upload of the batch tables failed");
+    return NGF_OK;
+}
+
+// One image pass per variant group, each covering its pairs' blocks.
+void launch_image_groups(const std::vector<LevelTables::Group>& groups, const char* d,
+                         size_t o_args, int ratio, hipStream_t s) {
+    for (const auto& g : groups) {
+        const auto* args = reinterpret_cast<const ImagePassArgs*>(d + o_args);
+        const auto* blk = reinterpret_cast<const BlockRef*>(d + g.off);
+        const int nb = static_cast<int>(g.blk.size());
+        if (is_gen(g.variant))
+            launch_image_gen_batch(args, blk, nb, g.pow2, s);
+        else if (is_march(g.variant))
+            launch_image_march_batch(args, blk, nb, ratio, g.variant, g.pow2, s);
+        else
+            launch_image_pass_batch(args, blk, nb, ratio, g.variant, g.pow2, s);
+    }
+}
+
+// The variant group of a level in a block-table set.
+LevelTables::Group& group_of(LevelTables& t, const Level& lv) {
+    const bool p2 = pow2(lv.h[0]) && pow2(lv.h[1]) && pow2(lv.h[2]);
+    for (auto& gg : t.groups)
+        if (gg.variant == lv.variant && gg.pow2 == p2) return gg;
+    t.groups.push_back(LevelTables::Group{lv.variant, p2, {}, 0});
+    return t.groups.back();
+}
+
+ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const float* const* T,
+                          const ngf_grid* grids, float* const* y_out, ngf_report* reports) {
+    if (const ngf_status s = build_pairs(b, np, R, T, grids); s != NGF_OK) return s;
     if (reports)
         for (int i = 0; i < np; ++i) {
             std::memset(&reports[i], 0, sizeof(ngf_report));
@@ -195,15 +251,7 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
             v.tol = b->p.tol_J;
             t.vec.push_back(v);
             // block tables
-            const bool p2 = pow2(lv.h[0]) && pow2(lv.h[1]) && pow2(lv.h[2]);
-            LevelTables::Group* g = nullptr;
-            for (auto& gg : t.groups)
-                if (gg.variant == lv.variant && gg.pow2 == p2) g = &gg;
-            if (!g) {
-                t.groups.push_back(LevelTables::Group{lv.variant, p2, {}, 0});
-                g = &t.groups.back();
-            }
-            add_blocks(g->blk, i, geometry(lv, lv.variant).ntiles());
+            add_blocks(group_of(t, lv).blk, i, geometry(lv, lv.variant).ntiles());
             add_blocks(t.node_blk, i, node_blocks(lv));
             add_blocks(t.vec_blk, i, v.nblocks);
         }
@@ -218,36 +266,13 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
         const size_t o_vblk = put(host, t.vec_blk);
         const size_t o_ctl = align_up(host.size(), 256);
         host.resize(o_ctl + np * sizeof(LbCtl));
-        if (host.size() > b->dtab_cap) {
-            if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, NGF_E_HIP, "sync");
-            if (b->dtab) (void)hipFree(b->dtab);
-            b->dtab = nullptr;
-            b->dtab_cap = 0;
-            if (hipMalloc(reinterpret_cast<void**>(&b->dtab), host.size() * 2) != hipSuccess)
-                return bfail(b, NGF_E_OOM, "batch tables");
-            b->dtab_cap = host.size() * 2;
-        }
         // the previous level's graph has finished reading the tables (the
         // control blocks were read back after its last replay)
-        if (hipMemcpyAsync(b->dtab, host.data(), o_ctl, hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return bfail(b, NGF_E_HIP, "upload of the batch tables failed");
+        if (const ngf_status us = upload_tables(b, host, o_ctl); us != NGF_OK) return us;
         char* d = b->dtab;
         auto P = [&](size_t off) { return static_cast<void*>(d + off); };
         const int ratio = b->p.ratio;
-        auto image_stage = [&](size_t o_args) {
-            for (const auto& g : t.groups) {
-                const auto* args = static_cast<const ImagePassArgs*>(P(o_args));
-                const auto* blk = static_cast<const BlockRef*>(P(g.off));
-                const int nb = static_cast<int>(g.blk.size());
-                if (is_gen(g.variant))
-                    launch_image_gen_batch(args, blk, nb, g.pow2, s);
-                else if (is_march(g.variant))
-                    launch_image_march_batch(args, blk, nb, ratio, g.variant, g.pow2, s);
-                else
-                    launch_image_pass_batch(args, blk, nb, ratio, g.variant, g.pow2, s);
-            }
-        };
+        auto image_stage = [&](size_t o_args) { launch_image_groups(t.groups, d, o_args, ratio, s); };
         const auto* vec = static_cast<const LbVecArgs*>(P(o_vec));
         const int nvb = static_cast<int>(t.vec_blk.size());
         auto node_stage = [&](size_t o_args) {
@@ -339,6 +364,62 @@ ngf_status graph_register(ngf_batch* b, int np, const float* const* R, const flo
             return bfail(b, NGF_E_HIP, "copy of a result failed");
     }
     if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, NGF_E_HIP, "final sync failed");
+    return NGF_OK;
+}
+
+// J and grad J of every built pair at level `lev`: one image pass per
+// variant group, one node pass and one reduction, each covering all pairs.
+ngf_status batch_eval(ngf_batch* b, int lev, const float* const* y, double* J,
+                      float* const* grad) {
+    const int np = b->nbuilt;
+    hipStream_t s = b->stream;
+    LevelTables t;
+    std::vector<ReduceArgs> red;
+    for (int i = 0; i < np; ++i) {
+        ngf_ctx* c = b->pctx[i];
+        if (lev < 0 || lev >= static_cast<int>(c->lv.size()))
+            return bfail(b, NGF_E_LEVEL, "level out of range");
+        const Level& lv = c->lv[lev];
+        // the batched kernels always form the gradient: for J alone it goes
+        // to the pair context's trial-gradient vector (sized for level 0)
+        float* gi = grad ? grad[i] : c->lgt;
+        const EvalArgs e = eval_args(c, lv, lv.R, lv.T, y[i], gi, nullptr, nullptr);
+        t.img0.push_back(e.a);
+        t.node0.push_back(e.b);
+        red.push_back(e.r);
+        add_blocks(group_of(t, lv).blk, i, geometry(lv, lv.variant).ntiles());
+        add_blocks(t.node_blk, i, node_blocks(lv));
+    }
+    std::vector<char> host;
+    const size_t o_img = put(host, t.img0), o_node = put(host, t.node0), o_red = put(host, red);
+    for (auto& g : t.groups) g.off = put(host, g.blk);
+    const size_t o_nblk = put(host, t.node_blk);
+    if (const ngf_status us = upload_tables(b, host, host.size()); us != NGF_OK) return us;
+    const char* d = b->dtab;
+    launch_image_groups(t.groups, d, o_img, b->p.ratio, s);
+    launch_node_pass_batch(reinterpret_cast<const NodePassArgs*>(d + o_node),
+                           reinterpret_cast<const BlockRef*>(d + o_nblk),
+                           static_cast<int>(t.node_blk.size()), s);
+    launch_reduce_batch(reinterpret_cast<const ReduceArgs*>(d + o_red), np, s);
+    if (hipGetLastError() != hipSuccess) return bfail(b, NGF_E_HIP, "batched evaluation launch");
+    if (J) {
+        if (b->hJ_cap < static_cast<size_t>(np)) {
+            if (b->hJ) (void)hipHostFree(b->hJ);
+            b->hJ = nullptr;
+            b->hJ_cap = 0;
+            if (hipHostMalloc(reinterpret_cast<void**>(&b->hJ), np * sizeof(double),
+                              hipHostMallocDefault) != hipSuccess)
+                return bfail(b, NGF_E_OOM, "pinned J buffer");
+            b->hJ_cap = np;
+        }
+        for (int i = 0; i < np; ++i)
+            if (hipMemcpyAsync(b->hJ + i, b->pctx[i]->jds, sizeof(double), hipMemcpyDeviceToHost,
+                               s) != hipSuccess)
+                return bfail(b, NGF_E_HIP, "copy of J failed");
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return bfail(b, NGF_E_HIP, "evaluation failed");
+    if (J)
+        for (int i = 0; i < np; ++i) J[i] = b->hJ[i];
     return NGF_OK;
 }
 
@@ -450,6 +531,7 @@ void ngf_batch_destroy(ngf_batch* b) {
     }
     if (b->dtab) (void)hipFree(b->dtab);
     if (b->hctl) (void)hipHostFree(b->hctl);
+    if (b->hJ) (void)hipHostFree(b->hJ);
     if (b->start) (void)hipEventDestroy(b->start);
     delete b;
 }
@@ -486,10 +568,42 @@ ngf_status ngf_batch_register(ngf_batch* b, int32_t npairs, const float* const* 
     // the inputs may still be written by work queued on the caller's stream
     if (hipEventRecord(b->start, static_cast<hipStream_t>(stream)) != hipSuccess)
         return bfail(b, NGF_E_HIP, "hipEventRecord on the caller's stream failed");
-    if (b->mode == 1) return thread_register(b, npairs, R, T, grids, y_out, reports);
+    if (b->mode == 1) {
+        b->nbuilt = 0;  // the worker contexts do not keep the pairs
+        return thread_register(b, npairs, R, T, grids, y_out, reports);
+    }
     if (hipStreamWaitEvent(b->stream, b->start, 0) != hipSuccess)
         return bfail(b, NGF_E_HIP, "hipStreamWaitEvent failed");
     return graph_register(b, npairs, R, T, grids, y_out, reports);
+}
+
+ngf_status ngf_batch_build(ngf_batch* b, int32_t npairs, const float* const* R,
+                           const float* const* T, const ngf_grid* grids, void* stream) {
+    if (!b) return NGF_E_ARG;
+    b->nbuilt = 0;
+    if (npairs < 0) return bfail(b, NGF_E_ARG, "npairs must be >= 0");
+    if (npairs == 0) return NGF_OK;
+    if (!R || !T || !grids) return bfail(b, NGF_E_ARG, "null array argument");
+    for (int i = 0; i < npairs; ++i)
+        if (!R[i] || !T[i]) return bfail(b, NGF_E_ARG, "null pointer for pair " + std::to_string(i));
+    if (hipEventRecord(b->start, static_cast<hipStream_t>(stream)) != hipSuccess ||
+        hipStreamWaitEvent(b->stream, b->start, 0) != hipSuccess)
+        return bfail(b, NGF_E_HIP, "ordering after the caller's stream failed");
+    return build_pairs(b, npairs, R, T, grids);
+}
+
+ngf_status ngf_batch_eval(ngf_batch* b, int32_t level, const float* const* y, double* J,
+                          float* const* grad, void* stream) {
+    if (!b) return NGF_E_ARG;
+    if (b->nbuilt == 0) return bfail(b, NGF_E_STATE, "no pairs built (ngf_batch_build)");
+    if (!y) return bfail(b, NGF_E_ARG, "null y array");
+    for (int i = 0; i < b->nbuilt; ++i)
+        if (!y[i] || (grad && !grad[i]))
+            return bfail(b, NGF_E_ARG, "null pointer for pair " + std::to_string(i));
+    if (hipEventRecord(b->start, static_cast<hipStream_t>(stream)) != hipSuccess ||
+        hipStreamWaitEvent(b->stream, b->start, 0) != hipSuccess)
+        return bfail(b, NGF_E_HIP, "ordering after the caller's stream failed");
+    return batch_eval(b, level, y, J, grad);
 }
 
 }  // extern "C"

@@ -110,6 +110,10 @@ def load():
         "ngf_batch_register": ([_P, i32, ctypes.POINTER(_P), ctypes.POINTER(_P),
                                 ctypes.POINTER(Grid), ctypes.POINTER(_P), _P,
                                 ctypes.POINTER(Report)], i32),
+        "ngf_batch_build": ([_P, i32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                             ctypes.POINTER(Grid), _P], i32),
+        "ngf_batch_eval": ([_P, i32, ctypes.POINTER(_P), ctypes.POINTER(f64),
+                            ctypes.POINTER(_P), _P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -478,6 +482,7 @@ class Batch:
         if st != OK:
             raise NgfError(st, "ngf_batch_create failed")
         self.h = h
+        self.built = []
         self.set_mode(mode)
 
     def close(self):
@@ -503,6 +508,7 @@ class Batch:
         """'graph' (default: batched launches per round, captured as a
         hipGraph) or 'threads' (worker threads, one context each)."""
         self._chk(self.lib.ngf_batch_set_mode(self.h, {"graph": 0, "threads": 1}[mode]))
+        self.mode = mode
 
     def register(self, Rs, Ts, hs=None, out=None):
         """Register pairs (Rs[i], Ts[i]) (contiguous float32 device tensors)
@@ -531,4 +537,53 @@ class Batch:
         stream = torch.cuda.current_stream(self.device).cuda_stream
         self._chk(self.lib.ngf_batch_register(self.h, n, arr(Rs), arr(Ts), grids, arr(ys),
                                               ctypes.c_void_p(stream), reps))
+        # graph mode leaves the pairs built in its pair contexts
+        self.built = [tuple(int(v) for v in R.shape) for R in Rs] if self.mode == "graph" else []
         return ys, [Context._report(reps[i]) for i in range(n)]
+
+    def build(self, Rs, Ts, hs=None):
+        """Pyramids of the pairs (Rs[i], Ts[i]) for ``eval``."""
+        n = len(Rs)
+        if len(Ts) != n:
+            raise ValueError("as many templates as references are needed")
+        hs = hs if hs is not None else [(1.0, 1.0, 1.0)] * n
+        grids = (Grid * max(n, 1))()
+        for i in range(n):
+            for name, t in (("R", Rs[i]), ("T", Ts[i])):
+                if not (isinstance(t, torch.Tensor) and t.dtype == torch.float32 and t.is_cuda
+                        and t.is_contiguous() and t.dim() == 3):
+                    raise TypeError(f"{name}[{i}] must be a contiguous 3D float32 GPU tensor")
+            if tuple(Rs[i].shape) != tuple(Ts[i].shape):
+                raise ValueError(f"pair {i}: R and T differ in shape")
+            grids[i] = _grid(Rs[i].shape, hs[i])
+        arr = lambda ts: (_P * max(n, 1))(*[t.data_ptr() for t in ts])
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self._chk(self.lib.ngf_batch_build(self.h, n, arr(Rs), arr(Ts), grids,
+                                           ctypes.c_void_p(stream)))
+        self.built = [tuple(int(v) for v in R.shape) for R in Rs]
+
+    def node_shape(self, i, level=0):
+        """Node counts of pair i's deformation grid on ``level``."""
+        return tuple((int(v) // self.p.ratio >> level) + 1 for v in self.built[i])
+
+    def eval(self, level, ys, want_grad=True):
+        """J and grad J of every built pair at ys[i] (contiguous float32
+        device tensors of node_shape(i, level)), in batched launches.
+        Returns (list of J, list of gradients or None)."""
+        n = len(self.built)
+        if len(ys) != n:
+            raise ValueError(f"{n} pairs are built, {len(ys)} deformations given")
+        for i, y in enumerate(ys):
+            if not (isinstance(y, torch.Tensor) and y.dtype == torch.float32 and y.is_cuda
+                    and y.is_contiguous()):
+                raise TypeError(f"y[{i}] must be a contiguous float32 GPU tensor")
+            if tuple(y.shape) != (3,) + self.node_shape(i, level):
+                raise ValueError(f"y[{i}] has shape {tuple(y.shape)}")
+        gs = [torch.empty_like(y) for y in ys] if want_grad else None
+        arr = lambda ts: (_P * max(n, 1))(*[t.data_ptr() for t in ts])
+        J = (ctypes.c_double * max(n, 1))()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self._chk(self.lib.ngf_batch_eval(self.h, int(level), arr(ys), J,
+                                          arr(gs) if gs is not None else None,
+                                          ctypes.c_void_p(stream)))
+        return [J[i] for i in range(n)], gs

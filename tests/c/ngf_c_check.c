@@ -6,8 +6,15 @@
  *   ngf_c_check gpu   a two-level registration (Sec. 2.1) of a synthetic
  *                     pair from host arrays: a smooth ball and the same
  *                     ball moved by one voxel along x; checks the report and
- *                     that the recovered displacement points along +x
+ *                     that the recovered displacement points along +x; then
+ *                     at the result, with device buffers: the level form of
+ *                     the differentiation (ngf_eval_J_grad_T) against
+ *                     ngf_eval_J_grad, and the batched evaluation
+ *                     (ngf_batch_build, ngf_batch_eval) of two pairs against
+ *                     the single-pair one
  *
+ * Device memory comes from the HIP runtime's C entry points, declared here
+ * by hand (the caller includes no HIP header).
  * Exit status 0 on success; a failed check prints its reason.
  */
 #include <math.h>
@@ -16,6 +23,12 @@
 #include <string.h>
 
 #include "ngfreg.h"
+
+/* HIP runtime entry points used for device buffers (libamdhip64) */
+int hipMalloc(void** ptr, size_t size);
+int hipFree(void* ptr);
+int hipMemcpy(void* dst, const void* src, size_t size, int kind);
+enum { H2D = 1, D2H = 2 };
 
 #define CHECK(cond, ...)                                                  \
     do {                                                                  \
@@ -68,6 +81,94 @@ static int cpu_checks(void) {
 static float ball(double x, double y, double z, double cx) {
     const double r = sqrt((x - cx) * (x - cx) + (y - 16.0) * (y - 16.0) + (z - 16.0) * (z - 16.0));
     return (float)(1.0 / (1.0 + exp(2.0 * (r - 8.0))));
+}
+
+/* relative L2 distance of two float vectors */
+static double rel_l2(const float* a, const float* b, size_t n) {
+    double num = 0.0, den = 0.0;
+    size_t i;
+    for (i = 0; i < n; ++i) {
+        num += ((double)a[i] - b[i]) * ((double)a[i] - b[i]);
+        den += (double)b[i] * b[i];
+    }
+    return sqrt(num / den);
+}
+
+/* At the registered y (host), with the pyramid the registration built. */
+static int device_forms(ngf_ctx* c, const ngf_params* p, const float* R, const float* T,
+                        const float* y) {
+    enum { M = 32, MY = M / 2 + 1 };
+    const size_t n = (size_t)M * M * M, ny = (size_t)3 * MY * MY * MY;
+    float *dR = NULL, *dT = NULL, *dy = NULL, *dg = NULL, *dgy = NULL, *dgT = NULL, *dg2 = NULL;
+    float* hg = malloc(ny * sizeof(float));
+    float* hgy = malloc(ny * sizeof(float));
+    float* hg2 = malloc(ny * sizeof(float));
+    ngf_batch* b = NULL;
+    ngf_grid g[2];
+    double J = 0.0, JT = 0.0, Jb[2] = {0.0, 0.0};
+    ngf_status st;
+    CHECK(hg && hgy && hg2, "host allocation");
+    CHECK(hipMalloc((void**)&dR, n * 4) == 0 && hipMalloc((void**)&dT, n * 4) == 0 &&
+              hipMalloc((void**)&dy, ny * 4) == 0 && hipMalloc((void**)&dg, ny * 4) == 0 &&
+              hipMalloc((void**)&dgy, ny * 4) == 0 && hipMalloc((void**)&dgT, n * 4) == 0 &&
+              hipMalloc((void**)&dg2, ny * 4) == 0,
+          "hipMalloc");
+    CHECK(hipMemcpy(dR, R, n * 4, H2D) == 0 && hipMemcpy(dT, T, n * 4, H2D) == 0 &&
+              hipMemcpy(dy, y, ny * 4, H2D) == 0,
+          "hipMemcpy to the device");
+    /* the plain form and the level form of the differentiation, same variants */
+    CHECK(ngf_set_kernel(c, -2) == NGF_OK, "ngf_set_kernel");
+    st = ngf_eval_J_grad(c, 0, dy, &J, dg, NULL);
+    CHECK(st == NGF_OK, "ngf_eval_J_grad: %d (%s)", (int)st, ngf_last_error(c));
+    st = ngf_eval_J_grad_T(c, 0, dy, NULL, &JT, NULL, dgy, dgT);
+    CHECK(st == NGF_OK, "ngf_eval_J_grad_T: %d (%s)", (int)st, ngf_last_error(c));
+    CHECK(hipMemcpy(hg, dg, ny * 4, D2H) == 0 && hipMemcpy(hgy, dgy, ny * 4, D2H) == 0,
+          "hipMemcpy to the host");
+    printf("level form: J %.9g (plain %.9g), grad y rel-L2 %.2e\n", JT, J, rel_l2(hgy, hg, ny));
+    CHECK(fabs(JT - J) <= 1e-6 * fabs(J), "J of the level form");
+    CHECK(rel_l2(hgy, hg, ny) <= 1e-5, "grad y of the level form");
+    /* the batched evaluation: (R, T) and (T, R), compared with the single pair */
+    {
+        const float* Rs[2];
+        const float* Ts[2];
+        const float* ys[2];
+        float* gs[2];
+        Rs[0] = dR;
+        Ts[0] = dT;
+        Rs[1] = dT;
+        Ts[1] = dR;
+        ys[0] = dy;
+        ys[1] = dy;
+        gs[0] = dg2;
+        gs[1] = dgy;
+        g[0].m[0] = g[0].m[1] = g[0].m[2] = M;
+        g[0].h[0] = g[0].h[1] = g[0].h[2] = 1.0;
+        g[1] = g[0];
+        CHECK(ngf_batch_create(p, 1, &b) == NGF_OK, "ngf_batch_create");
+        CHECK(ngf_batch_set_kernel(b, -2) == NGF_OK, "ngf_batch_set_kernel");
+        CHECK(ngf_batch_eval(b, 0, ys, Jb, gs, NULL) == NGF_E_STATE, "eval before build");
+        st = ngf_batch_build(b, 2, Rs, Ts, g, NULL);
+        CHECK(st == NGF_OK, "ngf_batch_build: %d (%s)", (int)st, ngf_batch_last_error(b));
+        st = ngf_batch_eval(b, 0, ys, Jb, gs, NULL);
+        CHECK(st == NGF_OK, "ngf_batch_eval: %d (%s)", (int)st, ngf_batch_last_error(b));
+        CHECK(hipMemcpy(hg2, dg2, ny * 4, D2H) == 0, "hipMemcpy to the host");
+        printf("batched: J %.9g and %.9g (single pair %.9g)\n", Jb[0], Jb[1], J);
+        CHECK(Jb[0] == J && memcmp(hg2, hg, ny * 4) == 0, "batched pair 0 differs");
+        CHECK(isfinite(Jb[1]) && Jb[1] > 0.0, "batched pair 1");
+        ngf_batch_destroy(b);
+    }
+    hipFree(dR);
+    hipFree(dT);
+    hipFree(dy);
+    hipFree(dg);
+    hipFree(dgy);
+    hipFree(dgT);
+    hipFree(dg2);
+    free(hg);
+    free(hgy);
+    free(hg2);
+    printf("c abi gpu device forms ok\n");
+    return 0;
 }
 
 static int gpu_registration(void) {
@@ -131,11 +232,12 @@ static int gpu_registration(void) {
            sz, umax);
     CHECK(sx > 0.25 && sx > 4.0 * (fabs(sy) + fabs(sz)), "displacement not along +x");
     CHECK(umax < 4.0, "displacement too large");
+    printf("c abi gpu registration ok\n");
+    if (device_forms(c, &p, R, T, y) != 0) return 1;
     ngf_destroy(c);
     free(R);
     free(T);
     free(y);
-    printf("c abi gpu registration ok\n");
     return 0;
 }
 

@@ -85,9 +85,11 @@ def _build_c_check(tmp_path):
     import subprocess
     pkg = os.path.join(ROOT, "paper_1812_06765_amd")
     exe = str(tmp_path / "ngf_c_check")
+    rocm = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
     cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", f"-I{os.path.join(ROOT, 'include')}",
            os.path.join(ROOT, "tests", "c", "ngf_c_check.c"), f"-L{pkg}", "-lngfreg",
-           f"-Wl,-rpath,{pkg}", "-lm", "-o", exe]
+           f"-Wl,-rpath,{pkg}", f"-L{rocm}", "-lamdhip64", f"-Wl,-rpath,{rocm}", "-lm",
+           "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     return exe

@@ -161,3 +161,48 @@ def test_batch_error_names_the_pair(gpu_lib, MODE):
     ys, _ = b.register([good[0]], [good[1]])
     assert bool(torch.isfinite(ys[0]).all())
     b.close()
+
+
+def test_batch_eval_equals_single_pair_eval_and_oracle(gpu_lib):
+    """The batched evaluation (ngf_batch_build, then ngf_batch_eval: one
+    image pass per variant in use, one node pass and one reduction over all
+    pairs) on pairs of different shapes, at two pyramid levels: every J and
+    gradient bit for bit the single-pair ngf_eval_J_grad's with the same
+    variant, which the oracle pins (J within 1e-5, grad J within 1e-4
+    relative L2), checked here again for one pair; the value-only form gives
+    the same J."""
+    import torch
+
+    import oracle as O
+    ngf = gpu_lib
+    shapes = [(64, 48, 32), (32, 64, 48), (48, 48, 48)]
+    pairs = _pairs(shapes, 71)
+    b = ngf.Batch(levels=2, max_iter=5, **PARAMS)
+    b.set_kernel("by_size")
+    b.build([p[0] for p in pairs], [p[1] for p in pairs])
+    single = ngf.Context(levels=2, max_iter=5, **PARAMS)
+    single.set_kernel("by_size")
+    for lev in (0, 1):
+        ys = []
+        for i, m in enumerate(shapes):
+            my = b.node_shape(i, lev)
+            X = O.identity(tuple(v >> lev for v in m), (2.0 ** lev,) * 3, my)
+            d = synth.smooth_node_perturbation(my, 4.0, 1.5 * 2 ** lev, 80 + i)
+            ys.append(torch.from_numpy((X + d).astype(np.float32)).cuda())
+        Js, gs = b.eval(lev, ys)
+        Jv, gv = b.eval(lev, ys, want_grad=False)
+        assert gv is None and Jv == Js
+        for i, (R, T) in enumerate(pairs):
+            single.build_pyramid(R, T)
+            J, g, _ = single.eval_J_grad(lev, ys[i])
+            _say(f"[batch eval] level {lev} pair {shapes[i]}: J {Js[i]} single {J}")
+            assert Js[i] == J and bool(torch.equal(gs[i], g))
+        # the oracle on the last pair at this level
+        Rl, Tl = single.level_images(lev)
+        prob = O.Problem(Rl.cpu().numpy().astype(np.float64), Tl.cpu().numpy().astype(np.float64),
+                         (2.0 ** lev,) * 3, b.node_shape(2, lev), 0.1, 10.0, 10.0)
+        Jo, go, _ = O.eval_J_grad(prob, ys[2].cpu().numpy().astype(np.float64))
+        err = float(np.linalg.norm(gs[2].cpu().numpy() - go) / np.linalg.norm(go))
+        assert abs(Js[2] - Jo) <= 1e-5 * abs(Jo) and err <= 1e-4
+    single.close()
+    b.close()

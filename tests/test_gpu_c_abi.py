@@ -1,6 +1,7 @@
-"""The C ABI from a plain C program on the GPU: a two-level registration of
-a synthetic pair from host arrays (tests/c/ngf_c_check.c), with no Python or
-torch in the caller."""
+"""The C ABI from a plain C program on the GPU (tests/c/ngf_c_check.c), with
+no Python or torch in the caller: a two-level registration of a synthetic
+pair from host arrays, then at its result the level form of the
+differentiation and the batched evaluation from device buffers."""
 
 import subprocess
 import sys
@@ -19,3 +20,4 @@ def test_c_caller_registers_on_the_gpu(tmp_path):
     sys.stdout.write(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "gpu registration ok" in r.stdout
+    assert "gpu device forms ok" in r.stdout
