@@ -6,10 +6,12 @@
 //   write has one owner;
 // * atomic scatter (the earlier GPU scheme): one thread per image point adds
 //   its weighted value into the 8 nodes of its cell with atomic additions;
-// * red-black slices (the earlier CPU scheme): image points are grouped by
-//   their x and y cell; groups whose cells are two apart never touch the same
-//   node, so four colour phases run one thread per group, each thread
-//   scattering its group serially without atomics.
+// * red-black slices (the earlier scheme): the image slices of the odd x
+//   cells are done in parallel, then those of the even x cells.  A cell's
+//   slices reach only the node planes at its two ends, and cells of one
+//   parity are two apart, so within a phase no two cells share a node plane;
+//   within a cell one thread per (y, z) node sums the slices over its y and
+//   z index sets and adds the result to the two node planes (no atomics).
 //
 // All three compute the same sums (in different orders).  These operators
 // are for measurement and testing; the evaluation itself fuses P into the
@@ -62,18 +64,14 @@ __device__ inline float omega(const Maps& a, int d, int i, int j) {
     return j0 == j ? a.w0[d][i] : (j0 + 1 == j ? a.w1[d][i] : 0.0f);
 }
 
-// first image index of node j's index set along one axis (the set is the
-// contiguous run of image points whose cell touches the node)
-__device__ inline int omega_lo(const Maps& a, int d, int j) {
-    int lo = 0, hi = a.m[d];  // smallest i with j0[i] + 1 >= j
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a.j0[d][mid] + 1 >= j)
-            hi = mid;
-        else
-            lo = mid + 1;
-    }
-    return lo;
+// index set of node j along one axis (Eq. 3): the contiguous run of image
+// points whose lower node is j - 1 or j, [lo, hi), from the exact integer
+// map (no table search)
+struct Range {
+    int lo, hi;
+};
+__device__ inline Range omega_range(const Maps& a, int d, int j) {
+    return Range{first_at_least(j - 1, a.m[d], a.n[d]), first_at_least(j + 1, a.m[d], a.n[d])};
 }
 
 __global__ __launch_bounds__(kThreads) void k_PT_gather(Maps a, const float* __restrict__ z,
@@ -85,13 +83,14 @@ __global__ __launch_bounds__(kThreads) void k_PT_gather(Maps a, const float* __r
         const int jz = static_cast<int>(j % a.n[2]);
         const int jy = static_cast<int>((j / a.n[2]) % a.n[1]);
         const int jx = static_cast<int>(j / (static_cast<int64_t>(a.n[2]) * a.n[1]));
-        const int lx = omega_lo(a, 0, jx), ly = omega_lo(a, 1, jy), lz = omega_lo(a, 2, jz);
+        const Range rx = omega_range(a, 0, jx), ry = omega_range(a, 1, jy),
+                    rz = omega_range(a, 2, jz);
         float acc[3] = {0.0f, 0.0f, 0.0f};
-        for (int ix = lx; ix < a.m[0] && a.j0[0][ix] <= jx; ++ix) {
+        for (int ix = rx.lo; ix < rx.hi; ++ix) {
             const float wx = omega(a, 0, ix, jx);
-            for (int iy = ly; iy < a.m[1] && a.j0[1][iy] <= jy; ++iy) {
+            for (int iy = ry.lo; iy < ry.hi; ++iy) {
                 const float wxy = wx * omega(a, 1, iy, jy);
-                for (int iz = lz; iz < a.m[2] && a.j0[2][iz] <= jz; ++iz) {
+                for (int iz = rz.lo; iz < rz.hi; ++iz) {
                     const float w = wxy * omega(a, 2, iz, jz);
                     const int64_t i = (static_cast<int64_t>(ix) * a.m[1] + iy) * a.m[2] + iz;
                     acc[0] = fmaf(w, z[i], acc[0]);
@@ -133,41 +132,49 @@ __global__ __launch_bounds__(kThreads) void k_PT_atomic(Maps a, const float* __r
     }
 }
 
-// One colour phase of the red-black scheme: thread (gx, gy) with cell
-// parities (px, py) scatters every image point whose x cell is gx and y cell
-// is gy, serially, into nodes {gx, gx+1} x {gy, gy+1} x all z.
+// One phase of the red-black scheme: every x cell gx of parity px, one
+// thread per (cell, y node, z node).  The thread sums the cell's slices (the
+// image points whose lower x node is gx) over its y and z index sets, each
+// slice weighted for node plane gx and for gx + 1, and adds both sums to the
+// output; no other thread of the phase touches those nodes.
 __global__ __launch_bounds__(kThreads) void k_PT_redblack(Maps a, const float* __restrict__ z,
-                                                          float* __restrict__ out, int px,
-                                                          int py, int cells_x, int cells_y) {
+                                                          float* __restrict__ out, int px) {
     const int64_t N = static_cast<int64_t>(a.m[0]) * a.m[1] * a.m[2];
     const int64_t Ny = static_cast<int64_t>(a.n[0]) * a.n[1] * a.n[2];
-    const int hx = (cells_x - px + 1) / 2, hy = (cells_y - py + 1) / 2;
-    const int t = blockIdx.x * kThreads + threadIdx.x;
-    if (t >= hx * hy) return;
-    const int gx = 2 * (t / hy) + px, gy = 2 * (t % hy) + py;
-    const int lx = omega_lo(a, 0, gx), ly = omega_lo(a, 1, gy);
-    for (int ix = lx; ix < a.m[0] && a.j0[0][ix] <= gx; ++ix) {
-        if (a.j0[0][ix] != gx) continue;
-        for (int iy = ly; iy < a.m[1] && a.j0[1][iy] <= gy; ++iy) {
-            if (a.j0[1][iy] != gy) continue;
-            const float wx[2] = {a.w0[0][ix], a.w1[0][ix]};
-            const float wy[2] = {a.w0[1][iy], a.w1[1][iy]};
-            for (int iz = 0; iz < a.m[2]; ++iz) {
-                const int jz = a.j0[2][iz];
-                const float wz[2] = {a.w0[2][iz], a.w1[2][iz]};
-                const int64_t i = (static_cast<int64_t>(ix) * a.m[1] + iy) * a.m[2] + iz;
-                for (int p = 0; p < 2; ++p)
-                    for (int q = 0; q < 2; ++q)
-                        for (int r = 0; r < 2; ++r) {
-                            const float w = wx[p] * wy[q] * wz[r];
-                            const int64_t j =
-                                ((gx + p) * static_cast<int64_t>(a.n[1]) + gy + q) * a.n[2] +
-                                jz + r;
-                            out[j] += w * z[i];
-                            out[Ny + j] += w * z[N + i];
-                            out[2 * Ny + j] += w * z[2 * N + i];
-                        }
+    const int cells = (a.n[0] - 1 - px + 1) / 2;  // x cells of this parity
+    const int64_t nyz = static_cast<int64_t>(a.n[1]) * a.n[2];
+    for (int64_t t = blockIdx.x * static_cast<int64_t>(kThreads) + threadIdx.x;
+         t < cells * nyz; t += static_cast<int64_t>(gridDim.x) * kThreads) {
+        const int gx = 2 * static_cast<int>(t / nyz) + px;
+        const int jy = static_cast<int>((t / a.n[2]) % a.n[1]);
+        const int jz = static_cast<int>(t % a.n[2]);
+        // the cell's slices: image points with lower x node gx
+        const int ilo = first_at_least(gx, a.m[0], a.n[0]);
+        const int ihi = first_at_least(gx + 1, a.m[0], a.n[0]);
+        const Range ry = omega_range(a, 1, jy), rz = omega_range(a, 2, jz);
+        float lo[3] = {0.0f, 0.0f, 0.0f}, hi[3] = {0.0f, 0.0f, 0.0f};
+        for (int ix = ilo; ix < ihi; ++ix) {
+            const float wx0 = a.w0[0][ix], wx1 = a.w1[0][ix];
+            float s[3] = {0.0f, 0.0f, 0.0f};
+            for (int iy = ry.lo; iy < ry.hi; ++iy) {
+                const float wy = omega(a, 1, iy, jy);
+                for (int iz = rz.lo; iz < rz.hi; ++iz) {
+                    const float w = wy * omega(a, 2, iz, jz);
+                    const int64_t i = (static_cast<int64_t>(ix) * a.m[1] + iy) * a.m[2] + iz;
+                    s[0] = fmaf(w, z[i], s[0]);
+                    s[1] = fmaf(w, z[N + i], s[1]);
+                    s[2] = fmaf(w, z[2 * N + i], s[2]);
+                }
             }
+            for (int c = 0; c < 3; ++c) {
+                lo[c] = fmaf(wx0, s[c], lo[c]);
+                hi[c] = fmaf(wx1, s[c], hi[c]);
+            }
+        }
+        const int64_t j = (static_cast<int64_t>(gx) * a.n[1] + jy) * a.n[2] + jz;
+        for (int c = 0; c < 3; ++c) {
+            out[c * Ny + j] += lo[c];
+            out[c * Ny + j + nyz] += hi[c];
         }
     }
 }
@@ -213,15 +220,14 @@ void launch_apply_PT(const int32_t* const j0[3], const float* const w0[3],
     } else if (scheme == 1) {
         hipLaunchKernelGGL(k_PT_atomic, dim3(blocks_for(N)), dim3(kThreads), 0, s, a, z, out);
     } else {
-        // cells along x and y: node indices 0 .. n-2 (a cell joins nodes j, j+1)
-        const int cx = n[0] - 1, cy = n[1] - 1;
-        for (int px = 0; px < 2; ++px)
-            for (int py = 0; py < 2; ++py) {
-                const int hx = (cx - px + 1) / 2, hy = (cy - py + 1) / 2;
-                const int threads = hx * hy;
-                hipLaunchKernelGGL(k_PT_redblack, dim3((threads + kThreads - 1) / kThreads),
-                                   dim3(kThreads), 0, s, a, z, out, px, py, cx, cy);
-            }
+        // odd x cells, then even ones (the second phase starts after the
+        // first on the stream: they share node planes)
+        const int64_t nyz = static_cast<int64_t>(n[1]) * n[2];
+        for (int px = 1; px >= 0; --px) {
+            const int64_t cells = (n[0] - 1 - px + 1) / 2;
+            hipLaunchKernelGGL(k_PT_redblack, dim3(blocks_for(cells * nyz)), dim3(kThreads), 0, s,
+                               a, z, out, px);
+        }
     }
 }
 
