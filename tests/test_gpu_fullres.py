@@ -6,9 +6,10 @@ At this size the oracle cannot evaluate the finest level in a test's time, so:
 index maps bit-exact on every level; pyramid levels bit-exact on sampled
 blocks (the oracle's box means over the blocks' level-0 regions); the full
 oracle evaluation at the 128 x 128 x 384 level (J, grad J); at the finest
-level the properties that hold at any size (finite J and gradient, 0 <= D <=
-hbar N / 2, S = 0 and grad S = 0 at the identity); and a full registration
-whose per-level outcome is valid.
+level grad J element-wise at the nodes of three boxes against the oracle on
+image cuts around them, the properties that hold at any size (finite J and
+gradient, 0 <= D <= hbar N / 2, S = 0 and grad S = 0 at the identity); and a
+full registration whose per-level outcome is valid.
 """
 
 import sys
@@ -89,6 +90,54 @@ def test_fullres_eval_parity_at_128x128x384(fullres):
         err = np.linalg.norm(g - go) / np.linalg.norm(go)
         _say(f"[fullres] level {lev} {m} amp={amp}: J {J} oracle {Jo} grad rel-L2 {err:.2e}")
         assert abs(J - Jo) <= 1e-5 * abs(Jo)
+        assert err <= 1e-4
+
+
+def test_fullres_finest_gradient_on_sub_boxes(fullres):
+    """grad J at the finest level (512 x 512 x 1536) against the oracle at
+    the nodes of three boxes of 24^3 nodes: in the middle, at the low faces
+    and at the high faces (the last planes, where the byte offsets into the
+    images are largest).  A node's gradient depends only on the image points
+    of its index sets (Eq. 3), their difference stencils (two points), the
+    template where those points are warped to (at most the displacement
+    away) and the nodes two cells around it (curvature).  The oracle
+    evaluates the images cut out with a margin of 12 points (6 node cells)
+    around a box, clipped at the domain's faces, at y shifted to the cut's
+    origin: at the box's nodes it sees exactly the full problem."""
+    ngf, ctx, pr, _, _ = fullres
+    import torch
+    li = ctx.level_info(0)
+    my = li.my
+    # y = identity + separable sines of peak 2.2 voxels (formed on the device)
+    j = [torch.arange(n, dtype=torch.float64, device="cuda") / (n - 1) for n in my]
+    w = (torch.sin(2 * np.pi * j[0])[:, None, None] * torch.sin(np.pi * j[1])[None, :, None]
+         * torch.cos(np.pi * j[2])[None, None, :])
+    y = ctx.identity(0).double()
+    y[0] += 2.0 * w
+    y[1] -= 2.0 * w
+    y[2] += 1.0 * w
+    del w
+    y = y.float().contiguous()
+    J, g, _ = ctx.eval_J_grad(0, y)
+    assert np.isfinite(J)
+    B, MARGIN = 24, 6  # box and margin in nodes (the margin is 12 image points)
+    for n0 in ((120, 100, 380), (0, 0, 0), (my[0] - B, my[1] - B, my[2] - B)):
+        lo = [max(n0[d] - MARGIN, 0) for d in range(3)]
+        hi = [min(n0[d] + B + MARGIN, my[d] - 1) for d in range(3)]  # last node of the cut
+        cut = tuple(slice(2 * lo[d], 2 * hi[d]) for d in range(3))   # image points
+        nodes = tuple(slice(lo[d], hi[d] + 1) for d in range(3))
+        ys = y[(slice(None),) + nodes].double().cpu().numpy()
+        for d in range(3):
+            ys[d] -= 2.0 * lo[d]  # physical origin of the cut (h = 1)
+        prob = O.Problem(pr.R[cut], pr.T[cut], (1.0, 1.0, 1.0), ys.shape[1:], 0.1, 10.0, 10.0)
+        _, go, _ = O.eval_J_grad(prob, ys)
+        box = tuple(slice(n0[d], n0[d] + B) for d in range(3))
+        rel = tuple(slice(n0[d] - lo[d], n0[d] - lo[d] + B) for d in range(3))
+        gg = g[(slice(None),) + box].double().cpu().numpy()
+        go = go[(slice(None),) + rel]
+        err = np.linalg.norm(gg - go) / np.linalg.norm(go)
+        _say(f"[fullres] level 0 box at nodes {n0}: grad rel-L2 {err:.2e} "
+             f"(max abs {np.abs(gg - go).max():.2e} of {np.abs(go).max():.2e})")
         assert err <= 1e-4
 
 

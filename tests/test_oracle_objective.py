@@ -89,3 +89,47 @@ def test_objective_parts_and_alpha():
     assert abs(J1 - (D1 + 2.5 * S1)) < 1e-12 * J1
     _, gS = O.curvature(y - p.identity(), p.hy)
     assert np.max(np.abs(g1 - (g0 + 2.5 * gS))) < 1e-12 * np.abs(g1).max()
+
+
+def _cut_gradient(R, T, y, n0, B, margin):
+    """grad J of the objective on the images cut out around a box of B^3
+    nodes at n0 (a margin of ``margin`` node cells, clipped at the faces), at
+    y shifted to the cut's origin; returned at the box's nodes."""
+    my = y.shape[1:]
+    lo = [max(n0[d] - margin, 0) for d in range(3)]
+    hi = [min(n0[d] + B + margin, my[d] - 1) for d in range(3)]
+    cut = tuple(slice(2 * lo[d], 2 * hi[d]) for d in range(3))
+    ys = y[(slice(None),) + tuple(slice(lo[d], hi[d] + 1) for d in range(3))].copy()
+    for d in range(3):
+        ys[d] -= 2.0 * lo[d]
+    p = O.Problem(R[cut], T[cut], (1.0, 1.0, 1.0), ys.shape[1:], 0.1, 10.0, 10.0)
+    _, g, _ = O.eval_J_grad(p, ys)
+    return g[(slice(None),) + tuple(slice(n0[d] - lo[d], n0[d] - lo[d] + B) for d in range(3))]
+
+
+def test_gradient_is_local_to_a_cut():
+    """A node's gradient depends only on the image points of its index sets
+    (Eq. 3), their difference stencils, the template where they are warped
+    to and the nodes two cells around it.  So the objective on the images
+    cut out with a margin of 6 node cells around a box (clipped at the
+    faces), at y shifted to the cut's origin, gives the full problem's
+    gradient at the box's nodes exactly; with a margin of one cell it does
+    not (the cut's replicated ends and the clamped warp reach the box).
+    This is what lets the full-resolution GPU test compare its finest level
+    with the oracle on cuts."""
+    m = (48, 40, 64)
+    pr = synth.ct_phantom_pair(m, seed_R=5, seed_u=6)
+    my = tuple(v // 2 + 1 for v in m)
+    p = O.Problem(pr.R, pr.T, (1.0, 1.0, 1.0), my, 0.1, 10.0, 10.0)
+    j = [np.arange(n, dtype=np.float64) / (n - 1) for n in my]
+    w = (np.sin(2 * np.pi * j[0])[:, None, None] * np.sin(np.pi * j[1])[None, :, None]
+         * np.cos(np.pi * j[2])[None, None, :])
+    y = (p.identity() + np.stack([2 * w, -2 * w, w])).astype(np.float32).astype(np.float64)
+    _, g, _ = O.eval_J_grad(p, y)
+    B = 6
+    for n0 in ((9, 7, 12), (0, 0, 0), (my[0] - B, my[1] - B, my[2] - B)):
+        box = (slice(None),) + tuple(slice(n0[d], n0[d] + B) for d in range(3))
+        assert np.array_equal(_cut_gradient(pr.R, pr.T, y, n0, B, 6), g[box])
+    n0 = (9, 7, 12)
+    box = (slice(None),) + tuple(slice(n0[d], n0[d] + B) for d in range(3))
+    assert not np.allclose(_cut_gradient(pr.R, pr.T, y, n0, B, 1), g[box], rtol=1e-6)
