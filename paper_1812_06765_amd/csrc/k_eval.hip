@@ -289,22 +289,13 @@ __device__ __forceinline__ void image_body(const ImagePassArgs& a, int block) {
         const float ab = fmaf(gTx, gRx, fmaf(gTy, gRy, fmaf(gTz, gRz, tau * rho)));
         const float iaa = __builtin_amdgcn_rcpf(aa), ibb = __builtin_amdgcn_rcpf(bb);
         if (hx + hy + hz == 0 && gx < mx && gy < my && gz < mz) {
-            // 1 - r^2 by Lagrange's identity on a = (grad T, tau), b = (grad R, rho):
-            // |a|^2 |b|^2 - <a,b>^2 = sum_{p<q} (a_p b_q - a_q b_p)^2.  Each term is the
-            // difference of two separately rounded products (never fused), so it is
-            // exactly 0 when a = b.
-            float q1, q2, q3, q4, q5, q6;
+            // 1 - r^2 = (aa bb - ab^2) / (aa bb) with a = (grad T, tau), b = (grad R,
+            // rho), products unfused: exactly 0 when a = b (aa = bb = ab bit for bit)
+            float lag;
             {
 #pragma clang fp contract(off)
-                q1 = gTx * gRy - gTy * gRx;
-                q2 = gTx * gRz - gTz * gRx;
-                q3 = gTy * gRz - gTz * gRy;
-                q4 = gTx * rho - tau * gRx;
-                q5 = gTy * rho - tau * gRy;
-                q6 = gTz * rho - tau * gRz;
+                lag = aa * bb - ab * ab;
             }
-            const float lag = fmaf(q1, q1, fmaf(q2, q2, fmaf(q3, q3,
-                                  fmaf(q4, q4, fmaf(q5, q5, q6 * q6)))));
             dsum += static_cast<double>(lag * iaa * ibb);
         }
         if (GRAD) {

@@ -362,18 +362,13 @@ __device__ __forceinline__ void march_body(const ImagePassArgs& a, int CX, int b
                 const float ab = fmaf(gTx, gRx, fmaf(gTy, gRy, fmaf(gTz, gRz, tau * rho)));
                 const float iaa = __builtin_amdgcn_rcpf(aa), ibb = __builtin_amdgcn_rcpf(bb);
                 if (inner && dtile && gy < my && gz < mz) {
-                    float q1, q2, q3, q4, q5, q6;
+                    // 1 - r^2 = (aa bb - ab^2) / (aa bb) with a = (grad T, tau), b = (grad R,
+                    // rho), products unfused: exactly 0 when a = b (aa = bb = ab bit for bit)
+                    float lag;
                     {
 #pragma clang fp contract(off)
-                        q1 = gTx * gRy - gTy * gRx;
-                        q2 = gTx * gRz - gTz * gRx;
-                        q3 = gTy * gRz - gTz * gRy;
-                        q4 = gTx * rho - tau * gRx;
-                        q5 = gTy * rho - tau * gRy;
-                        q6 = gTz * rho - tau * gRz;
+                        lag = aa * bb - ab * ab;
                     }
-                    const float lag = fmaf(q1, q1, fmaf(q2, q2, fmaf(q3, q3,
-                                          fmaf(q4, q4, fmaf(q5, q5, q6 * q6)))));
                     dsum += static_cast<double>(lag * iaa * ibb);
                 }
                 if (GRAD) {

@@ -435,8 +435,8 @@ __device__ __forceinline__ void gen_body(const ImagePassArgs& a, int CX, int blo
                 const int gy = gyof(kk), gz = gzof(kk);
                 const int p = (gy - y0 + 2) * GH + (gz - z0 + 2);  // the clamped voxel
                 const float4 rn = bld4(rR, static_cast<uint32_t>(gy * mz + gz) * 16u, 0u);
-                const float gRx = rn.x, gRy = rn.y, gRz = rn.z;
-                const float ibb = __builtin_amdgcn_rcpf(rn.w);
+                const float gRx = rn.x, gRy = rn.y, gRz = rn.z, bb = rn.w;
+                const float ibb = __builtin_amdgcn_rcpf(bb);
                 const float gTx = (tyv[kk][2] - tyv[kk][0]) * a.i2hx;
                 const float gTy = (T0[p + GH] - T0[p - GH]) * a.i2hy;
                 const float gTz = (T0[p + 1] - T0[p - 1]) * a.i2hz;
@@ -447,20 +447,13 @@ __device__ __forceinline__ void gen_body(const ImagePassArgs& a, int CX, int blo
                 // the mirrored ghost of the adjoint stencil's end rows
                 const int uy = y0 - 2 + pby[kk], uz = z0 - 2 + pbz[kk];
                 if (kk < KP && dplane && uy < my && uz < mz) {
-                    // 1 - r^2 by Lagrange's identity on a = (grad T, tau),
-                    // b = (grad R, rho), unfused: exactly 0 when a = b
-                    float q1, q2, q3, q4, q5, q6;
+                    // 1 - r^2 = (aa bb - ab^2) / (aa bb) with a = (grad T, tau), b = (grad R,
+                    // rho), products unfused: exactly 0 when a = b (aa = bb = ab bit for bit)
+                    float lag;
                     {
 #pragma clang fp contract(off)
-                        q1 = gTx * gRy - gTy * gRx;
-                        q2 = gTx * gRz - gTz * gRx;
-                        q3 = gTy * gRz - gTz * gRy;
-                        q4 = gTx * rho - tau * gRx;
-                        q5 = gTy * rho - tau * gRy;
-                        q6 = gTz * rho - tau * gRz;
+                        lag = aa * bb - ab * ab;
                     }
-                    const float lag = fmaf(q1, q1, fmaf(q2, q2, fmaf(q3, q3,
-                                          fmaf(q4, q4, fmaf(q5, q5, q6 * q6)))));
                     dsum += static_cast<double>(lag * iaa * ibb);
                 }
                 if (GRAD) {

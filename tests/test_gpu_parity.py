@@ -209,7 +209,7 @@ def test_identical_images_give_zero(gpu_lib, variant):
     ctx.build_pyramid(_t(pr.R), _t(pr.R))
     ctx.set_kernel(variant)
     J, g, (D, S) = ctx.eval_J_grad(0, ctx.identity(0))
-    # Lagrange's form of 1 - r^2 is exactly zero for identical gradients
+    # 1 - r^2 with unfused products is exactly zero for identical gradients
     assert J == 0.0 and D == 0.0 and S == 0.0
     assert float(g.abs().max()) == 0.0
 
