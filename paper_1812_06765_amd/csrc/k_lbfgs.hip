@@ -28,7 +28,7 @@ __global__ void k_lb_init(LbState* st, int mem, double hmin, const double* jds, 
 __global__ void k_lb_solve(LbState* st, double* jds) {
     __shared__ SolveLds w;
     lb_stage(st, w);
-    if (threadIdx.x == 0) lb_solve_one(st, jds, w);
+    if (threadIdx.x < 64) lb_solve_wave(st, jds, w);
 }
 
 __global__ __launch_bounds__(kThreads) void k_lb_combine(const LbState* st,

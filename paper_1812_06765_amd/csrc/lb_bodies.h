@@ -80,64 +80,83 @@ __device__ inline void lb_stage(const LbState* st, SolveLds& w) {
     __syncthreads();
 }
 
-// One lane.  The g^T g entry of G refers to the current gradient: it is set
-// in the staged copy and in the state.
-__device__ inline void lb_solve_one(LbState* st, double* jds, SolveLds& w) {
-    double* G = w.G;
-    double* q = w.q;
-    G[kBasisG * kBasis + kBasisG] = st->gnorm2;
-    st->G[kBasisG * kBasis + kBasisG] = st->gnorm2;
-    double flags = 0.0;
-    double gtd = 0.0;
-    for (int i = 0; i < kBasis; ++i) q[i] = 0.0;
-    if (!(st->gmax > 0.0)) {
-        st->flags = 2.0;
-        st->gtd = 0.0;
-        jds[5] = 0.0;
-        for (int i = 0; i < kBasis; ++i) st->coef[i] = 0.0;
+// Sum over the 64 lanes of a wave by a butterfly: every lane ends with the
+// same value (each step adds a + b and b + a, which round alike).
+__device__ inline double lb_wave_allsum(double v) {
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// The recursion on one wave: lane l < kBasis holds the coefficient q_l of
+// basis vector l, each inner product q^T G e_i is a wave sum, and the scalars
+// of the recursion (every lane computes them alike) stay in registers; lane k
+// keeps alpha_k for the second loop.  The g^T g entry of G refers to the
+// current gradient: it is read as such here and set in the state.  Called by
+// every lane of the block's first wave.
+__device__ inline void lb_solve_wave(LbState* st, double* jds, SolveLds& w) {
+    const int l = threadIdx.x & 63;
+    const double* G = w.G;
+    const double gn2 = st->gnorm2;
+    auto Gat = [&](int i, int j) {
+        return (i == kBasisG && j == kBasisG) ? gn2 : G[i * kBasis + j];
+    };
+    auto row_dot = [&](double q, int i) {  // sum_l q_l G(i, l)
+        return lb_wave_allsum(l < kBasis ? q * Gat(i, l) : 0.0);
+    };
+    const double gmax = st->gmax, hmin = st->hmin;
+    int count = st->count;
+    if (l == 0) st->G[kBasisG * kBasis + kBasisG] = gn2;
+    if (!(gmax > 0.0)) {
+        if (l == 0) {
+            st->flags = 2.0;
+            st->gtd = 0.0;
+            jds[5] = 0.0;
+        }
+        if (l < kBasis) st->coef[l] = 0.0;
         return;
     }
-    int count = st->count;
+    double flags = 0.0, gtd = 0.0, q = 0.0;
     if (count > 0) {
-        q[kBasisG] = 1.0;
+        q = l == kBasisG ? 1.0 : 0.0;
+        double al = 0.0;
         for (int k = count - 1; k >= 0; --k) {
-            const int si = w.order[k], ti = kSlots + w.order[k];
-            double sq = 0.0;
-            for (int l = 0; l < kBasis; ++l) sq += q[l] * G[si * kBasis + l];
-            w.al[k] = sq / G[si * kBasis + ti];
-            q[ti] -= w.al[k];
+            const int si = w.order[k], ti = kSlots + si;
+            const double a = row_dot(q, si) / Gat(si, ti);
+            if (l == k) al = a;
+            if (l == ti) q -= a;
         }
-        const int sn = w.order[count - 1], tn = kSlots + w.order[count - 1];
-        const double gamma = G[sn * kBasis + tn] / G[tn * kBasis + tn];
-        for (int i = 0; i < kBasis; ++i) q[i] *= gamma;
+        const int sn = w.order[count - 1], tn = kSlots + sn;
+        q *= Gat(sn, tn) / Gat(tn, tn);
         for (int k = 0; k < count; ++k) {
-            const int si = w.order[k], ti = kSlots + w.order[k];
-            double tr = 0.0;
-            for (int l = 0; l < kBasis; ++l) tr += q[l] * G[ti * kBasis + l];
-            const double b = tr / G[si * kBasis + ti];
-            q[si] += w.al[k] - b;
+            const int si = w.order[k], ti = kSlots + si;
+            const double b = row_dot(q, ti) / Gat(si, ti);
+            const double a = __shfl(al, k, 64);
+            if (l == si) q += a - b;
         }
-        for (int i = 0; i < kBasis; ++i) q[i] = -q[i];  // the coefficients of d
-        for (int l = 0; l < kBasis; ++l) gtd += q[l] * G[kBasisG * kBasis + l];
+        q = -q;  // the coefficients of d
+        gtd = row_dot(q, kBasisG);
         if (!(gtd < 0.0)) {
             count = 0;
             flags = 1.0;
         }
     }
     if (count == 0) {
-        st->count = 0;
-        for (int i = 0; i < kSlots; ++i) st->order[i] = -1;
-        st->free_slot = 0;
-        const double scale = st->hmin / st->gmax;
-        for (int i = 0; i < kBasis; ++i) q[i] = 0.0;
-        q[kBasisG] = -scale;
-        gtd = -scale * st->gnorm2;
+        if (l == 0) {
+            st->count = 0;
+            st->free_slot = 0;
+        }
+        if (l < kSlots) st->order[l] = -1;
+        const double scale = hmin / gmax;
+        q = l == kBasisG ? -scale : 0.0;
+        gtd = -scale * gn2;
     }
-    for (int i = 0; i < kBasis; ++i) st->coef[i] = q[i];
-    st->gtd = gtd;
-    st->flags = flags;
-    st->count_d = static_cast<double>(st->count);
-    jds[5] = gtd;  // read by the host with the trial's J in one copy
+    if (l < kBasis) st->coef[l] = q;
+    if (l == 0) {
+        st->gtd = gtd;
+        st->flags = flags;
+        st->count_d = static_cast<double>(count);
+        jds[5] = gtd;  // read by the host with the trial's J in one copy
+    }
 }
 
 // d = sum_l coef_l b_l over the active basis; yt = y + d.  Four elements per
@@ -492,25 +511,31 @@ __device__ __forceinline__ void lb_gram_one(LbState* st, const double* dots, con
 __device__ __forceinline__ void lb_plan_body(LbState* st, double* jds) {
     __shared__ SolveLds w;
     lb_stage(st, w);
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x >= 64) return;  // the first wave decides; lane 0 writes
     LbCtl& c = st->ctl;
-    if (c.phase == kPhDone) {
-        c.op = kOpNone;
-    } else if (c.phase == kPhNeedDir) {
-        if (c.iters >= c.max_iter) {
-            lb_finish(c, NGF_INFO_MAX_ITER);
-        } else if (!isfinite(c.gmax)) {
-            lb_finish(c, NGF_INFO_NONFINITE);
-        } else if (c.gmax == 0.0) {
-            lb_finish(c, NGF_INFO_CONVERGED);
+    const bool lead = threadIdx.x == 0;
+    const int phase = c.phase;
+    if (phase == kPhDone) {
+        if (lead) c.op = kOpNone;
+    } else if (phase == kPhNeedDir) {
+        const int iters = c.iters, max_iter = c.max_iter;
+        const double gmax = c.gmax;
+        if (iters >= max_iter) {
+            if (lead) lb_finish(c, NGF_INFO_MAX_ITER);
+        } else if (!isfinite(gmax)) {
+            if (lead) lb_finish(c, NGF_INFO_NONFINITE);
+        } else if (gmax == 0.0) {
+            if (lead) lb_finish(c, NGF_INFO_CONVERGED);
         } else {
-            lb_solve_one(st, jds, w);
-            c.t = 1.0;
-            c.halvings = 0;
-            c.phase = kPhTrial;
-            c.op = kOpCombine;
+            lb_solve_wave(st, jds, w);
+            if (lead) {
+                c.t = 1.0;
+                c.halvings = 0;
+                c.phase = kPhTrial;
+                c.op = kOpCombine;
+            }
         }
-    } else {
+    } else if (lead) {
         c.op = kOpAxpy;  // kPhTrial after a rejection: same d, halved t
     }
 }
