@@ -36,6 +36,26 @@
  * Errors.  No call throws or aborts across the ABI.  Every call returns an
  *   ngf_status; on failure ngf_last_error() describes the cause and the
  *   outputs are left unspecified.  One context per host thread.
+ *
+ * The method's operations and the calls that carry them
+ * ----------------------------------------------------
+ *   register(R, T, alpha, levels) -> y   (Sec. 2.1: coarse-to-fine L-BFGS)
+ *       ngf_create(params, stream, &ctx) with params.alpha and params.levels,
+ *       then ngf_register(ctx, R, T, grid, y, host_ptrs, report).  alpha and
+ *       the level count are context parameters (ngf_create, ngf_set_params)
+ *       rather than per-call arguments because the pyramid, the index maps,
+ *       the partial-sum buffers and the L-BFGS history are sized from them
+ *       once, so that no evaluation or iteration allocates.
+ *   build_pyramid(R, T)                  (Sec. 2.2)  ngf_build_pyramid
+ *   eval_J_grad(level, y) -> J, grad     (Eq. 1-3)   ngf_eval_J_grad
+ *   eval_J_grad_T(level, y) -> J, grad_y, grad_T     ngf_eval_J_grad_T
+ *   lbfgs_step(level, y) -> y, grad, J   (Sec. 2.1)  ngf_lbfgs_reset(level,
+ *       y0) once, then ngf_lbfgs_step per iteration and ngf_lbfgs_get for the
+ *       iterate: the iterate, its gradient and the history stay in the
+ *       context between steps instead of crossing the ABI every iteration.
+ *   prolongate(level, y_c) -> y_f        (Sec. 2.1)  ngf_prolongate
+ *   the same over many pairs             ngf_batch_create, ngf_batch_register,
+ *       ngf_batch_build + ngf_batch_eval.
  */
 #ifndef NGFREG_H
 #define NGFREG_H
