@@ -136,11 +136,27 @@ class BSplineField:
         out = np.einsum("cijk,xi,yj,zk->cxyz", self.coef, bx, by, bz, optimize=True)
         return np.ascontiguousarray(self.scale * out)
 
-    def __call__(self, p: np.ndarray) -> np.ndarray:
+    def __call__(self, p: np.ndarray, chunk: int = 1 << 16) -> np.ndarray:
+        """Field at arbitrary points p (3, ...).  A point sees the 4 x 4 x 4
+        control points whose basis functions cover it; outside the control
+        lattice the missing ones contribute nothing."""
         shp = p.shape[1:]
         flat = p.reshape(3, -1)
-        bx, by, bz = (self._basis(d, flat[d]) for d in range(3))
-        out = np.einsum("cijk,ni,nj,nk->cn", self.coef, bx, by, bz, optimize=True)
+        out = np.empty((3, flat.shape[1]))
+        for a in range(0, flat.shape[1], chunk):
+            q = flat[:, a:a + chunk]
+            ks, ws = [], []
+            for d in range(3):
+                t = q[d] / self.spacing
+                k = np.floor(t).astype(np.int64)[:, None] + np.arange(4)  # (n, 4)
+                w = _cubic_bspline(t[:, None] - (k - 1.0))  # control point k sits at (k-1) s
+                ok = (k >= 0) & (k < self.ncp[d])
+                ks.append(np.clip(k, 0, self.ncp[d] - 1))
+                ws.append(np.where(ok, w, 0.0))
+            c = self.coef[:, ks[0][:, :, None, None], ks[1][:, None, :, None],
+                          ks[2][:, None, None, :]]  # (3, n, 4, 4, 4)
+            out[:, a:a + chunk] = np.einsum("cnijk,ni,nj,nk->cn", c, ws[0], ws[1], ws[2],
+                                            optimize=True)
         return (self.scale * out).reshape((3,) + shp)
 
 
