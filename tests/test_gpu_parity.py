@@ -290,6 +290,26 @@ def test_register_blob32_against_oracle(gpu_lib):
     assert eg < 0.6 * e0 and abs(eg - eo) < 0.05 * e0
 
 
+def test_register_early_stop_against_oracle(gpu_lib):
+    """The early stop of Sec. 2.1's L-BFGS (a decrease of at most tol (1 + |J|)
+    ends the level): the GPU level ends with the converged outcome at the
+    same iteration as the oracle's run, with J close.  tol = 0.009 lies
+    between the oracle's relative decreases of iterations 12 and 13 on this
+    pair (0.012 and 0.0069), away from both."""
+    ngf = gpu_lib
+    pr = synth.blob_phantom_pair((32, 32, 32), seed_R=1, seed_u=2, max_disp=2.0)
+    ctx = _ctx(ngf, alpha=0.1, tau=0.1, rho=0.1, levels=1, max_iter=40, lbfgs_mem=5,
+               tol_J=0.009, early_stop=True)
+    _, rep = ctx.register(_t(pr.R), _t(pr.T))
+    _, repo = O.register(pr.R, pr.T, (1.0, 1.0, 1.0), levels=1, alpha=0.1, tau=0.1, rho=0.1,
+                         max_iter=40, mem=5, tol=0.009, early_stop=True)
+    _, it, _, J, info = repo[0]
+    _say(f"[early stop] gpu {rep[0]} oracle {repo[0]}")
+    assert info == O.INFO["CONVERGED"] and it == 13
+    assert rep[0]["info"] == ngf.INFO_CONVERGED and rep[0]["iters"] == it
+    assert abs(rep[0]["J"] - J) <= 2e-3 * abs(J)
+
+
 def test_register_multilevel_and_host_path(gpu_lib):
     """A registration from host arrays equals the one from device arrays bit
     for bit.  Both contexts take the image-pass variants of the size rule:
