@@ -38,7 +38,10 @@ __global__ __launch_bounds__(kThreads) void k_lb_combine(const LbState* st,
                                                          const float* __restrict__ g,
                                                          float* __restrict__ d,
                                                          float* __restrict__ yt) {
-    lb_combine_body(st, hist, ld, n, y, g, d, yt, blockIdx.x, gridDim.x);
+    if (lb_streams(n))
+        lb_combine_body<true>(st, hist, ld, n, y, g, d, yt, blockIdx.x, gridDim.x);
+    else
+        lb_combine_body<false>(st, hist, ld, n, y, g, d, yt, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(kThreads) void k_lb_axpy(const float* __restrict__ y,
@@ -56,8 +59,14 @@ __global__ __launch_bounds__(kThreads) void k_lb_update_dots(const LbState* st,
                                                              const float* __restrict__ g,
                                                              const float* __restrict__ gt,
                                                              double* __restrict__ dotpart) {
-    lb_update_dots_body<false, CMAX>(st, hist, ld, n, const_cast<float*>(y), yt,
-                               const_cast<float*>(g), gt, dotpart, blockIdx.x, gridDim.x);
+    if (lb_streams(n))
+        lb_update_dots_body<false, CMAX, true>(st, hist, ld, n, const_cast<float*>(y), yt,
+                                               const_cast<float*>(g), gt, dotpart, blockIdx.x,
+                                               gridDim.x);
+    else
+        lb_update_dots_body<false, CMAX, false>(st, hist, ld, n, const_cast<float*>(y), yt,
+                                                const_cast<float*>(g), gt, dotpart, blockIdx.x,
+                                                gridDim.x);
 }
 
 __global__ __launch_bounds__(kGramThreads) void k_lb_gram_update(LbState* st,
@@ -75,7 +84,7 @@ __global__ __launch_bounds__(kThreads) void k_lb_vec(const LbState* st,
                                                      const float* __restrict__ g,
                                                      float* __restrict__ d,
                                                      float* __restrict__ yt) {
-    lb_vec_body(st, hist, ld, n, y, g, d, yt, blockIdx.x, gridDim.x);
+    lb_vec_body(st, hist, ld, n, y, g, d, yt, blockIdx.x, gridDim.x, lb_streams(n));
 }
 
 template <int CMAX>
@@ -87,8 +96,12 @@ __global__ __launch_bounds__(kThreads) void k_lb_accept_dots(const LbState* st,
                                                              const float* __restrict__ gt,
                                                              double* __restrict__ dotpart) {
     if (st->ctl.phase != kPhAccepted) return;
-    lb_update_dots_body<true, CMAX>(st, hist, ld, n, y, yt, g, gt, dotpart, blockIdx.x,
-                                    gridDim.x);
+    if (lb_streams(n))
+        lb_update_dots_body<true, CMAX, true>(st, hist, ld, n, y, yt, g, gt, dotpart,
+                                              blockIdx.x, gridDim.x);
+    else
+        lb_update_dots_body<true, CMAX, false>(st, hist, ld, n, y, yt, g, gt, dotpart,
+                                               blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(kGramThreads) void k_lb_gram_plan(LbState* st,
@@ -115,7 +128,8 @@ __global__ __launch_bounds__(kThreads) void k_lb_vec_batch(const LbVecArgs* args
     const BlockRef e = blk[blockIdx.x];
     if (e.pair < 0) return;
     const LbVecArgs& a = args[e.pair];
-    lb_vec_body(a.st, a.hist, a.ld, a.n, a.y, a.g, a.d, a.yt, e.block, a.nblocks);
+    lb_vec_body(a.st, a.hist, a.ld, a.n, a.y, a.g, a.d, a.yt, e.block, a.nblocks,
+                lb_streams(a.n));
 }
 
 template <int CMAX>
@@ -125,8 +139,12 @@ __global__ __launch_bounds__(kThreads) void k_lb_accept_dots_batch(const LbVecAr
     if (e.pair < 0) return;
     const LbVecArgs& a = args[e.pair];
     if (a.st->ctl.phase != kPhAccepted) return;
-    lb_update_dots_body<true, CMAX>(a.st, a.hist, a.ld, a.n, a.y, a.yt, a.g, a.gt, a.dotpart,
-                                    e.block, a.nblocks);
+    if (lb_streams(a.n))
+        lb_update_dots_body<true, CMAX, true>(a.st, a.hist, a.ld, a.n, a.y, a.yt, a.g, a.gt,
+                                              a.dotpart, e.block, a.nblocks);
+    else
+        lb_update_dots_body<true, CMAX, false>(a.st, a.hist, a.ld, a.n, a.y, a.yt, a.g, a.gt,
+                                               a.dotpart, e.block, a.nblocks);
 }
 
 __global__ __launch_bounds__(kGramThreads) void k_lb_gram_plan_batch(const LbVecArgs* args) {

@@ -19,6 +19,39 @@ static_assert(kDots <= 64, "one lane per inner product in the Gram update");
 
 constexpr int kLbBlocks = 768;
 
+// Whether the L-BFGS vector passes of a level with n unknowns stream the
+// stored pairs and the direction past the last-level cache: from 4 Mi
+// unknowns on, the pairs alone fill a large part of it and would push out
+// the level's images, which every image pass reads again.
+__device__ inline bool lb_streams(int64_t n) { return n >= (int64_t{1} << 22); }
+
+// 16-byte loads and stores of the vector passes.  With NT the streams that
+// nothing reads again soon (the stored pairs, the direction) bypass the
+// last-level cache, which then keeps the level's images for the image pass.
+typedef float lb_f4 __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ inline float4 lb_ld4(const float* p, int64_t q) {
+    if constexpr (NT) {
+        const lb_f4 v = __builtin_nontemporal_load(reinterpret_cast<const lb_f4*>(p) + q);
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else {
+        return reinterpret_cast<const float4*>(p)[q];
+    }
+}
+template <bool NT>
+__device__ inline void lb_st4(float* p, int64_t q, float4 v) {
+    if constexpr (NT) {
+        lb_f4 w;
+        w.x = v.x;
+        w.y = v.y;
+        w.z = v.z;
+        w.w = v.w;
+        __builtin_nontemporal_store(w, reinterpret_cast<lb_f4*>(p) + q);
+    } else {
+        reinterpret_cast<float4*>(p)[q] = v;
+    }
+}
+
 __device__ inline double lb_wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     return v;
@@ -163,6 +196,7 @@ __device__ inline void lb_solve_wave(LbState* st, double* jds, SolveLds& w) {
 // thread and iteration (16-byte loads), then a scalar tail.  The pairs are
 // visited in a loop (two history streams at a time): unrolling it over all
 // pairs measured slower.
+template <bool NT>
 __device__ __forceinline__ void lb_combine_body(const LbState* st,
                                                 const float* __restrict__ hist, int64_t ld,
                                                 int64_t n, const float* __restrict__ y,
@@ -193,8 +227,8 @@ __device__ __forceinline__ void lb_combine_body(const LbState* st,
         double v0 = cg * gv.x, v1 = cg * gv.y, v2 = cg * gv.z, v3 = cg * gv.w;
         for (int k = 0; k < count; ++k) {
             const float* sk = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
-            const float4 a = reinterpret_cast<const float4*>(sk)[q];
-            const float4 b = reinterpret_cast<const float4*>(sk + ld)[q];
+            const float4 a = lb_ld4<NT>(sk, q);
+            const float4 b = lb_ld4<NT>(sk + ld, q);
             v0 += cs[k] * a.x + ct[k] * b.x;
             v1 += cs[k] * a.y + ct[k] * b.y;
             v2 += cs[k] * a.z + ct[k] * b.z;
@@ -203,7 +237,7 @@ __device__ __forceinline__ void lb_combine_body(const LbState* st,
         const float4 yv = reinterpret_cast<const float4*>(y)[q];
         const float4 dv = make_float4(static_cast<float>(v0), static_cast<float>(v1),
                                       static_cast<float>(v2), static_cast<float>(v3));
-        reinterpret_cast<float4*>(d)[q] = dv;
+        lb_st4<NT>(d, q, dv);
         reinterpret_cast<float4*>(yt)[q] =
             make_float4(yv.x + dv.x, yv.y + dv.y, yv.z + dv.z, yv.w + dv.w);
     }
@@ -242,7 +276,7 @@ __device__ __forceinline__ void lb_axpy_body(const float* __restrict__ y,
 // only 6 C + 6 float64 accumulators are live).  With ACCEPT, the accepted
 // trial point also replaces the current one (y = yt, g = gt), each element
 // by the thread that has just read it.
-template <bool ACCEPT, int C>
+template <bool ACCEPT, int C, bool NT>
 __device__ __forceinline__ void lb_dots_pass(const int* sl, int fs, float* __restrict__ hist,
                                              int64_t ld, int64_t n, float* y,
                                              const float* __restrict__ yt, float* g,
@@ -288,13 +322,13 @@ __device__ __forceinline__ void lb_dots_pass(const int* sl, int fs, float* __res
         float4 av[C > 0 ? C : 1], bv[C > 0 ? C : 1];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            av[k] = reinterpret_cast<const float4*>(hk[k])[q];
-            bv[k] = reinterpret_cast<const float4*>(hk[k] + ld)[q];
+            av[k] = lb_ld4<NT>(hk[k], q);
+            bv[k] = lb_ld4<NT>(hk[k] + ld, q);
         }
         const float4 s = make_float4(ytv.x - yv.x, ytv.y - yv.y, ytv.z - yv.z, ytv.w - yv.w);
         const float4 t = make_float4(gtv.x - gv.x, gtv.y - gv.y, gtv.z - gv.z, gtv.w - gv.w);
-        reinterpret_cast<float4*>(sn)[q] = s;
-        reinterpret_cast<float4*>(tn)[q] = t;
+        lb_st4<NT>(sn, q, s);
+        lb_st4<NT>(tn, q, t);
         if (ACCEPT) {
             reinterpret_cast<float4*>(y)[q] = ytv;
             reinterpret_cast<float4*>(g)[q] = gtv;
@@ -359,7 +393,7 @@ __device__ __forceinline__ void lb_dots_pass(const int* sl, int fs, float* __res
 // thread and iteration (16-byte loads), then a scalar tail.
 // CMAX: the largest pair count the kernel is built for (the L-BFGS memory
 // rounded up to 5 or 8); registers are allocated for the largest case.
-template <bool ACCEPT, int CMAX>
+template <bool ACCEPT, int CMAX, bool NT>
 __device__ __forceinline__ void lb_update_dots_body(const LbState* st,
                                                     float* __restrict__ hist, int64_t ld,
                                                     int64_t n, float* y,
@@ -379,8 +413,8 @@ __device__ __forceinline__ void lb_update_dots_body(const LbState* st,
     switch (cnt) {
 #define NGF_DOTS_CASE(C)                                                                \
     case C:                                                                             \
-        lb_dots_pass<ACCEPT, (C <= CMAX ? C : CMAX)>(sl, fs, hist, ld, n, y, yt, g, gt,   \
-                                                     dotpart, block, nblocks, sh);      \
+        lb_dots_pass<ACCEPT, (C <= CMAX ? C : CMAX), NT>(sl, fs, hist, ld, n, y, yt, g,   \
+                                                         gt, dotpart, block, nblocks, sh);  \
         break;
         NGF_DOTS_CASE(0)
         NGF_DOTS_CASE(1)
@@ -544,12 +578,16 @@ __device__ __forceinline__ void lb_vec_body(const LbState* st, const float* __re
                                             int64_t ld, int64_t n, const float* __restrict__ y,
                                             const float* __restrict__ g,
                                             float* __restrict__ d, float* __restrict__ yt,
-                                            int block, int nblocks) {
+                                            int block, int nblocks, bool nt) {
     const int op = st->ctl.op;
-    if (op == kOpCombine)
-        lb_combine_body(st, hist, ld, n, y, g, d, yt, block, nblocks);
-    else if (op == kOpAxpy)
+    if (op == kOpCombine) {
+        if (nt)
+            lb_combine_body<true>(st, hist, ld, n, y, g, d, yt, block, nblocks);
+        else
+            lb_combine_body<false>(st, hist, ld, n, y, g, d, yt, block, nblocks);
+    } else if (op == kOpAxpy) {
         lb_axpy_body(y, d, static_cast<float>(st->ctl.t), yt, n, block, nblocks);
+    }
 }
 
 // Gram update for the accepted step, then the stopping tests of the level:
