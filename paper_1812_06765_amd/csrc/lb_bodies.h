@@ -26,7 +26,8 @@ constexpr int kLbBlocks = 768;
 __device__ inline bool lb_streams(int64_t n) { return n >= (int64_t{1} << 22); }
 
 // 16-byte loads and stores of the vector passes.  With NT the streams that
-// nothing reads again soon (the stored pairs, the direction) bypass the
+// nothing reads again soon (the stored pairs, the direction, and in the
+// history update the last reads of y, g and their trial values) bypass the
 // last-level cache, which then keeps the level's images for the image pass.
 typedef float lb_f4 __attribute__((ext_vector_type(4)));
 template <bool NT>
@@ -315,10 +316,10 @@ __device__ __forceinline__ void lb_dots_pass(const int* sl, int fs, float* __res
     for (int k = 0; k < C; ++k) hk[k] = hist + (2 * static_cast<int64_t>(sl[k])) * ld;
     for (int64_t q = block * static_cast<int64_t>(kThreads) + threadIdx.x; q < n4;
          q += stride) {
-        const float4 yv = reinterpret_cast<const float4*>(y)[q];
-        const float4 ytv = reinterpret_cast<const float4*>(yt)[q];
-        const float4 gv = reinterpret_cast<const float4*>(g)[q];
-        const float4 gtv = reinterpret_cast<const float4*>(gt)[q];
+        const float4 yv = lb_ld4<NT>(y, q);
+        const float4 ytv = lb_ld4<NT>(yt, q);
+        const float4 gv = lb_ld4<NT>(g, q);
+        const float4 gtv = lb_ld4<NT>(gt, q);
         float4 av[C > 0 ? C : 1], bv[C > 0 ? C : 1];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
