@@ -65,6 +65,15 @@ SMALL = [(32, 48, 40), (64, 32, 48), (48, 48, 48), (40, 56, 32), (32, 32, 32),
          (56, 40, 64), (48, 32, 64), (64, 48, 32)]
 
 
+def test_empty_batch_is_a_no_op(gpu_lib):
+    ngf = gpu_lib
+    for mode in ("graph", "threads"):
+        b = ngf.Batch(levels=2, max_iter=5, workers=2, mode=mode, **PARAMS)
+        ys, reps = b.register([], [])
+        b.close()
+        assert ys == [] and reps == [], mode
+
+
 def test_batch_equals_single_pair_bitwise(gpu_lib):
     ngf = gpu_lib
     pairs = _pairs(SMALL, 100)

@@ -376,6 +376,12 @@ def test_error_paths(gpu_lib):
     with pytest.raises(ngf.NgfError) as e:
         ctx.build_pyramid(R, R)
     assert e.value.status == ngf.E_SHAPE
+    # An empty image: torch hands over a null data pointer for it, which the
+    # library's argument check rejects before its shape check would.
+    R = torch.zeros((0, 32, 32), device="cuda")
+    with pytest.raises(ngf.NgfError) as e:
+        ctx.build_pyramid(R, R)
+    assert e.value.status in (ngf.E_ARG, ngf.E_SHAPE)
     R = torch.zeros((8, 8, 8), device="cuda")
     with pytest.raises(ngf.NgfError) as e:
         ctx.build_pyramid(R, R)  # coarsest level would have 2 cells per axis
