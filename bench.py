@@ -15,6 +15,8 @@ Printed (one JSON line):
               levels, line-search trials included) per second;
 * accuracy_voxels  distance of the registration to the true correspondence at
               sampled body and edge voxels, next to the identity's;
+* image_mismatch_hu  mean |T(P y) - R| at sampled voxels for the registration,
+              the identity and the true correspondence;
 * roofline    the dominant kernel (the fused image-grid pass), timed with HIP
               events on the library's stream over the timed region;
 * cpu_baseline the FP64 oracle on the host, one 256^3 evaluation.
@@ -118,6 +120,49 @@ def accuracy(ctx, y, pr, samples=20000, seed=5):
             at = v[:, idx[0], idx[1], idx[2]].double().cpu().numpy()
             res.append(float(np.sqrt(((at - zstar) ** 2).sum(0)).mean()))
         out[name] = {"identity": res[0], "registered": res[1]}
+    return out
+
+
+def _trilinear(V, p):
+    """V (float64 array) at points p (3, n) in voxel units, voxel i's centre at
+    i + 1/2; points outside are clamped to the edge voxels."""
+    import numpy as np
+    i0, f = [], []
+    for d in range(3):
+        xi = np.clip(p[d] - 0.5, 0.0, V.shape[d] - 1.0)
+        i = np.minimum(np.floor(xi), V.shape[d] - 2).astype(np.int64)
+        i0.append(i)
+        f.append(xi - i)
+    out = np.zeros(p.shape[1])
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                w = ((f[0] if a else 1.0 - f[0]) * (f[1] if b else 1.0 - f[1])
+                     * (f[2] if c else 1.0 - f[2]))
+                out += w * V[i0[0] + a, i0[1] + b, i0[2] + c]
+    return out
+
+
+def image_mismatch(ctx, y, pr, samples=200000, seed=7):
+    """Mean |T(P y) - R| (HU) at uniformly sampled voxels, next to the same for
+    the identity and for the true correspondence: the registration's image
+    match, which the objective rewards, beside the correspondence error."""
+    import numpy as np
+    import torch
+
+    from paper_1812_06765_amd import synth
+    m = pr.R.shape
+    rng = np.random.default_rng(seed)
+    pick = np.unravel_index(rng.choice(m[0] * m[1] * m[2], size=samples, replace=False), m)
+    pts = np.stack(pick).astype(np.float64) + 0.5
+    idx = tuple(torch.from_numpy(p.astype(np.int64)).cuda() for p in pick)
+    at = ctx.apply_P(0, y)[:, idx[0], idx[1], idx[2]].double().cpu().numpy()
+    zstar = synth.invert_displacement(pr.field, pts)
+    Rv = pr.R[pick].astype(np.float64)
+    Tv = pr.T.astype(np.float64)
+    out = {"samples": samples}
+    for name, p in (("identity", pts), ("registered", at), ("truth", zstar)):
+        out[name] = float(np.abs(_trilinear(Tv, p) - Rv).mean())
     return out
 
 
@@ -280,6 +325,11 @@ def main():
                     help="image shape (x y z) instead of size^3, e.g. 512 512 1536")
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--max-iter", type=int, default=50)
+    ap.add_argument("--alpha", type=float, default=0.1, help="curvature weight")
+    ap.add_argument("--eps", type=float, default=10.0,
+                    help="NGF edge parameter of R and T (HU per unit length)")
+    ap.add_argument("--noise", type=float, default=20.0,
+                    help="std of the phantom's Gaussian noise in R and T (HU)")
     ap.add_argument("--finest-evals", type=int, default=200)
     ap.add_argument("--host-reps", type=int, default=3,
                     help="registrations from pinned host arrays (PCIe-inclusive timing)")
@@ -329,15 +379,16 @@ def main():
         def progress(done, total):
             if done % 128 == 0 or done == total:
                 print(f"[bench] inputs: {done}/{total} planes", file=sys.stderr, flush=True)
-        pr = synth.ct_phantom_pair_slabs(shape, seed_R=5, seed_u=6, progress=progress,
+        pr = synth.ct_phantom_pair_slabs(shape, seed_R=5, seed_u=6, noise=args.noise,
+                                         progress=progress,
                                          workers=min(16, os.cpu_count() or 1))
     else:
-        pr = synth.ct_phantom_pair(shape, seed_R=5, seed_u=6)
+        pr = synth.ct_phantom_pair(shape, seed_R=5, seed_u=6, noise=args.noise)
     t_gen = time.perf_counter() - t_gen
     print(f"[bench] inputs {sname} generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
     R = torch.from_numpy(pr.R).cuda()
     T = torch.from_numpy(pr.T).cuda()
-    ctx = ngf.Context(alpha=0.1, tau=10.0, rho=10.0, levels=args.levels, ratio=2,
+    ctx = ngf.Context(alpha=args.alpha, tau=args.eps, rho=args.eps, levels=args.levels, ratio=2,
                       max_iter=args.max_iter, lbfgs_mem=5, tol_J=1e-6, early_stop=True)
     # image-pass variants by the size rule (the timed selection's choices on
     # cubic levels), so that no selection runs appear in a profile of this run
@@ -419,8 +470,9 @@ def main():
         "data": "synthetic: seeded CT-like phantom pair, B-spline warp (max 6 voxels)",
         "config": {"workload": f"single pair {sname} CT phantom, {args.levels}-level pyramid, "
                                f"deformation grid {'x'.join(str(v) for v in li.my)} at the "
-                               "finest level, "
-                               f"alpha=0.1, eps=10, L-BFGS m=5, <= {args.max_iter} it/level, "
+                               f"finest level, noise {args.noise:g} HU, "
+                               f"alpha={args.alpha:g}, eps={args.eps:g}, L-BFGS m=5, "
+                               f"<= {args.max_iter} it/level, "
                                "early stop 1e-6",
                    "global_batch": 1, "seq_len": None, "parallelism": "single GPU"},
         "registration_s": dt / args.steps,
@@ -453,6 +505,7 @@ def main():
     }
     if not args.no_accuracy and shape[0] * shape[1] * shape[2] <= (1 << 26):
         out["accuracy_voxels"] = accuracy(ctx, y, pr)
+        out["image_mismatch_hu"] = image_mismatch(ctx, y, pr)
         print("[bench] accuracy sampled", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, 256^3 eval)...", file=sys.stderr, flush=True)
