@@ -61,6 +61,7 @@
 #define NGFREG_H
 
 #include <stdint.h>
+#include <stddef.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -270,6 +271,31 @@ ngf_status ngf_lbfgs_step(ngf_ctx* ctx, double* J, int32_t* info);
  * buffers (either may be NULL); `J` (host, may be NULL) gets J there. */
 ngf_status ngf_lbfgs_get(ngf_ctx* ctx, float* y, float* grad, double* J);
 
+/* Checkpoint and resume of an L-BFGS level (Sec. 2.1: the iterate and the
+ * stored correction pairs are the whole state of the method between two
+ * iterations).  ngf_lbfgs_save writes the state left by ngf_lbfgs_reset and
+ * ngf_lbfgs_step calls into a host buffer: the level, its deformation-grid
+ * shape, the iterate y and its gradient, J and the evaluation count, the
+ * device state block (Gram matrix of the stored pairs and the gradient, ring
+ * order, control block) and the stored pairs (s, t) of the slots in use.
+ * ngf_lbfgs_load puts such a state back, into this context or another one
+ * of the same library build with a pyramid of the same shapes and the same
+ * L-BFGS memory; the ngf_lbfgs_step calls that follow take the same steps,
+ * bit for bit, as they would have taken after the save.
+ *   ngf_lbfgs_state_size  *bytes: the size of the state as it stands now
+ *                         (it depends on the number of stored pairs)
+ *   ngf_lbfgs_save        buf: host memory of at least that size; bytes: its
+ *                         size.  Synchronises.
+ *   ngf_lbfgs_load        buf, bytes: a saved state.  Synchronises.
+ * Errors: NGF_E_STATE before ngf_lbfgs_reset (save) or without a pyramid
+ * (load); NGF_E_ARG for a null buffer, a buffer too small, or bytes that are
+ * not a state of this build (wrong header, size or memory); NGF_E_SHAPE when
+ * the saved level's grid differs from this context's level of that index;
+ * NGF_E_LEVEL when this context has no such level. */
+ngf_status ngf_lbfgs_state_size(const ngf_ctx* ctx, size_t* bytes);
+ngf_status ngf_lbfgs_save(ngf_ctx* ctx, void* buf, size_t bytes);
+ngf_status ngf_lbfgs_load(ngf_ctx* ctx, const void* buf, size_t bytes);
+
 /* Prolongate a deformation from level `coarse_level` to the next finer level
  * (coarse-to-fine scheme of Sec. 2.1): along each axis fine node 2j takes
  * coarse node j, fine node 2j+1 the mean of coarse nodes j and j+1.  Only for
@@ -393,6 +419,38 @@ ngf_status ngf_apply_PT(ngf_ctx* ctx, int32_t level, const float* z, float* out,
 ngf_status ngf_set_profiling(ngf_ctx* ctx, int32_t enable, int32_t level);
 ngf_status ngf_kernel_time(ngf_ctx* ctx, int32_t level, int32_t* launches, double* total_ms,
                            int64_t* voxels, int64_t* nodes);
+
+/* Per-iteration record of the L-BFGS levels (the quantities Sec. 2.1 and
+ * Sec. 3 speak of, one record per accepted step, plus one for the start
+ * point of every level). */
+typedef struct {
+    int32_t level;   /* pyramid level */
+    int32_t iter;    /* accepted steps on the level so far (0: its start point) */
+    int32_t evals;   /* J + grad J evaluations on the level so far */
+    int32_t reserved;
+    double J, D, S;  /* objective (Eq. 1) and its two terms at the iterate */
+    double gmax;     /* max |grad J| at the iterate */
+    double t;        /* step length of the accepted step (0 at the start) */
+    double us;       /* time since the previous record of the level: device
+                        clock for the device-driven search, host clock for the
+                        host-driven one (0 at the start) */
+} ngf_iter_record;
+
+/* Iteration log.  ngf_set_iteration_log(ctx, 1) starts recording (and
+ * clears the log), 0 stops.  While on, ngf_lbfgs_reset adds the start record
+ * of its level and every accepted step adds one record, in both drivers
+ * (ngf_set_driver), which give the same records apart from `us`;
+ * ngf_register and ngf_register_levels clear the log first.  The
+ * device-driven search then adds one single-lane kernel per round and its
+ * records are copied back at the end of each level; its buffer (one record
+ * per possible step of a level) is allocated when a level needs a larger one.
+ * The batched form records nothing.
+ * ngf_iteration_log copies up to `cap` records, oldest first, into `out`
+ * (host; may be NULL when cap is 0) and sets *count to the number recorded.
+ * Errors: NGF_E_ARG for a negative cap or a null count. */
+ngf_status ngf_set_iteration_log(ngf_ctx* ctx, int32_t enable);
+ngf_status ngf_iteration_log(const ngf_ctx* ctx, ngf_iter_record* out, int32_t cap,
+                             int32_t* count);
 
 /* Failure injection, for tests of the error paths (no other use).  `flags`
  * is a bit set; 0 clears it.

@@ -3,6 +3,7 @@
 // Every compute step runs in the HIP kernels of this library; this file only
 // validates arguments, owns device buffers and enqueues work.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -27,6 +28,15 @@ ngf_status fail(ngf_ctx* c, ngf_status s, const std::string& msg) {
     if (c) c->err = msg;
     return s;
 }
+
+// A named host-side range for tools that collect markers (rocprofv3
+// --marker-trace); without such a tool the calls return at once.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 #define HIPCHK(ctx, expr)                                                              \
     do {                                                                               \
@@ -588,6 +598,10 @@ ngf_status enqueue_round(ngf_ctx* c, const Level& L, bool* recorded) {
     const ngf_status e = enqueue_eval(c, L, L.R, L.T, c->lyt, c->lgt, gate, c->st);
     if (e != NGF_OK) return e;
     *recorded = c->nprof > before;
+    if (c->log_on) {
+        const ngf_status le = log_round(c);
+        if (le != NGF_OK) return le;
+    }
     launch_lb_accept(c->st, c->hist, static_cast<int64_t>(c->lb_ld), n, c->ly, c->lyt, c->lg,
                      c->lgt, c->dotpart, lb_dot_blocks(n), c->jds, c->p.lbfgs_mem, c->stream);
     HIPCHK(c, hipGetLastError());
@@ -609,6 +623,10 @@ ngf_status run_level_on_device(ngf_ctx* c, LbCtl* out) {
     LbCtl* h = reinterpret_cast<LbCtl*>(c->host_jds + 8);
     launch_lb_plan(c->st, c->jds, c->stream);  // later plans end the rounds before them
     HIPCHK(c, hipGetLastError());
+    if (c->log_on) {
+        const ngf_status le = log_level_begin(c);
+        if (le != NGF_OK) return le;
+    }
     for (;;) {
         for (int k = 0; k < batch; ++k) {
             bool r = false;
@@ -632,6 +650,8 @@ ngf_status run_level_on_device(ngf_ctx* c, LbCtl* out) {
     c->lb_J = h->J;
     c->lb_gmax = h->gmax;
     c->lb_evals = h->evals;
+    c->lb_iters = h->iters;
+    if (c->log_on) return log_level_end(c, h->iters);
     return NGF_OK;
 }
 
@@ -771,6 +791,7 @@ void ngf_destroy(ngf_ctx* c) {
     for (hipEvent_t e : c->ev)
         if (e) (void)hipEventDestroy(e);
     free_pyramid(c);
+    log_free(c);
     for (void* p : {static_cast<void*>(c->part), static_cast<void*>(c->dpart),
                     static_cast<void*>(c->spart), static_cast<void*>(c->gpart),
                     static_cast<void*>(c->jds), static_cast<void*>(c->dflag),
@@ -807,6 +828,7 @@ ngf_status ngf_set_params(ngf_ctx* c, const ngf_params* p) {
 ngf_status ngf_build_pyramid(ngf_ctx* c, const float* R, const float* T, const ngf_grid* g,
                              int32_t host_ptrs) {
     if (!c) return NGF_E_ARG;
+    const TraceRange range("ngf_build_pyramid");
     if (!R || !T || !g) return fail(c, NGF_E_ARG, "null R, T or grid");
     const int L = c->p.levels, r = c->p.ratio;
     int64_t N = 1;
@@ -1062,12 +1084,15 @@ ngf_status ngf_lbfgs_reset(ngf_ctx* c, int32_t level, const float* y0) {
     c->lb_J = c->host_jds[0];
     c->lb_gmax = c->host_jds[3];
     c->lb_evals = 1;
+    c->lb_iters = 0;
     if (!std::isfinite(c->lb_J)) return fail(c, NGF_E_NONFINITE, "J(y0) is not finite");
+    log_start_point(c);
     return NGF_OK;
 }
 
 ngf_status ngf_lbfgs_step(ngf_ctx* c, double* J, int32_t* info) {
     if (!c) return NGF_E_ARG;
+    const TraceRange range("ngf_lbfgs_step");
     if (c->lb_level < 0 || c->lb_level >= static_cast<int>(c->lv.size()))
         return fail(c, NGF_E_STATE, "ngf_lbfgs_reset first");
     const Level& L = c->lv[c->lb_level];
@@ -1112,6 +1137,8 @@ ngf_status ngf_lbfgs_step(ngf_ctx* c, double* J, int32_t* info) {
             std::swap(c->lg, c->lgt);
             c->lb_J = c->host_jds[0];
             c->lb_gmax = c->host_jds[3];
+            c->lb_iters++;
+            log_host_step(c, t);
         }
     }
     if (J) *J = c->lb_J;
@@ -1152,8 +1179,13 @@ ngf_status ngf_register_levels(ngf_ctx* c, float* y_out, ngf_report* rep) {
         std::memset(rep, 0, sizeof(*rep));
         rep->levels = static_cast<int32_t>(c->lv.size());
     }
+    c->log.clear();
     const int L = static_cast<int>(c->lv.size());
     for (int lev = L - 1; lev >= 0; --lev) {
+        char rname[64];
+        std::snprintf(rname, sizeof(rname), "ngf level %d (%dx%dx%d)", lev, c->lv[lev].m[0],
+                      c->lv[lev].m[1], c->lv[lev].m[2]);
+        const TraceRange range(rname);
         const auto t_level = std::chrono::steady_clock::now();
         const Level& lv = c->lv[lev];
         if (lev == L - 1) {
@@ -1214,6 +1246,7 @@ ngf_status ngf_register_levels(ngf_ctx* c, float* y_out, ngf_report* rep) {
 ngf_status ngf_register(ngf_ctx* c, const float* R, const float* T, const ngf_grid* g,
                         float* y_out, int32_t host_ptrs, ngf_report* rep) {
     if (!c) return NGF_E_ARG;
+    const TraceRange range("ngf_register");
     ngf_status e = ngf_build_pyramid(c, R, T, g, host_ptrs);
     if (e != NGF_OK) return e;
     if (!host_ptrs) return ngf_register_levels(c, y_out, rep);

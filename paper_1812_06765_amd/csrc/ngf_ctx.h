@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <string>
 #include <utility>
 #include <vector>
@@ -42,6 +43,14 @@ struct LevelStore {
 };
 
 constexpr int kProfMax = 4096;
+
+// One accepted L-BFGS step as the device-driven search records it (slot k of
+// the level's record buffer; slot 0 holds the tick of the level's start).
+struct IterDev {
+    int iter, evals;
+    double J, D, S, gmax, t;
+    unsigned long long tick;  // device wall clock
+};
 
 }  // namespace ngf_host
 
@@ -84,6 +93,14 @@ struct ngf_ctx {
     double lb_J = 0.0;
     double lb_gmax = 0.0;
     int lb_evals = 0;
+    int lb_iters = 0;  // accepted steps since ngf_lbfgs_reset
+
+    // iteration log (ngf_set_iteration_log)
+    bool log_on = false;
+    std::vector<ngf_iter_record> log;
+    ngf_host::IterDev* log_dev = nullptr;  // records of the running device-driven level
+    int log_dev_cap = 0;
+    std::chrono::steady_clock::time_point log_prev;  // host time of the last host record
 
     // float64 evaluation (precision study): one scratch buffer of doubles,
     // allocated on the first float64 evaluation and grown when a later one
@@ -154,5 +171,18 @@ ngf_status eval_scatter(ngf_ctx* c, const Level& P, const float* R, const float*
 // Device address of the static scratch array of the no-allocation entry
 // point on the current device; taken once per device at context creation.
 ngf_status static_scratch_setup(ngf_ctx* c);
+
+// Iteration log hooks (no-ops while the log is off).
+// After ngf_lbfgs_reset has read J at y0 into host_jds: the start record.
+void log_start_point(ngf_ctx* c);
+// After an accepted host-driven step of length t (host_jds holds the new point).
+void log_host_step(ngf_ctx* c, double t);
+// Device-driven level: before its first round (buffer, start tick), after
+// the evaluation of every round (records an accepted step), and after the
+// level has ended with `iters` accepted steps (copies the records back).
+ngf_status log_level_begin(ngf_ctx* c);
+ngf_status log_round(ngf_ctx* c);
+ngf_status log_level_end(ngf_ctx* c, int iters);
+void log_free(ngf_ctx* c);
 
 }  // namespace ngf_host

@@ -45,6 +45,25 @@ class Report(ctypes.Structure):
                 ("J", ctypes.c_double * MAX_LEVELS), ("ms", ctypes.c_double * MAX_LEVELS)]
 
 
+class IterRecord(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("iter", ctypes.c_int32), ("evals", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("J", ctypes.c_double), ("D", ctypes.c_double),
+                ("S", ctypes.c_double), ("gmax", ctypes.c_double), ("t", ctypes.c_double),
+                ("us", ctypes.c_double)]
+
+
+ITER_FIELDS = ("level", "iter", "evals", "J", "D", "S", "gmax", "t", "us")
+
+
+def write_jsonl(records, path):
+    """Write iteration records (dicts as Context.iteration_log returns them)
+    as JSON lines, one record per line."""
+    import json
+    with open(path, "w") as f:
+        for r in records:
+            f.write(json.dumps({k: r[k] for k in ITER_FIELDS}) + "\n")
+
+
 class NgfError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -82,6 +101,11 @@ def load():
         "ngf_lbfgs_reset": ([_P, i32, _P], i32),
         "ngf_lbfgs_step": ([_P, ctypes.POINTER(f64), ctypes.POINTER(i32)], i32),
         "ngf_lbfgs_get": ([_P, _P, _P, ctypes.POINTER(f64)], i32),
+        "ngf_lbfgs_state_size": ([_P, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "ngf_lbfgs_save": ([_P, _P, ctypes.c_size_t], i32),
+        "ngf_lbfgs_load": ([_P, _P, ctypes.c_size_t], i32),
+        "ngf_set_iteration_log": ([_P, i32], i32),
+        "ngf_iteration_log": ([_P, ctypes.POINTER(IterRecord), i32, ctypes.POINTER(i32)], i32),
         "ngf_prolongate": ([_P, i32, _P, _P], i32),
         "ngf_register": ([_P, _P, _P, ctypes.POINTER(Grid), _P, i32, ctypes.POINTER(Report)], i32),
         "ngf_register_levels": ([_P, _P, ctypes.POINTER(Report)], i32),
@@ -292,6 +316,39 @@ class Context:
         J = ctypes.c_double()
         self._chk(self.lib.ngf_lbfgs_get(self.h, _ptr(y), _ptr(g), ctypes.byref(J)))
         return y, g, J.value
+
+    def lbfgs_save(self) -> bytes:
+        """The L-BFGS state left by lbfgs_reset / lbfgs_step (level, iterate,
+        gradient, stored pairs, device state block) as bytes."""
+        n = ctypes.c_size_t()
+        self._chk(self.lib.ngf_lbfgs_state_size(self.h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._chk(self.lib.ngf_lbfgs_save(self.h, buf, n))
+        return buf.raw
+
+    def lbfgs_load(self, state: bytes):
+        """Resume from lbfgs_save's bytes (same pyramid shapes and memory);
+        lbfgs_step then continues as it would have after the save."""
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        self._chk(self.lib.ngf_lbfgs_load(self.h, buf, len(state)))
+
+    def set_iteration_log(self, enable=True):
+        """Record every accepted L-BFGS step (and each level's start point);
+        clears the log."""
+        self._chk(self.lib.ngf_set_iteration_log(self.h, int(bool(enable))))
+
+    def iteration_log(self, path=None):
+        """The records since the log was cleared, as dicts with the keys
+        level, iter, evals, J, D, S, gmax, t, us; also written to ``path`` as
+        JSON lines when given."""
+        n = ctypes.c_int32()
+        self._chk(self.lib.ngf_iteration_log(self.h, None, 0, ctypes.byref(n)))
+        arr = (IterRecord * max(n.value, 1))()
+        self._chk(self.lib.ngf_iteration_log(self.h, arr, n.value, ctypes.byref(n)))
+        recs = [{k: getattr(arr[i], k) for k in ITER_FIELDS} for i in range(n.value)]
+        if path is not None:
+            write_jsonl(recs, path)
+        return recs
 
     def prolongate(self, coarse_level, yc):
         fine = self.level_info(coarse_level - 1).my

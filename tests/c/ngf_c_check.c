@@ -73,6 +73,19 @@ static int cpu_checks(void) {
     CHECK(ngf_create(&p, NULL, NULL) == NGF_E_ARG, "null output accepted");
     CHECK(ngf_eval_J_grad(NULL, 0, NULL, NULL, NULL, NULL) == NGF_E_ARG, "null context");
     CHECK(ngf_register(NULL, NULL, NULL, NULL, NULL, 1, NULL) == NGF_E_ARG, "null context");
+    {
+        /* iteration log and L-BFGS checkpoint: record layout, argument checks */
+        size_t bytes = 0;
+        int32_t count = 0;
+        char buf[8] = {0};
+        CHECK(sizeof(ngf_iter_record) == 64, "iteration record of %u bytes",
+              (unsigned)sizeof(ngf_iter_record));
+        CHECK(ngf_set_iteration_log(NULL, 1) == NGF_E_ARG, "null context");
+        CHECK(ngf_iteration_log(NULL, NULL, 0, &count) == NGF_E_ARG, "null context");
+        CHECK(ngf_lbfgs_state_size(NULL, &bytes) == NGF_E_ARG, "null context");
+        CHECK(ngf_lbfgs_save(NULL, buf, sizeof buf) == NGF_E_ARG, "null context");
+        CHECK(ngf_lbfgs_load(NULL, buf, sizeof buf) == NGF_E_ARG, "null context");
+    }
     printf("c abi cpu checks ok (%s)\n", v);
     return 0;
 }

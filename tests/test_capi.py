@@ -101,3 +101,37 @@ def test_c_caller_compiles_links_and_checks_arguments(tmp_path):
     r = subprocess.run([exe, "cpu"], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "cpu checks ok" in r.stdout
+
+
+def test_iteration_record_layout_and_jsonl(tmp_path):
+    """The binding's record matches the header's 64-byte ngf_iter_record
+    field by field, and the JSON-lines writer keeps every field."""
+    import json
+
+    from paper_1812_06765_amd.ngf import ITER_FIELDS, IterRecord, write_jsonl
+    assert ctypes.sizeof(IterRecord) == 64
+    offs = {name: getattr(IterRecord, name).offset for name, _ in IterRecord._fields_}
+    assert offs == {"level": 0, "iter": 4, "evals": 8, "reserved": 12, "J": 16, "D": 24,
+                    "S": 32, "gmax": 40, "t": 48, "us": 56}
+    recs = [dict(level=1, iter=0, evals=1, J=3.5, D=3.0, S=5.0, gmax=0.25, t=0.0, us=0.0),
+            dict(level=0, iter=7, evals=9, J=1.25, D=1.0, S=2.5, gmax=1e-3, t=0.5, us=12.5)]
+    path = tmp_path / "log.jsonl"
+    write_jsonl(recs, str(path))
+    back = [json.loads(line) for line in open(path)]
+    assert back == [{k: r[k] for k in ITER_FIELDS} for r in recs]
+
+
+def test_aux_calls_check_arguments_without_gpu(lib):
+    """Log and checkpoint calls reject a null context before any HIP call."""
+    from paper_1812_06765_amd.ngf import E_ARG
+    for name in ("ngf_set_iteration_log", "ngf_iteration_log", "ngf_lbfgs_state_size",
+                 "ngf_lbfgs_save", "ngf_lbfgs_load"):
+        getattr(lib, name).restype = ctypes.c_int32
+    n = ctypes.c_int32()
+    sz = ctypes.c_size_t()
+    buf = ctypes.create_string_buffer(8)
+    assert lib.ngf_set_iteration_log(None, 1) == E_ARG
+    assert lib.ngf_iteration_log(None, None, 0, ctypes.byref(n)) == E_ARG
+    assert lib.ngf_lbfgs_state_size(None, ctypes.byref(sz)) == E_ARG
+    assert lib.ngf_lbfgs_save(None, buf, ctypes.c_size_t(8)) == E_ARG
+    assert lib.ngf_lbfgs_load(None, buf, ctypes.c_size_t(8)) == E_ARG

@@ -1,0 +1,146 @@
+"""Iteration log and L-BFGS checkpoint / resume through the C ABI.
+
+Sec. 2.1 solves every level with L-BFGS; between two iterations its whole
+state is the iterate, its gradient and the stored correction pairs.  The log
+records each accepted step (and each level's start point) in both line-search
+drivers; a saved state resumes a level bit for bit.  Inputs: the 32^3 blob
+pair (ellipsoid with six Gaussian blobs, sinusoidal warp of 2 voxels)."""
+
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1812_06765_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+M = (32, 32, 32)
+KW = dict(alpha=0.1, tau=0.1, rho=0.1, levels=2, max_iter=12, lbfgs_mem=5)
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _pair(m=M):
+    return synth.blob_phantom_pair(m, seed_R=1, seed_u=2, max_disp=2.0)
+
+
+def test_iteration_log_drivers_agree_and_follow_the_oracle(gpu_lib, tmp_path):
+    ngf = gpu_lib
+    pr = _pair()
+    logs = {}
+    for drv in ("device", "host"):
+        ctx = ngf.Context(**KW)
+        ctx.set_kernel("by_size")
+        ctx.set_driver(drv)
+        ctx.set_iteration_log(True)
+        _, rep = ctx.register(_t(pr.R), _t(pr.T))
+        logs[drv] = (ctx.iteration_log(path=str(tmp_path / f"{drv}.jsonl")), rep)
+        ctx.close()
+    recs, rep = logs["device"]
+    _say(f"[log] {len(recs)} records, report {rep}")
+    assert [x["level"] for x in recs] == sorted((x["level"] for x in recs), reverse=True)
+    for r in rep:
+        lv = [x for x in recs if x["level"] == r["level"]]
+        assert [x["iter"] for x in lv] == list(range(r["iters"] + 1))
+        assert lv[0]["t"] == 0.0 and lv[0]["us"] == 0.0 and lv[0]["evals"] == 1
+        assert lv[-1]["J"] == r["J"]
+        if r["info"] in (ngf.INFO_MAX_ITER, ngf.INFO_CONVERGED):
+            assert lv[-1]["evals"] == r["evals"]
+        for a, b in zip(lv, lv[1:]):
+            assert b["J"] <= a["J"] and b["evals"] > a["evals"]
+            assert b["t"] > 0.0 and np.log2(b["t"]) == np.round(np.log2(b["t"]))
+            assert b["us"] > 0.0
+        for x in lv:
+            assert abs(x["J"] - (x["D"] + KW["alpha"] * x["S"])) <= 1e-12 * abs(x["J"])
+            assert x["gmax"] > 0.0
+    # the two drivers take the same steps: identical records but for the clock
+    hrecs, _ = logs["host"]
+
+    def strip(rs):
+        return [{k: v for k, v in x.items() if k != "us"} for x in rs]
+
+    assert strip(hrecs) == strip(recs)
+    assert [json.loads(line) for line in open(tmp_path / "device.jsonl")] == recs
+    # the oracle's registration, accepted step by accepted step
+    rec_o = []
+    _, repo = O.register(pr.R, pr.T, (1.0, 1.0, 1.0), levels=2, alpha=0.1, tau=0.1, rho=0.1,
+                         max_iter=12, mem=5, record=rec_o)
+    for lev, it, _, _, _ in repo:
+        Jo = [J for (lv_, J) in rec_o if lv_ == lev]
+        Jg = [x["J"] for x in recs if x["level"] == lev and x["iter"] > 0]
+        assert len(Jg) == len(Jo) == it
+        rel = max(abs(a - b) / abs(b) for a, b in zip(Jg, Jo))
+        _say(f"[log] level {lev}: {it} steps, largest relative J difference {rel:.2e}")
+        assert rel <= 5e-3
+
+
+def test_lbfgs_checkpoint_resume_bitwise(gpu_lib):
+    ngf = gpu_lib
+    pr = _pair()
+    kw = dict(alpha=0.1, tau=0.1, rho=0.1, levels=1, max_iter=50, lbfgs_mem=3)
+
+    def built(**over):
+        c = ngf.Context(**{**kw, **over})
+        c.set_kernel("by_size")
+        c.build_pyramid(_t(pr.R), _t(pr.T))
+        return c
+
+    def steps(c, k):
+        out = []
+        for _ in range(k):
+            J, info = c.lbfgs_step()
+            assert info == ngf.INFO_OK
+            out.append(J)
+        return out
+
+    a = built()
+    with pytest.raises(ngf.NgfError) as e:
+        a.lbfgs_save()  # nothing to save before a reset
+    assert e.value.status == ngf.E_STATE
+    a.lbfgs_reset(0, a.identity(0))
+    steps(a, 5)  # memory 3: the ring has dropped its oldest pairs
+    state = a.lbfgs_save()
+    n = 3 * 17 ** 3
+    assert len(state) > (2 + 2 * 3) * 4 * n  # y, g and three stored pairs
+    Ja = steps(a, 6)
+    ya, ga, _ = a.lbfgs_get(0)
+
+    b = built()
+    b.lbfgs_load(state)
+    Jb = steps(b, 6)
+    yb, gb, _ = b.lbfgs_get(0)
+    _say(f"[resume] J after the save {Ja}, resumed {Jb}")
+    assert Jb == Ja
+    assert bool((yb == ya).all()) and bool((gb == ga).all())
+    # rewinding the first context to the saved point replays the same steps
+    a.lbfgs_load(state)
+    assert steps(a, 6) == Ja
+
+    # states that do not fit are refused
+    for bad, status in ((state[:-1], ngf.E_ARG), (b"x" + state[1:], ngf.E_ARG)):
+        with pytest.raises(ngf.NgfError) as e:
+            b.lbfgs_load(bad)
+        assert e.value.status == status
+    other_mem = built(lbfgs_mem=5)
+    with pytest.raises(ngf.NgfError) as e:
+        other_mem.lbfgs_load(state)
+    assert e.value.status == ngf.E_ARG
+    small = _pair((24, 24, 24))
+    other_shape = ngf.Context(**kw)
+    other_shape.build_pyramid(_t(small.R), _t(small.T))
+    with pytest.raises(ngf.NgfError) as e:
+        other_shape.lbfgs_load(state)
+    assert e.value.status == ngf.E_SHAPE
+    for c in (a, b, other_mem, other_shape):
+        c.close()
