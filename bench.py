@@ -342,8 +342,9 @@ def main():
     ap.add_argument("--workers", type=int, default=4)
     ap.add_argument("--pt-ablation", action="store_true",
                     help="instead: time the three P^T schemes and P at the 256^3 grids")
-    ap.add_argument("--kernel", default="by_size",
-                    help="image-pass selection: by_size (default), auto, or a variant name")
+    ap.add_argument("--kernel", default="auto",
+                    help="image-pass selection: auto (the timed selection, default), by_size "
+                         "(the size rule) or a variant name")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only copy 1 GiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -390,9 +391,14 @@ def main():
     T = torch.from_numpy(pr.T).cuda()
     ctx = ngf.Context(alpha=args.alpha, tau=args.eps, rho=args.eps, levels=args.levels, ratio=2,
                       max_iter=args.max_iter, lbfgs_mem=5, tol_J=1e-6, early_stop=True)
-    # image-pass variants by the size rule (the timed selection's choices on
-    # cubic levels), so that no selection runs appear in a profile of this run
+    # image-pass variants: the timed selection times its candidates for every
+    # level shape when the pyramid is first built, here, before the warm-up
+    # and the timed region (later pyramids of the same shapes reuse them)
     ctx.set_kernel(args.kernel)
+    ctx.build_pyramid(R, T)
+    vname = {v: k for k, v in ngf.Context.VARIANTS.items()}
+    variants = [vname[ctx.get_kernel(lev)] for lev in range(args.levels)]
+    print(f"[bench] image-pass variants per level: {variants}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         ctx.register(R, T)
@@ -476,6 +482,7 @@ def main():
                                "early stop 1e-6",
                    "global_batch": 1, "seq_len": None, "parallelism": "single GPU"},
         "registration_s": dt / args.steps,
+        "image_pass_variants": {"selection": args.kernel, "per_level": variants},
         "evals_per_registration": evals / args.steps,
         "evals_per_s_registration": evals / dt,
         "levels": reports[-1],
