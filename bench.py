@@ -19,6 +19,8 @@ Printed (one JSON line):
               the identity and the true correspondence;
 * roofline    the dominant kernel (the fused image-grid pass), timed with HIP
               events on the library's stream over the timed region;
+* forms       the differentiation form (level form and autograd) and the
+              batched form (64 uneven pairs) beside the plain one;
 * cpu_baseline the FP64 oracle on the host, one 256^3 evaluation.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -238,32 +240,41 @@ def bench_pt(args, torch, ngf):
     print(json.dumps(out), flush=True)
 
 
-def bench_batch(args, torch, ngf, synth):
-    """Uneven batch: pairs with axes drawn from {96, 128, 160, 192, 256}, the
-    CT phantom recipe per pair, 3 levels.  Timed: the batched form in graph
-    mode (the reported value), in threads mode, and the same pairs registered
-    one after another by a single context."""
-    shapes = synth.batch_shapes(args.batch)
-    Rs, Ts = [], []
+def _batch_inputs(torch, synth, npairs):
+    """The uneven batch: axes drawn from {96, 128, 160, 192, 256}, the CT
+    phantom recipe per pair (seeds 1000 + 2 i and 1001 + 2 i), generated on
+    host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    shapes = synth.batch_shapes(npairs)
     t_gen = time.perf_counter()
-    for i, m in enumerate(shapes):
-        pr = synth.ct_phantom_pair(m, seed_R=1000 + 2 * i, seed_u=1001 + 2 * i)
-        Rs.append(torch.from_numpy(pr.R).cuda())
-        Ts.append(torch.from_numpy(pr.T).cuda())
-        if i % 8 == 7:
-            print(f"[bench] {i + 1} pairs generated", file=sys.stderr, flush=True)
-    print(f"[bench] inputs generated in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr,
-          flush=True)
-    kw = dict(alpha=0.1, tau=10.0, rho=10.0, levels=3, ratio=2, max_iter=args.max_iter,
+
+    def gen(i):
+        return synth.ct_phantom_pair(shapes[i], seed_R=1000 + 2 * i, seed_u=1001 + 2 * i)
+
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        prs = list(ex.map(gen, range(npairs)))
+    Rs = [torch.from_numpy(p.R).cuda() for p in prs]
+    Ts = [torch.from_numpy(p.T).cuda() for p in prs]
+    del prs
+    print(f"[bench] {npairs} pairs generated in {time.perf_counter() - t_gen:.1f}s",
+          file=sys.stderr, flush=True)
+    return shapes, Rs, Ts
+
+
+def _batch_times(torch, ngf, Rs, Ts, max_iter, workers, steps, warmup):
+    """Seconds and evaluations of `steps` registrations of the whole batch:
+    the batched form in graph and in threads mode, and the pairs one after
+    another in one context (3 levels, the workload's parameters)."""
+    kw = dict(alpha=0.1, tau=10.0, rho=10.0, levels=3, ratio=2, max_iter=max_iter,
               lbfgs_mem=5, tol_J=1e-6, early_stop=True)
 
     def timed(run):
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             run()
         torch.cuda.synchronize()
         evals = 0
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             reps = run()
             evals += sum(r["evals"] for rep in reps for r in rep)
         torch.cuda.synchronize()
@@ -271,22 +282,33 @@ def bench_batch(args, torch, ngf, synth):
 
     res = {}
     for mode in ("graph", "threads"):
-        b = ngf.Batch(workers=args.workers, mode=mode, **kw)
+        b = ngf.Batch(workers=workers, mode=mode, **kw)
         if mode == "threads":
             b.set_kernel("by_size")
-        dt, ev = timed(lambda: b.register(Rs, Ts)[1])
+        res[mode] = timed(lambda: b.register(Rs, Ts)[1])
         b.close()
-        res[mode] = (dt, ev)
-        print(f"[bench] batch {mode}: {dt / args.steps:.3f} s per batch", file=sys.stderr,
+        print(f"[bench] batch {mode}: {res[mode][0] / steps:.3f} s per batch", file=sys.stderr,
               flush=True)
     ctx = ngf.Context(**kw)
-
-    def sequential():
-        return [ctx.register(R, T)[1] for R, T in zip(Rs, Ts)]
-
-    res["sequential"] = timed(sequential)
-    print(f"[bench] sequential: {res['sequential'][0] / args.steps:.3f} s per batch",
+    res["sequential"] = timed(lambda: [ctx.register(R, T)[1] for R, T in zip(Rs, Ts)])
+    ctx.close()
+    print(f"[bench] sequential: {res['sequential'][0] / steps:.3f} s per batch",
           file=sys.stderr, flush=True)
+    return res
+
+
+def _batch_summary(res, npairs, steps):
+    return {"batch_s": {k: v[0] / steps for k, v in res.items()},
+            "evals_per_s": {k: v[1] / v[0] for k, v in res.items()},
+            "pairs_per_s": {k: npairs * steps / v[0] for k, v in res.items()}}
+
+
+def bench_batch(args, torch, ngf, synth):
+    """Uneven batch of args.batch pairs, 3 levels.  Timed: the batched form in
+    graph mode (the reported value), in threads mode, and the same pairs
+    registered one after another by a single context."""
+    shapes, Rs, Ts = _batch_inputs(torch, synth, args.batch)
+    res = _batch_times(torch, ngf, Rs, Ts, args.max_iter, args.workers, args.steps, args.warmup)
     dt, evals = res["graph"]
     vox = sum(m[0] * m[1] * m[2] for m in shapes)
     out = {
@@ -307,12 +329,70 @@ def bench_batch(args, torch, ngf, synth):
                                f"alpha=0.1, eps=10, L-BFGS m=5, <= {args.max_iter} it/level, "
                                "early stop 1e-6; batched form in graph mode",
                    "global_batch": args.batch, "seq_len": None, "parallelism": "single GPU"},
-        "batch_s": {k: v[0] / args.steps for k, v in res.items()},
-        "evals_per_s": {k: v[1] / v[0] for k, v in res.items()},
-        "pairs_per_s": {k: args.batch * args.steps / v[0] for k, v in res.items()},
+        **_batch_summary(res, args.batch, args.steps),
         "threads_workers": args.workers,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_forms(args, torch, ngf, synth, reps=20):
+    """The differentiation and batched forms beside the plain one, on this
+    device.  Differentiation: one 128^3 CT pair (65^3 nodes, alpha 0.1,
+    eps 10) at a smooth deformation of up to 2 voxels; per call, the plain
+    J + grad J (gather), the level form J, grad_y and grad_T (scatter), and
+    the autograd function's forward and backward (J, then both gradients).
+    Batched: the uneven batch of args.forms_batch pairs (1 warm-up, 1 timed
+    registration of the whole batch per mode)."""
+    from paper_1812_06765_amd.autograd import ngf_objective
+    m = (128, 128, 128)
+    pr = synth.ct_phantom_pair(m, seed_R=3, seed_u=4)
+    R = torch.from_numpy(pr.R).cuda()
+    T = torch.from_numpy(pr.T).cuda()
+    ctx = ngf.Context(alpha=0.1, tau=10.0, rho=10.0, levels=1)
+    ctx.build_pyramid(R, T)
+    my = ctx.level_info(0).my
+    d = torch.from_numpy(synth.smooth_node_perturbation(my, 8.0, 2.0, 7).astype("float32"))
+    y = (ctx.identity(0) + d.cuda()).contiguous()
+    g = torch.empty_like(y)
+    yv = y.clone().requires_grad_(True)
+    Tv = T.clone().requires_grad_(True)
+
+    def autograd_call():
+        J = ngf_objective(yv, Tv, R, (1.0, 1.0, 1.0), ctx)
+        torch.autograd.grad(J, (yv, Tv))
+
+    calls = {"plain": lambda: ctx.eval_J_grad_async(0, y, g),
+             "level_form": lambda: ctx.eval_J_grad_T(0, y, sync=False),
+             "autograd": autograd_call}
+    us = {}
+    for name, call in calls.items():
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        us[name] = 1e6 * (time.perf_counter() - t0) / reps
+    ctx.close()
+    print(f"[bench] forms at 128^3: {us}", file=sys.stderr, flush=True)
+    out = {"differentiation": {
+        "workload": "128x128x128 CT pair, 65x65x65 nodes, alpha=0.1, eps=10, smooth y",
+        "us_per_call": us,
+        "vs_plain": {k: us[k] / us["plain"] for k in us}}}
+    if args.forms_batch > 0:
+        shapes, Rs, Ts = _batch_inputs(torch, synth, args.forms_batch)
+        res = _batch_times(torch, ngf, Rs, Ts, args.max_iter, args.workers, 1, 1)
+        vox = sum(s[0] * s[1] * s[2] for s in shapes)
+        out["batched"] = {
+            "workload": f"{args.forms_batch} pairs, axes drawn from 96..256, "
+                        f"{vox / 1e6:.1f} M voxels at the finest levels, 3 levels",
+            **_batch_summary(res, args.forms_batch, 1),
+            "speedup_vs_sequential": {k: res["sequential"][0] / res[k][0]
+                                      for k in ("graph", "threads")},
+            "threads_workers": args.workers}
+        del Rs, Ts
+    return out
 
 
 def main():
@@ -340,6 +420,11 @@ def main():
                     help="instead: the uneven batch of this many pairs (axes drawn from "
                          "96..256, 3 levels) through the batched form")
     ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--forms-batch", type=int, default=64,
+                    help="pairs of the batched form timed beside the plain one in the default "
+                         "line (0: none)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the differentiation and batched forms in the default line")
     ap.add_argument("--pt-ablation", action="store_true",
                     help="instead: time the three P^T schemes and P at the 256^3 grids")
     ap.add_argument("--kernel", default="auto",
@@ -514,6 +599,10 @@ def main():
         out["accuracy_voxels"] = accuracy(ctx, y, pr)
         out["image_mismatch_hu"] = image_mismatch(ctx, y, pr)
         print("[bench] accuracy sampled", file=sys.stderr, flush=True)
+    if not args.no_forms:
+        ctx.close()  # the 256^3 context's buffers are not needed any more
+        del R, T
+        out["forms"] = bench_forms(args, torch, ngf, synth)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, 256^3 eval)...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pr.R, pr.T)
