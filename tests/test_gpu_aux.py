@@ -144,3 +144,68 @@ def test_lbfgs_checkpoint_resume_bitwise(gpu_lib):
     assert e.value.status == ngf.E_SHAPE
     for c in (a, b, other_mem, other_shape):
         c.close()
+
+
+def test_iteration_log_when_a_level_ends_early(gpu_lib):
+    """Early stop: the log ends with the converged step.  Forced line-search
+    failure (every trial rejected): each level logs only its start point, and
+    the report counts the 11 rejected trials beyond it."""
+    ngf = gpu_lib
+    pr = _pair()
+    ctx = ngf.Context(alpha=0.1, tau=0.1, rho=0.1, levels=1, max_iter=40, lbfgs_mem=5,
+                      tol_J=0.009, early_stop=True)
+    ctx.set_iteration_log(True)
+    _, rep = ctx.register(_t(pr.R), _t(pr.T))
+    recs = ctx.iteration_log()
+    assert rep[0]["info"] == ngf.INFO_CONVERGED
+    assert [x["iter"] for x in recs] == list(range(rep[0]["iters"] + 1))
+    assert recs[-1]["J"] == rep[0]["J"] and recs[-1]["evals"] == rep[0]["evals"]
+    last = recs[-1]
+    assert recs[-2]["J"] - last["J"] <= 0.009 * (1.0 + abs(recs[-2]["J"]))
+    ctx.close()
+    for drv in ("device", "host"):
+        ctx = ngf.Context(alpha=0.1, tau=0.1, rho=0.1, levels=2, max_iter=5, lbfgs_mem=5)
+        ctx.set_driver(drv)
+        ctx.set_faults(ngf.Context.FAULT_REJECT_STEPS)
+        ctx.set_iteration_log(True)
+        _, rep = ctx.register(_t(pr.R), _t(pr.T))
+        recs = ctx.iteration_log()
+        _say(f"[log] forced line-search failure ({drv}): {rep}")
+        assert [(x["level"], x["iter"]) for x in recs] == [(1, 0), (0, 0)]
+        for r in rep:
+            assert r["info"] == ngf.INFO_LINESEARCH_FAIL and r["iters"] == 0
+            assert r["evals"] == 1 + 11
+        ctx.close()
+
+
+def test_lbfgs_checkpoint_on_a_coarse_level(gpu_lib):
+    """A state saved at level 1 of a 2-level pyramid resumes in another
+    context with the same pyramid; a context whose pyramid has one level
+    refuses it."""
+    ngf = gpu_lib
+    pr = _pair()
+    kw = dict(alpha=0.1, tau=0.1, rho=0.1, levels=2, max_iter=50, lbfgs_mem=5)
+    a = ngf.Context(**kw)
+    a.set_kernel("by_size")
+    a.build_pyramid(_t(pr.R), _t(pr.T))
+    a.lbfgs_reset(1, a.identity(1))
+    for _ in range(3):
+        a.lbfgs_step()
+    state = a.lbfgs_save()
+    Ja = [a.lbfgs_step()[0] for _ in range(4)]
+    b = ngf.Context(**kw)
+    b.set_kernel("by_size")
+    b.build_pyramid(_t(pr.R), _t(pr.T))
+    b.lbfgs_load(state)
+    Jb = [b.lbfgs_step()[0] for _ in range(4)]
+    assert Jb == Ja
+    ya = a.lbfgs_get(1)[0]
+    yb = b.lbfgs_get(1)[0]
+    assert bool((ya == yb).all())
+    one = ngf.Context(**{**kw, "levels": 1})
+    one.build_pyramid(_t(pr.R), _t(pr.T))
+    with pytest.raises(ngf.NgfError) as e:
+        one.lbfgs_load(state)
+    assert e.value.status == ngf.E_LEVEL
+    for c in (a, b, one):
+        c.close()
