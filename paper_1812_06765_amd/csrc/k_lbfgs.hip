@@ -212,8 +212,12 @@ void launch_ctl_gather(const LbVecArgs* args, LbCtl* out, int npairs, hipStream_
     hipLaunchKernelGGL(k_ctl_gather, dim3((npairs + 63) / 64), dim3(64), 0, s, args, out, npairs);
 }
 
+// Workgroups of the L-BFGS vector passes over n floats: a thread takes four
+// consecutive floats per step, so one workgroup per kThreads such groups, at
+// most kLbBlocks (then the passes stride over the vector).  The last n mod 4
+// floats go to the first threads of workgroup 0.
 int lb_dot_blocks(int64_t n) {
-    int64_t b = (n + kThreads - 1) / kThreads;
+    int64_t b = ((n >> 2) + kThreads - 1) / kThreads;
     if (b > kLbBlocks) b = kLbBlocks;
     if (b < 1) b = 1;
     return static_cast<int>(b);
