@@ -505,7 +505,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # the finest level's launches of the image pass, the dominant kernel
-    launches, kms, vox, nodes = ctx.kernel_time(level=0)
+    launches, kms, vox, _ = ctx.kernel_time(level=0)
     ctx.set_profiling(False)
     print(f"[bench] timed {args.steps} registrations in {dt:.3f}s", file=sys.stderr, flush=True)
 
