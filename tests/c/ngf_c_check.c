@@ -184,6 +184,56 @@ static int device_forms(ngf_ctx* c, const ngf_params* p, const float* R, const f
     return 0;
 }
 
+/* The iteration log of a registration and an L-BFGS checkpoint, from C:
+ * one record per accepted step plus one per level start, in level order; a
+ * saved state replays the same steps after further ones. */
+static int aux_forms(ngf_ctx* c, const float* R, const float* T, const ngf_grid* g) {
+    enum { MY = 17 };
+    const size_t ny = (size_t)3 * MY * MY * MY;
+    ngf_report rep;
+    ngf_iter_record* recs = NULL;
+    int32_t count = 0, expect = 0, info = 0, l;
+    size_t bytes = 0;
+    void* state = NULL;
+    float* dy = NULL;
+    double Ja[3], Jb[3];
+    int k;
+    CHECK(ngf_set_iteration_log(c, 1) == NGF_OK, "iteration log on");
+    CHECK(ngf_register(c, R, T, g, NULL, 1, &rep) == NGF_OK, "register: %s", ngf_last_error(c));
+    CHECK(ngf_iteration_log(c, NULL, 0, &count) == NGF_OK, "log count");
+    for (l = 0; l < rep.levels; ++l) expect += rep.iters[l] + 1;
+    CHECK(count == expect, "%d records, expected %d", (int)count, (int)expect);
+    recs = malloc((size_t)count * sizeof(ngf_iter_record));
+    CHECK(recs != NULL, "host allocation");
+    CHECK(ngf_iteration_log(c, recs, count, &count) == NGF_OK, "log copy");
+    CHECK(recs[0].level == rep.levels - 1 && recs[0].iter == 0 && recs[0].evals == 1,
+          "first record");
+    CHECK(recs[count - 1].level == 0 && recs[count - 1].iter == rep.iters[0] &&
+              recs[count - 1].J == rep.J[0],
+          "last record");
+    free(recs);
+    CHECK(ngf_set_iteration_log(c, 0) == NGF_OK, "iteration log off");
+
+    CHECK(hipMalloc((void**)&dy, ny * sizeof(float)) == 0, "hipMalloc");
+    CHECK(ngf_identity(c, 0, dy) == NGF_OK, "identity");
+    CHECK(ngf_lbfgs_reset(c, 0, dy) == NGF_OK, "reset: %s", ngf_last_error(c));
+    for (k = 0; k < 2; ++k) CHECK(ngf_lbfgs_step(c, Ja, &info) == NGF_OK, "step");
+    CHECK(ngf_lbfgs_state_size(c, &bytes) == NGF_OK && bytes > 2 * ny * sizeof(float),
+          "state size %lu", (unsigned long)bytes);
+    state = malloc(bytes);
+    CHECK(state != NULL, "host allocation");
+    CHECK(ngf_lbfgs_save(c, state, bytes) == NGF_OK, "save: %s", ngf_last_error(c));
+    CHECK(ngf_lbfgs_save(c, state, bytes - 1) == NGF_E_ARG, "short buffer accepted");
+    for (k = 0; k < 3; ++k) CHECK(ngf_lbfgs_step(c, &Ja[k], &info) == NGF_OK, "step");
+    CHECK(ngf_lbfgs_load(c, state, bytes) == NGF_OK, "load: %s", ngf_last_error(c));
+    for (k = 0; k < 3; ++k) CHECK(ngf_lbfgs_step(c, &Jb[k], &info) == NGF_OK, "step");
+    for (k = 0; k < 3; ++k) CHECK(Ja[k] == Jb[k], "resumed step %d: %.17g vs %.17g", k, Jb[k], Ja[k]);
+    free(state);
+    hipFree(dy);
+    printf("c abi gpu iteration log and checkpoint ok (%d records)\n", (int)count);
+    return 0;
+}
+
 static int gpu_registration(void) {
     enum { M = 32, MY = M / 2 + 1 };
     const size_t n = (size_t)M * M * M, ny = (size_t)3 * MY * MY * MY;
@@ -247,6 +297,7 @@ static int gpu_registration(void) {
     CHECK(umax < 4.0, "displacement too large");
     printf("c abi gpu registration ok\n");
     if (device_forms(c, &p, R, T, y) != 0) return 1;
+    if (aux_forms(c, R, T, &g) != 0) return 1;
     ngf_destroy(c);
     free(R);
     free(T);
