@@ -690,17 +690,27 @@ void launch_image_tile(const ImagePassArgs& a, hipStream_t s) {
     }
 }
 
-template <int RATIO>
-void launch_image_ratio_atomic(const ImagePassArgs& a, hipStream_t s) {
-    using L = ImageTile<kTX, kTY, kTZ, RATIO>;
+template <int TX, int TY, int TZ, int RATIO>
+void launch_image_tile_atomic(const ImagePassArgs& a, hipStream_t s) {
+    using L = ImageTile<TX, TY, TZ, RATIO>;
     const int blocks = a.ntx * a.nty * a.ntz;
     const size_t lds = sizeof(float) * L::LDS_FLOATS;
     if (a.pow2h)
-        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, true, true, true>), dim3(blocks),
+        hipLaunchKernelGGL((k_image_pass<TX, TY, TZ, RATIO, true, true, true>), dim3(blocks),
                            dim3(kThreads), lds, s, a);
     else
-        hipLaunchKernelGGL((k_image_pass<kTX, kTY, kTZ, RATIO, true, true, false>),
-                           dim3(blocks), dim3(kThreads), lds, s, a);
+        hipLaunchKernelGGL((k_image_pass<TX, TY, TZ, RATIO, true, true, false>), dim3(blocks),
+                           dim3(kThreads), lds, s, a);
+}
+
+template <int RATIO>
+void launch_image_ratio_atomic(const ImagePassArgs& a, int variant, hipStream_t s) {
+    if (variant == kTile3DTiny)
+        launch_image_tile_atomic<4, 4, 16, RATIO>(a, s);
+    else if (variant == kTile3DSmall)
+        launch_image_tile_atomic<4, 8, 32, RATIO>(a, s);
+    else
+        launch_image_tile_atomic<kTX, kTY, kTZ, RATIO>(a, s);
 }
 
 template <int TX, int TY, int TZ, int RATIO>
@@ -763,11 +773,11 @@ void launch_node_pass_batch(const NodePassArgs* args, const BlockRef* blk, int n
     hipLaunchKernelGGL(k_node_pass_batch, dim3(nblk), dim3(kThreads), 0, s, args, blk);
 }
 
-void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s) {
+void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, int variant, hipStream_t s) {
     if (ratio == 2)
-        launch_image_ratio_atomic<2>(a, s);
+        launch_image_ratio_atomic<2>(a, variant, s);
     else if (ratio == 4)
-        launch_image_ratio_atomic<4>(a, s);
+        launch_image_ratio_atomic<4>(a, variant, s);
 }
 
 int node_march_slots() {

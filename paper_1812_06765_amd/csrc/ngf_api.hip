@@ -682,9 +682,9 @@ ngf_status eval_scatter(ngf_ctx* c, const Level& P, const float* R, const float*
     a.dpart = dpart;
     a.part = nullptr;
     if (want)
-        launch_image_pass_atomic(a, r, c->stream);
+        launch_image_pass_atomic(a, r, P.variant, c->stream);
     else
-        launch_image_pass(a, r, kTile3D, c->stream);
+        launch_image_pass(a, r, P.variant, c->stream);
     HIPCHK(c, hipGetLastError());
     NodePassArgs b{};
     b.y = y;
@@ -717,7 +717,7 @@ ngf_status eval_scatter(ngf_ctx* c, const Level& P, const float* R, const float*
     HIPCHK(c, hipGetLastError());
     ReduceArgs rd{};
     rd.dpart = dpart;
-    rd.nd = static_cast<int>(geometry(P, kTile3D).ntiles());
+    rd.nd = static_cast<int>(geometry(P, P.variant).ntiles());
     rd.spart = spart;
     rd.ns = static_cast<int>(node_blocks(P));
     rd.gpart = gpart;
@@ -1363,7 +1363,7 @@ ngf_status ngf_eval_pair(ngf_ctx* c, const ngf_grid* g, const int32_t my[3], con
         }
         HIPCHK(c, hipGetLastError());
     }
-    P.variant = kTile3D;  // the scatter form lives in the 3D-tile kernel
+    P.variant = kScatterVariant;  // the scatter form lives in a 3D-tile kernel
     P.dyadic = r;
     if (const ngf_status st = ensure_scratch(c, P); st != NGF_OK) return st;
     return eval_scatter(c, P, R, T, y, gscale, J, J_dev, grad_y, grad_T, nullptr);
@@ -1379,8 +1379,8 @@ ngf_status ngf_eval_J_grad_T(ngf_ctx* c, int32_t level, const float* y, const do
     if (!L.dyadic)
         return fail(c, NGF_E_SHAPE,
                     "the scatter form needs a deformation grid of m/2 + 1 or m/4 + 1 nodes");
-    Level P = L;  // same grids and buffers; the scatter lives in the 3D-tile kernel
-    P.variant = kTile3D;
+    Level P = L;  // same grids and buffers; the scatter lives in a 3D-tile kernel
+    P.variant = kScatterVariant;
     return eval_scatter(c, P, L.R, L.T, y, gscale, J, J_dev, grad_y, grad_T, nullptr);
 }
 

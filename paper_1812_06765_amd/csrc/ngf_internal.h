@@ -52,6 +52,10 @@ inline int tile3d_x(int v) { return v == kTile3D ? 8 : 4; }
 inline int tile3d_y(int v) { return v == kTile3DTiny ? 4 : 8; }
 inline int tile3d_z(int v) { return v == kTile3DTiny ? 16 : 32; }
 inline bool is_tile3d(int v) { return v == kTile3D || v == kTile3DSmall || v == kTile3DTiny; }
+// 3D tile of the differentiation form (float atomics into grad_y and grad_T):
+// four voxels per thread keep the warp cells they scatter from in fewer
+// registers than the 8 x 8 x 32 tile's eight
+constexpr int kScatterVariant = kTile3DSmall;
 // fixed x chunk of a marching variant; 0 for the fit variants
 inline int march_cx(int v) {
     if (v >= kMarch32Fit) return 0;
@@ -344,7 +348,7 @@ void launch_node_pass(const NodePassArgs& a, hipStream_t s);
 void launch_reduce(const ReduceArgs& a, hipStream_t s);
 void launch_check_finite(const float* v, int64_t n, int* flag, hipStream_t s);
 void launch_fill(float* p, int64_t n, float v, hipStream_t s);
-void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, hipStream_t s);
+void launch_image_pass_atomic(const ImagePassArgs& a, int ratio, int variant, hipStream_t s);
 
 // standalone grid conversion (P, and P^T by gather / atomic scatter / red-black)
 void launch_apply_P(const int32_t* const j0[3], const float* const w0[3],

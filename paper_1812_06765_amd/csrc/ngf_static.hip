@@ -85,12 +85,12 @@ extern "C" ngf_status ngf_eval_pair_static(ngf_ctx* c, const ngf_grid* g, const 
         P.my[d] = my[d];
         P.hy[d] = P.m[d] * P.h[d] / (P.my[d] - 1);
     }
-    P.variant = kTile3D;  // the scatter form lives in the 3D-tile kernel
+    P.variant = kScatterVariant;  // the scatter form lives in a 3D-tile kernel
     P.dyadic = r;
     // layout of the scratch: D partials per image tile, S partials and
     // (max, sum of squares) of the gradient per node block, then the index
     // maps (j0, w0, w1 per axis)
-    const size_t nt = static_cast<size_t>(geometry(P, kTile3D).ntiles());
+    const size_t nt = static_cast<size_t>(geometry(P, kScatterVariant).ntiles());
     const size_t nb = static_cast<size_t>(node_blocks(P));
     size_t off = 0;
     const size_t o_d = off;
