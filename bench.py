@@ -340,7 +340,8 @@ def bench_forms(args, torch, ngf, synth, reps=20):
     device.  Differentiation: one 128^3 CT pair (65^3 nodes, alpha 0.1,
     eps 10) at a smooth deformation of up to 2 voxels; per call, the plain
     J + grad J (gather), the level form J, grad_y and grad_T (scatter), and
-    the autograd function's forward and backward (J, then both gradients).
+    the autograd function's forward and backward (J, then both gradients);
+    each the median of 5 runs of `reps` calls.
     Batched: the uneven batch of args.forms_batch pairs (1 warm-up, 1 timed
     registration of the whole batch per mode)."""
     from paper_1812_06765_amd.autograd import ngf_objective
@@ -369,11 +370,14 @@ def bench_forms(args, torch, ngf, synth, reps=20):
         for _ in range(3):
             call()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            call()
-        torch.cuda.synchronize()
-        us[name] = 1e6 * (time.perf_counter() - t0) / reps
+        runs = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                call()
+            torch.cuda.synchronize()
+            runs.append(1e6 * (time.perf_counter() - t0) / reps)
+        us[name] = sorted(runs)[2]  # median of 5 runs
     ctx.close()
     print(f"[bench] forms at 128^3: {us}", file=sys.stderr, flush=True)
     out = {"differentiation": {
