@@ -662,6 +662,20 @@ ngf_status check_level(const ngf_ctx* c, int level) {
 }
 
 
+// J of the evaluation just queued: copied to J_dev (device) and read back to
+// J (host, synchronises) when given.
+ngf_status finish_J(ngf_ctx* c, double* J, double* J_dev) {
+    if (J_dev)
+        HIPCHK(c, hipMemcpyAsync(J_dev, c->jds, sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream));
+    if (J) {
+        if (read_jds(c) != NGF_OK) return NGF_E_HIP;
+        *J = c->host_jds[0];
+        if (!std::isfinite(*J)) return fail(c, NGF_E_NONFINITE, "J is not finite");
+    }
+    return NGF_OK;
+}
+
 // Differentiation form on level L (its grids and index maps) with images R, T:
 // J, and grad_y / grad_T by atomic scatter (3D-tile kernel), alpha grad S
 // added by the node pass.  Uses only buffers sized beforehand.
@@ -673,6 +687,17 @@ ngf_status eval_scatter(ngf_ctx* c, const Level& P, const float* R, const float*
     double* spart = sb ? sb->spart : c->spart;
     double* gpart = sb ? sb->gpart : c->gpart;
     const bool want = grad_y != nullptr || grad_T != nullptr;
+    if (!want && !sb) {
+        // J alone (the autograd function's forward): the plain evaluation with
+        // the image-pass kernel of the size rule (the context's scratch holds
+        // every variant's partial sums for this grid)
+        Level V = P;
+        const int v = variant_by_size(V);
+        V.variant = variant_ok(V, v) ? v : P.variant;
+        const ngf_status e = enqueue_eval(c, V, R, T, y, nullptr);
+        if (e != NGF_OK) return e;
+        return finish_J(c, J, J_dev);
+    }
     if (grad_y) launch_fill(grad_y, 3 * P.Ny(), 0.0f, c->stream);
     if (grad_T) launch_fill(grad_T, P.N(), 0.0f, c->stream);
     ImagePassArgs a = image_args(c, P, R, T, y, want);
@@ -728,15 +753,7 @@ ngf_status eval_scatter(ngf_ctx* c, const Level& P, const float* R, const float*
     rd.out = c->jds;
     launch_reduce(rd, c->stream);
     HIPCHK(c, hipGetLastError());
-    if (J_dev)
-        HIPCHK(c, hipMemcpyAsync(J_dev, c->jds, sizeof(double), hipMemcpyDeviceToDevice,
-                                 c->stream));
-    if (J) {
-        if (read_jds(c) != NGF_OK) return NGF_E_HIP;
-        *J = c->host_jds[0];
-        if (!std::isfinite(*J)) return fail(c, NGF_E_NONFINITE, "J is not finite");
-    }
-    return NGF_OK;
+    return finish_J(c, J, J_dev);
 }
 
 }  // namespace ngf_host
