@@ -345,7 +345,8 @@ ngf_status ngf_register_levels(ngf_ctx* ctx, float* y_out, ngf_report* rep);
  *   J          host double (the call then synchronises) or NULL
  *   J_dev      device double receiving J without synchronising, or NULL
  *   grad_y     device float32 like y, or NULL; grad_T device float32 like T,
- *              or NULL; both NULL: only J is computed
+ *              or NULL; both NULL: only J is computed, with the plain
+ *              evaluation's kernels (no scatter)
  * Allocates index maps and scratch on the first call for a new grid. */
 ngf_status ngf_eval_pair(ngf_ctx* ctx, const ngf_grid* g, const int32_t my[3],
                          const float* R, const float* T, const float* y,
