@@ -540,17 +540,20 @@ __global__ __launch_bounds__((march_threads<TY, TZ>()), TZ == 32 ? 4 : 2) void k
     march_body<TY, TZ, R, GRAD, POW2>(a, CX, blockIdx.x);
 }
 
-// each pair's chunk length is its own (a.cx)
-// The batched form indexes its arguments per block and needs a few more
-// registers: at four waves per SIMD a few of them spill to scratch.
+// each pair's chunk length is its own (a.cx).  The pair and block indices
+// are uniform over the workgroup: taken as such, the pair's arguments load
+// into scalar registers and the kernel needs no more vector registers than
+// the single-pair one (no spills).
 template <int TY, int TZ, int R, bool POW2>
 __global__ __launch_bounds__((march_threads<TY, TZ>()), TZ == 32 ? 4 : 2) void k_image_march_batch(
     const ImagePassArgs* args, const BlockRef* blk) {
     const BlockRef e = blk[blockIdx.x];
-    if (e.pair < 0) return;
-    const ImagePassArgs& a = args[e.pair];
+    const int pair = __builtin_amdgcn_readfirstlane(e.pair);
+    if (pair < 0) return;
+    const ImagePassArgs a = args[pair];
     if (a.gate && *a.gate == kOpNone) return;
-    march_body<TY, TZ, R, true, POW2>(a, a.cx, e.block);
+    march_body<TY, TZ, R, true, POW2>(a, __builtin_amdgcn_readfirstlane(a.cx),
+                                      __builtin_amdgcn_readfirstlane(e.block));
 }
 
 template <int TY, int TZ, int R>

@@ -583,10 +583,12 @@ template <int KP, bool POW2>
 __global__ __launch_bounds__(GNI / KP, 4) void k_image_gen_batch(const ImagePassArgs* args,
                                                                 const BlockRef* blk) {
     const BlockRef e = blk[blockIdx.x];
-    if (e.pair < 0) return;
-    const ImagePassArgs& a = args[e.pair];
+    const int pair = __builtin_amdgcn_readfirstlane(e.pair);  // uniform: scalar loads
+    if (pair < 0) return;
+    const ImagePassArgs a = args[pair];
     if (a.gate && *a.gate == kOpNone) return;
-    gen_body<KP, true, POW2>(a, a.cx, e.block);
+    gen_body<KP, true, POW2>(a, __builtin_amdgcn_readfirstlane(a.cx),
+                             __builtin_amdgcn_readfirstlane(e.block));
 }
 
 // Reference side of the NGF term per voxel: (grad R, |grad R|^2 + rho^2)
