@@ -410,6 +410,10 @@ def main():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--max-iter", type=int, default=50)
     ap.add_argument("--alpha", type=float, default=0.1, help="curvature weight")
+    ap.add_argument("--ratio", type=int, default=2,
+                    help="image cells per deformation-grid cell between levels (2 or 4)")
+    ap.add_argument("--node-grid", type=int, nargs=3, default=None,
+                    help="finest-level deformation-grid nodes per axis (default m/ratio + 1)")
     ap.add_argument("--eps", type=float, default=10.0,
                     help="NGF edge parameter of R and T (HU per unit length)")
     ap.add_argument("--noise", type=float, default=20.0,
@@ -481,12 +485,15 @@ def main():
     print(f"[bench] inputs {sname} generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
     R = torch.from_numpy(pr.R).cuda()
     T = torch.from_numpy(pr.T).cuda()
-    ctx = ngf.Context(alpha=args.alpha, tau=args.eps, rho=args.eps, levels=args.levels, ratio=2,
+    ctx = ngf.Context(alpha=args.alpha, tau=args.eps, rho=args.eps, levels=args.levels,
+                      ratio=args.ratio,
                       max_iter=args.max_iter, lbfgs_mem=5, tol_J=1e-6, early_stop=True)
     # image-pass variants: the timed selection times its candidates for every
     # level shape when the pyramid is first built, here, before the warm-up
     # and the timed region (later pyramids of the same shapes reuse them)
     ctx.set_kernel(args.kernel)
+    if args.node_grid:
+        ctx.set_node_grid(args.node_grid)
     ctx.build_pyramid(R, T)
     vname = {v: k for k, v in ngf.Context.VARIANTS.items()}
     variants = [vname[ctx.get_kernel(lev)] for lev in range(args.levels)]
